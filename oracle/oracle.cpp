@@ -1,0 +1,383 @@
+// CPU oracle for one coarsening level of an SNN hypergraph and for the
+// (lambda - 1) connectivity objective.
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+// GPU library is checked against.  Only the test-suite, the smoke check and
+// the CPU-baseline leg of the benchmark may load it; the product path never
+// does.  It shares no code with the GPU library.
+//
+// Everything is integer arithmetic.  Each function follows one passage of
+// Ronzani & Silvano, "GPU-Accelerated Hypergraph Partitioning and Placement to
+// Map SNNs on Neuromorphic Hardware":
+//
+//   * level-0 model ............ Section 2, "SNN and Hardware Models"
+//   * constraints .............. Section 3, "Partitioning Definition"
+//                                (|p| <= Omega, |U in(n)| <= Delta,
+//                                 sum |in(n)| <= Phi)
+//   * score / candidate ........ Section 4.1, "Coarsening", Eq. (12)
+//   * matching ................. Section 4.1, "Coarsening", Eq. (13)
+//   * coarse hypergraph ........ Section 3, "Partitioning Definition" (G_P),
+//                                and Section 4.1 (state propagated per level)
+//   * connectivity ............. Section 3, Eq. (1)
+//
+// Readings of passages the paper leaves open (also listed in the design notes):
+//   R1 ties in every argmax go to the lowest vertex id;
+//   R2 a super-node's inbound set is the set of ORIGINAL axons with at least
+//      one destination inside it; it is propagated as an explicit set, the
+//      way the paper propagates "size, inbound hyperedges set, and pin count";
+//   R3 pins of a coarse hyperedge carry a destination flag (set iff the
+//      super-node holds a destination of one of its axons); coarse hyperedges
+//      are merged only when their (vertex, flag) lists are identical, and the
+//      number of merged original axons is carried as `mult`;
+//   R4 coarse hyperedges with fewer than two distinct pins are dropped;
+//   R5 coarse vertices are numbered by their smallest member, coarse
+//      hyperedges by their smallest fine hyperedge, pins ascending;
+//   R6 Eq. (13)'s first case takes precedence over its second;
+//   R7 the level loop stops when no vertex proposes a candidate.
+//
+// Plainness is the point: per-vertex dense score arrays, std::map for
+// grouping, explicit sets for inbound axons.  The only parallelism is an
+// OpenMP loop over vertices in the candidate step.
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+const uint32_t DST = 0x80000000u;
+const uint32_t IDMASK = 0x7FFFFFFFu;
+
+// Incidence lists I(n) = in(n) U out(n) (Section 2): for every vertex the
+// hyperedges that contain it, as (edge, is_destination) pairs.
+struct Incidence {
+  std::vector<int64_t> off;
+  std::vector<int32_t> edge;
+  std::vector<uint8_t> is_dst;
+};
+
+Incidence build_incidence(int32_t V, int32_t E, const int64_t* eoff,
+                          const uint32_t* pins) {
+  Incidence inc;
+  inc.off.assign((size_t)V + 1, 0);
+  for (int32_t e = 0; e < E; ++e)
+    for (int64_t k = eoff[e]; k < eoff[e + 1]; ++k) inc.off[(pins[k] & IDMASK) + 1]++;
+  for (int32_t v = 0; v < V; ++v) inc.off[v + 1] += inc.off[v];
+  inc.edge.resize(inc.off[V]);
+  inc.is_dst.resize(inc.off[V]);
+  std::vector<int64_t> pos(inc.off.begin(), inc.off.end() - 1);
+  for (int32_t e = 0; e < E; ++e)
+    for (int64_t k = eoff[e]; k < eoff[e + 1]; ++k) {
+      uint32_t v = pins[k] & IDMASK;
+      inc.edge[pos[v]] = e;
+      inc.is_dst[pos[v]] = (pins[k] & DST) ? 1 : 0;
+      pos[v]++;
+    }
+  return inc;
+}
+
+// |A n B| for two ascending id lists.
+int64_t intersect_count(const int32_t* a, int64_t na, const int32_t* b, int64_t nb) {
+  int64_t i = 0, j = 0, c = 0;
+  while (i < na && j < nb) {
+    if (a[i] < b[j]) ++i;
+    else if (b[j] < a[i]) ++j;
+    else { ++c; ++i; ++j; }
+  }
+  return c;
+}
+
+struct Limits {
+  int32_t omega, phi, delta;
+};
+
+struct Level {
+  int32_t V, E;
+  const int64_t* eoff;
+  const uint32_t* pins;
+  const int32_t* w;
+  const int32_t* size;
+  const int32_t* syn;
+  const int64_t* soff;   // inbound-axon sets, CSR over vertices
+  const int32_t* sids;
+};
+
+// Merge constraint check between super-nodes n and m (Section 3 constraints
+// applied to the union n U m; R2 for the inbound set).
+bool merge_valid(const Level& L, const Limits& lim, int32_t n, int32_t m) {
+  if ((int64_t)L.size[n] + L.size[m] > lim.omega) return false;
+  if ((int64_t)L.syn[n] + L.syn[m] > lim.phi) return false;
+  int64_t an = L.soff[n + 1] - L.soff[n];
+  int64_t am = L.soff[m + 1] - L.soff[m];
+  if (an + am <= lim.delta) return true;  // |A U B| <= |A| + |B|
+  int64_t ov = intersect_count(L.sids + L.soff[n], an, L.sids + L.soff[m], am);
+  return an + am - ov <= lim.delta;
+}
+
+}  // namespace
+
+extern "C" {
+
+// ---------------------------------------------------------------------------
+// Level-0 state (Section 2 model; Section 3 constraint quantities).
+// size = 1 neuron; syn = |in(n)| inbound pins; inbound set = in(n), the axons
+// that have n as a destination; every hyperedge stands for one axon (mult 1).
+// soff must hold V+1 entries; sids as many entries as there are destination
+// pins.  Returns 0.
+int oracle_level0_state(int32_t V, int32_t E, const int64_t* eoff, const uint32_t* pins,
+                        int32_t* size, int32_t* syn, int32_t* mult, int64_t* soff,
+                        int32_t* sids) {
+  std::vector<std::vector<int32_t>> in(V);
+  for (int32_t e = 0; e < E; ++e) {
+    mult[e] = 1;
+    for (int64_t k = eoff[e]; k < eoff[e + 1]; ++k)
+      if (pins[k] & DST) in[pins[k] & IDMASK].push_back(e);
+  }
+  soff[0] = 0;
+  for (int32_t v = 0; v < V; ++v) {
+    size[v] = 1;
+    syn[v] = (int32_t)in[v].size();
+    std::sort(in[v].begin(), in[v].end());
+    soff[v + 1] = soff[v] + (int64_t)in[v].size();
+    std::copy(in[v].begin(), in[v].end(), sids + soff[v]);
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Score and candidate, Section 4.1 Eq. (12).
+//   score(n, m) = sum of w(e) over hyperedges e incident to n that contain m;
+//   cand(n)     = the valid neighbour with the largest score, lowest id on a
+//                 tie (R1); -1 when no neighbour is valid.
+// Computes cand/cscore for the `nq` vertices listed in `query` (all vertices
+// when query is null; then nq must equal V).  cscore is score(n, cand(n)), or
+// 0 when there is no candidate.
+int oracle_candidates(int32_t V, int32_t E, const int64_t* eoff, const uint32_t* pins,
+                      const int32_t* w, const int32_t* size, const int32_t* syn,
+                      const int64_t* soff, const int32_t* sids, int32_t omega,
+                      int32_t phi, int32_t delta, int32_t nq, const int32_t* query,
+                      int32_t* cand, int32_t* cscore, int32_t nthreads) {
+  Level L{V, E, eoff, pins, w, size, syn, soff, sids};
+  Limits lim{omega, phi, delta};
+  Incidence inc = build_incidence(V, E, eoff, pins);
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+  {
+    // Sparse accumulator: a dense score array over all vertices plus the
+    // list of touched entries, reset after every vertex.
+    std::vector<int64_t> score((size_t)V, 0);
+    std::vector<int32_t> touched;
+#pragma omp for schedule(dynamic, 64)
+    for (int32_t qi = 0; qi < nq; ++qi) {
+      int32_t n = query ? query[qi] : qi;
+      touched.clear();
+      for (int64_t j = inc.off[n]; j < inc.off[n + 1]; ++j) {
+        int32_t e = inc.edge[j];
+        for (int64_t k = eoff[e]; k < eoff[e + 1]; ++k) {
+          int32_t m = (int32_t)(pins[k] & IDMASK);
+          if (m == n) continue;
+          if (score[m] == 0) touched.push_back(m);
+          score[m] += w[e];
+        }
+      }
+      int32_t best = -1;
+      int64_t best_s = 0;
+      for (int32_t m : touched) {
+        int64_t s = score[m];
+        bool better = s > best_s || (s == best_s && m < best);
+        if (better && merge_valid(L, lim, n, m)) {
+          best = m;
+          best_s = s;
+        }
+      }
+      for (int32_t m : touched) score[m] = 0;
+      cand[qi] = best;
+      cscore[qi] = best < 0 ? 0 : (int32_t)best_s;
+    }
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Matching, Section 4.1 Eq. (13), evaluated as written:
+//   match(n) = cand(n)           if cand(cand(n)) = n or match(cand(n)) = n,
+//            = argmax_{m : cand(m) = n} score(n, m)   otherwise, if such m,
+//            = -1                otherwise.
+// score(n, m) for a child m is cscore[m] because scores are symmetric.  The
+// recursion "match(cand(n)) = n" climbs the candidate arcs; it is evaluated
+// with an explicit stack and memoised.  Returns 0, or -1 if a candidate cycle
+// longer than two is found (impossible per Section 4.1).
+int oracle_match(int32_t V, const int32_t* cand, const int32_t* cscore, int32_t* match) {
+  // best child by (score desc, id asc), R1
+  std::vector<int32_t> bc(V, -1);
+  for (int32_t m = 0; m < V; ++m) {
+    int32_t p = cand[m];
+    if (p < 0) continue;
+    int32_t cur = bc[p];
+    if (cur < 0 || cscore[m] > cscore[cur] || (cscore[m] == cscore[cur] && m < cur))
+      bc[p] = m;
+  }
+  // state: 0 unknown, 1 in progress, 2 known
+  std::vector<uint8_t> state(V, 0);
+  std::vector<int32_t> memo(V, -1);
+  std::vector<int32_t> stack;
+  for (int32_t s = 0; s < V; ++s) {
+    if (state[s] == 2) continue;
+    stack.clear();
+    stack.push_back(s);
+    while (!stack.empty()) {
+      int32_t n = stack.back();
+      int32_t c = cand[n];
+      bool ready = true;
+      bool taken = false;
+      if (c >= 0) {
+        if (cand[c] == n) {
+          taken = true;  // two-cycle
+        } else if (state[c] == 2) {
+          taken = (memo[c] == n);
+        } else {
+          if (state[c] == 1) return -1;  // longer cycle
+          state[n] = 1;
+          stack.push_back(c);
+          ready = false;
+        }
+      }
+      if (!ready) continue;
+      memo[n] = taken ? c : bc[n];
+      state[n] = 2;
+      stack.pop_back();
+    }
+  }
+  for (int32_t n = 0; n < V; ++n) match[n] = memo[n];
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Coarse vertex map from a matching (R5): a vertex is a representative when it
+// is unmatched or smaller than its partner; coarse ids rank representatives in
+// ascending order and a matched pair shares its representative's id.
+// Returns the number of coarse vertices.
+int32_t oracle_vmap_from_match(int32_t V, const int32_t* match, int32_t* vmap) {
+  std::vector<int32_t> rank(V, -1);
+  int32_t r = 0;
+  for (int32_t n = 0; n < V; ++n)
+    if (match[n] < 0 || n < match[n]) rank[n] = r++;
+  for (int32_t n = 0; n < V; ++n) {
+    int32_t rep = (match[n] < 0 || n < match[n]) ? n : match[n];
+    vmap[n] = rank[rep];
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Coarse hypergraph G_P for an arbitrary vertex map rho = vmap with values in
+// [0, n_coarse) (Section 3, "Partitioning Definition", and Section 4.1 state
+// propagation):
+//   * each fine hyperedge becomes its set of distinct coarse vertices, a
+//     vertex's destination flag being the OR over its members (R3);
+//     hyperedges left with fewer than two vertices are dropped (R4);
+//   * hyperedges with identical (vertex, flag) lists are one coarse hyperedge;
+//     eta = sum of w (Section 3), mult = sum of mult;
+//   * coarse hyperedges are ordered by their smallest fine hyperedge (R5);
+//   * super-node state: size and syn summed, inbound set = union (R2).
+// Output arrays must have the input capacities (E+1, P, E, E, V', V', V'+1 and
+// the input's inbound-set length).  Writes the output sizes to `sizes`:
+// [E', P', total inbound-set length].  Returns 0, or -1 on a vmap value out of
+// range.
+int oracle_contract(int32_t V, int32_t E, const int64_t* eoff, const uint32_t* pins,
+                    const int32_t* w, const int32_t* mult, const int32_t* size,
+                    const int32_t* syn, const int64_t* soff, const int32_t* sids,
+                    const int32_t* vmap, int32_t n_coarse, int64_t* out_eoff,
+                    uint32_t* out_pins, int32_t* out_w, int32_t* out_mult,
+                    int32_t* out_size, int32_t* out_syn, int64_t* out_soff,
+                    int32_t* out_sids, int64_t* sizes) {
+  for (int32_t v = 0; v < V; ++v)
+    if (vmap[v] < 0 || vmap[v] >= n_coarse) return -1;
+  // hyperedges
+  std::map<std::vector<uint32_t>, int32_t> group;  // list -> coarse edge id
+  std::vector<std::vector<uint32_t>> lists;
+  std::vector<int64_t> eta, mu;
+  for (int32_t e = 0; e < E; ++e) {
+    std::map<int32_t, uint32_t> flags;  // coarse vertex -> destination flag
+    for (int64_t k = eoff[e]; k < eoff[e + 1]; ++k) {
+      int32_t c = vmap[pins[k] & IDMASK];
+      uint32_t d = (pins[k] & DST) ? 1u : 0u;
+      auto it = flags.find(c);
+      if (it == flags.end()) flags[c] = d;
+      else it->second |= d;
+    }
+    if (flags.size() < 2) continue;
+    std::vector<uint32_t> key;
+    for (auto& kv : flags) key.push_back((uint32_t)kv.first | (kv.second ? DST : 0u));
+    auto it = group.find(key);
+    if (it == group.end()) {
+      int32_t id = (int32_t)lists.size();
+      group.emplace(key, id);
+      lists.push_back(key);
+      eta.push_back(w[e]);
+      mu.push_back(mult[e]);
+    } else {
+      eta[it->second] += w[e];
+      mu[it->second] += mult[e];
+    }
+  }
+  int64_t p = 0;
+  out_eoff[0] = 0;
+  for (size_t a = 0; a < lists.size(); ++a) {
+    for (uint32_t x : lists[a]) out_pins[p++] = x;
+    out_eoff[a + 1] = p;
+    out_w[a] = (int32_t)eta[a];
+    out_mult[a] = (int32_t)mu[a];
+  }
+  // super-node state
+  std::vector<std::vector<int32_t>> members(n_coarse);
+  for (int32_t v = 0; v < V; ++v) members[vmap[v]].push_back(v);
+  int64_t s = 0;
+  out_soff[0] = 0;
+  for (int32_t c = 0; c < n_coarse; ++c) {
+    int64_t sz = 0, sy = 0;
+    std::vector<int32_t> uni;
+    for (int32_t v : members[c]) {
+      sz += size[v];
+      sy += syn[v];
+      uni.insert(uni.end(), sids + soff[v], sids + soff[v + 1]);
+    }
+    std::sort(uni.begin(), uni.end());
+    uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
+    out_size[c] = (int32_t)sz;
+    out_syn[c] = (int32_t)sy;
+    for (int32_t x : uni) out_sids[s++] = x;
+    out_soff[c + 1] = s;
+  }
+  sizes[0] = (int64_t)lists.size();
+  sizes[1] = p;
+  sizes[2] = s;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Connectivity, Section 3 Eq. (1):
+//   Conn(rho) = sum over hyperedges e of w(e) * (|{rho(n) : n in e}| - 1).
+// Every pin counts, the source included.  int64 accumulation.
+int64_t oracle_connectivity(int32_t E, const int64_t* eoff, const uint32_t* pins,
+                            const int32_t* w, const int32_t* part) {
+  int64_t conn = 0;
+  std::vector<int32_t> blocks;
+  for (int32_t e = 0; e < E; ++e) {
+    blocks.clear();
+    for (int64_t k = eoff[e]; k < eoff[e + 1]; ++k) blocks.push_back(part[pins[k] & IDMASK]);
+    std::sort(blocks.begin(), blocks.end());
+    int64_t lambda = std::unique(blocks.begin(), blocks.end()) - blocks.begin();
+    if (lambda > 0) conn += (int64_t)w[e] * (lambda - 1);
+  }
+  return conn;
+}
+
+}  // extern "C"

@@ -1,0 +1,206 @@
+"""Brute-force definitions for tiny hypergraphs (test helper).
+
+Every quantity is computed straight from its definition in Ronzani & Silvano,
+"GPU-Accelerated Hypergraph Partitioning and Placement to Map SNNs on
+Neuromorphic Hardware", by enumeration, with no data structure shared with the
+C++ oracle.  Super-nodes are tracked as explicit sets of ORIGINAL neurons, and
+every constraint is evaluated on the original hypergraph, so the propagated
+state of the oracle (sizes, inbound sets) is checked against first principles.
+
+Intended for inputs with at most a few dozen vertices.
+"""
+from __future__ import annotations
+
+DST = 1 << 31
+
+
+def edges_of(eoff, pins):
+    """List of hyperedges as lists of (vertex, is_destination)."""
+    out = []
+    for e in range(len(eoff) - 1):
+        out.append([(int(p) & (DST - 1), bool(int(p) & DST)) for p in pins[eoff[e]:eoff[e + 1]]])
+    return out
+
+
+class Orig:
+    """The original (level-0) SNN: in(n) and the Section 3 constraints."""
+
+    def __init__(self, n_vertices, eoff, pins):
+        self.V = n_vertices
+        self.edges = edges_of(eoff, pins)
+        self.inb = [set() for _ in range(n_vertices)]  # in(n): axons with n as destination
+        for e, pl in enumerate(self.edges):
+            for v, d in pl:
+                if d:
+                    self.inb[v].add(e)
+
+    def size(self, members):
+        return len(members)
+
+    def synapses(self, members):
+        """sum over n in p of |in(n)| (inbound pins)."""
+        return sum(len(self.inb[n]) for n in members)
+
+    def axons(self, members):
+        """|U_{n in p} in(n)| (distinct inbound hyperedges)."""
+        s = set()
+        for n in members:
+            s |= self.inb[n]
+        return len(s)
+
+    def feasible(self, members, lim):
+        return (self.size(members) <= lim.max_neurons
+                and self.synapses(members) <= lim.max_synapses
+                and self.axons(members) <= lim.max_axons)
+
+
+def score(edges, w, n, m):
+    """Eq. (12): sum of w(e) over e incident to n with m in e."""
+    s = 0
+    for e, pl in enumerate(edges):
+        vs = {v for v, _ in pl}
+        if n in vs and m in vs:
+            s += int(w[e])
+    return s
+
+
+def neighbours(edges, n):
+    out = set()
+    for pl in edges:
+        vs = {v for v, _ in pl}
+        if n in vs:
+            out |= vs
+    out.discard(n)
+    return out
+
+
+def candidates(V, edges, w, members, orig, lim):
+    """cand(n): valid neighbour of largest score, lowest id on ties."""
+    cand = [-1] * V
+    cs = [0] * V
+    for n in range(V):
+        best, bs = -1, 0
+        for m in sorted(neighbours(edges, n)):
+            if not orig.feasible(members[n] | members[m], lim):
+                continue
+            s = score(edges, w, n, m)
+            if s > bs or (s == bs and m < best):
+                best, bs = m, s
+        cand[n], cs[n] = best, bs
+    return cand, cs
+
+
+def best_child(V, cand, edges, w, n):
+    best, bs = -1, 0
+    for m in range(V):
+        if cand[m] == n:
+            s = score(edges, w, n, m)
+            if best < 0 or s > bs or (s == bs and m < best):
+                best, bs = m, s
+    return best
+
+
+def match_eq13(V, cand, edges, w):
+    """Eq. (13) by literal memoised recursion (first case takes precedence)."""
+    memo = {}
+
+    def match(n):
+        if n in memo:
+            return memo[n]
+        c = cand[n]
+        if c >= 0 and (cand[c] == n or match(c) == n):
+            r = c
+        else:
+            r = best_child(V, cand, edges, w, n)
+        memo[n] = r
+        return r
+
+    return [match(n) for n in range(V)]
+
+
+def match_walk(V, cand, edges, w):
+    """Sequential simulation of the walk procedure of Section 4.1: each node
+    acquires its candidate (a contested candidate keeps the acquirer of best
+    score, lowest id on ties), two-cycles are matched first, then the forest is
+    walked downward from the roots, matching a node with its acquirer when
+    both are still free."""
+    acq = [best_child(V, cand, edges, w, n) for n in range(V)]
+    m = [-1] * V
+    roots = [n for n in range(V) if cand[n] >= 0 and cand[cand[n]] == n]
+    for n in roots:
+        m[n] = cand[n]
+    frontier = list(roots)
+    seen = set(frontier)
+    while frontier:
+        nxt = []
+        for c in frontier:
+            children = sorted(x for x in range(V) if cand[x] == c and x not in seen)
+            if m[c] < 0 and acq[c] >= 0 and m[acq[c]] < 0:
+                m[c] = acq[c]
+                m[acq[c]] = c
+            for x in children:
+                seen.add(x)
+                nxt.append(x)
+        frontier = nxt
+    return m
+
+
+def vmap_from_match(V, m):
+    reps = [n for n in range(V) if m[n] < 0 or n < m[n]]
+    rank = {r: i for i, r in enumerate(reps)}
+    return [rank[n if (m[n] < 0 or n < m[n]) else m[n]] for n in range(V)], len(reps)
+
+
+def contract(edges, w, mult, vmap):
+    """Coarse hyperedges: distinct coarse vertices with OR-ed destination flags,
+    fewer than two dropped, identical (vertex, flag) lists merged (weights and
+    multiplicities summed), ordered by smallest fine hyperedge."""
+    order, agg = [], {}
+    for e, pl in enumerate(edges):
+        flags = {}
+        for v, d in pl:
+            c = vmap[v]
+            flags[c] = flags.get(c, False) or d
+        if len(flags) < 2:
+            continue
+        key = tuple(sorted(flags.items()))
+        if key not in agg:
+            agg[key] = [0, 0]
+            order.append(key)
+        agg[key][0] += int(w[e])
+        agg[key][1] += int(mult[e])
+    new_edges = [list(k) for k in order]
+    return new_edges, [agg[k][0] for k in order], [agg[k][1] for k in order]
+
+
+def connectivity(edges, w, part):
+    """Eq. (1)."""
+    return sum(int(w[e]) * (len({part[v] for v, _ in pl}) - 1) for e, pl in enumerate(edges))
+
+
+def hierarchy(n_vertices, eoff, pins, weight, lim, max_levels=64):
+    """Full coarsening loop by brute force.  Returns a list of per-level dicts."""
+    orig = Orig(n_vertices, eoff, pins)
+    edges = orig.edges
+    w = [int(x) for x in weight]
+    mult = [1] * len(edges)
+    members = [frozenset([n]) for n in range(n_vertices)]
+    V = n_vertices
+    out = []
+    for _ in range(max_levels):
+        cand, cs = candidates(V, edges, w, members, orig, lim)
+        m = match_eq13(V, cand, edges, w)
+        rec = dict(V=V, edges=edges, w=w, mult=mult, members=members, cand=cand, cscore=cs,
+                   match=m, match_walk=match_walk(V, cand, edges, w))
+        out.append(rec)
+        if all(c < 0 for c in cand):
+            break
+        vmap, nc = vmap_from_match(V, m)
+        rec["vmap"], rec["n_coarse"] = vmap, nc
+        new_members = [set() for _ in range(nc)]
+        for n in range(V):
+            new_members[vmap[n]] |= members[n]
+        members = [frozenset(s) for s in new_members]
+        edges, w, mult = contract(edges, w, mult, vmap)
+        V = nc
+    return out, orig

@@ -1,0 +1,199 @@
+"""Pins of the CPU oracle against the paper's definitions (no GPU).
+
+* hand-derived cases H1-H6 (tests/golden/hand_cases.json, each citing the
+  definition it follows);
+* brute-force enumeration on hundreds of tiny random SNNs, including tight
+  limits and many ties (tests/brute.py evaluates every constraint on the
+  original neurons of each super-node);
+* the paper's walk procedure, simulated sequentially, against Eq. (13);
+* closed forms of Eq. (1).
+"""
+import numpy as np
+import pytest
+
+import brute
+import hgcheck
+import oracle
+from paper_2609_07577_amd import synth
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+CASES = hgcheck.load_hand_cases()
+
+
+def _run_level(case, lim):
+    g = hgcheck.level_from_case(case)
+    L = oracle.level0(g)
+    return L, oracle.coarsen_level(L, lim)
+
+
+@pytest.mark.parametrize("name", ["H1_path_increasing", "H2_path_ties", "H3_neuron_limit",
+                                  "H4_axon_overlap"])
+def test_hand_case_level0(name):
+    case = CASES[name]
+    lim = hgcheck.limits_of(case["limits"])
+    L, r = _run_level(case, lim)
+    assert r.cand.tolist() == case["cand"]
+    if "cscore" in case:
+        assert r.cscore.tolist() == case["cscore"]
+    assert r.match.tolist() == case["match"]
+    if "vmap" in case:
+        assert r.vmap.tolist() == case["vmap"]
+    if "coarse_edges" in case:
+        c = r.coarse
+        assert hgcheck.edge_lists(c.eoff, c.pins) == case["coarse_edges"]
+        assert c.w.tolist() == case["coarse_w"]
+    if "coarse_mult" in case:
+        assert r.coarse.mult.tolist() == case["coarse_mult"]
+    if "coarse_size" in case:
+        assert r.coarse.size.tolist() == case["coarse_size"]
+        assert r.coarse.syn.tolist() == case["coarse_syn"]
+        assert r.coarse.ax.tolist() == case["coarse_ax"]
+    if "conn_vmap" in case:
+        assert oracle.connectivity(L.eoff, L.pins, L.w, r.vmap) == case["conn_vmap"]
+
+
+@pytest.mark.parametrize("name", ["H1_path_increasing", "H3_neuron_limit"])
+def test_hand_case_hierarchy(name):
+    case = CASES[name]
+    lim = hgcheck.limits_of(case["limits"])
+    g = hgcheck.level_from_case(case)
+    h = oracle.hierarchy(g, lim)
+    assert h.n_levels == case["levels_until_stop"]
+    if "level1_cand" in case:
+        assert h.levels[1].cand.tolist() == case["level1_cand"]
+    if "final_conn" in case:
+        L0 = h.levels[0].level
+        assert oracle.connectivity(L0.eoff, L0.pins, L0.w, h.final_partition()) == case["final_conn"]
+
+
+def test_hand_case_destination_flags():
+    case = CASES["H5_destination_flags"]
+    g = hgcheck.level_from_case(case)
+    L = oracle.level0(g)
+    c = oracle.contract(L, np.array(case["vmap"], np.int32), case["n_coarse"])
+    assert hgcheck.edge_lists(c.eoff, c.pins) == case["coarse_edges"]
+    assert c.w.tolist() == case["coarse_w"]
+    assert c.mult.tolist() == case["coarse_mult"]
+    assert c.ax.tolist() == case["coarse_ax"]
+    c2 = oracle.contract(c, np.array([0, 0], np.int32), 1)
+    assert c2.ax.tolist() == [case["merged_ax_after_second_contraction"]]
+    assert c2.E == 0
+
+
+def test_hand_case_connectivity():
+    case = CASES["H6_connectivity"]
+    g = hgcheck.level_from_case(case)
+    n = case["n"]
+    assert oracle.connectivity(g.eoff, g.pins, g.weight, np.array(case["part"], np.int32)) == case["conn"]
+    assert oracle.connectivity(g.eoff, g.pins, g.weight, np.arange(n, dtype=np.int32)) == case["conn_singletons"]
+    assert oracle.connectivity(g.eoff, g.pins, g.weight, np.zeros(n, np.int32)) == case["conn_one_block"]
+
+
+def _tiny_limits(rng):
+    kind = rng.integers(0, 4)
+    if kind == 0:
+        return hgcheck.BIG
+    return synth.Limits(int(rng.integers(2, 6)), int(rng.integers(1, 10)), int(rng.integers(1, 8)))
+
+
+def _compare_with_brute(g, lim):
+    bl, orig = brute.hierarchy(g.n_vertices, g.eoff, g.pins, g.weight, lim)
+    h = oracle.hierarchy(g, lim)
+    assert len(h.levels) == len(bl)
+    for r, b in zip(h.levels, bl):
+        L = r.level
+        assert L.V == b["V"]
+        assert hgcheck.edge_lists(L.eoff, L.pins) == [[[v, int(d)] for v, d in pl] for pl in b["edges"]]
+        assert L.w.tolist() == b["w"]
+        assert L.mult.tolist() == b["mult"]
+        mem = b["members"]
+        assert L.size.tolist() == [orig.size(s) for s in mem]
+        assert L.syn.tolist() == [orig.synapses(s) for s in mem]
+        assert L.ax.tolist() == [orig.axons(s) for s in mem]
+        assert r.cand.tolist() == b["cand"]
+        assert r.cscore.tolist() == b["cscore"]
+        assert r.match.tolist() == b["match"]
+        assert b["match_walk"] == b["match"]
+        if "vmap" in b:
+            assert r.vmap.tolist() == b["vmap"]
+            assert r.n_coarse == b["n_coarse"]
+        # every super-node is within limits at every level
+        for s in mem:
+            if len(s) > 1:
+                assert orig.feasible(s, lim)
+
+
+@pytest.mark.parametrize("block", range(6))
+def test_oracle_matches_brute_force_tiny(block):
+    rng = np.random.default_rng(1000 + block)
+    for i in range(60):
+        seed = int(rng.integers(0, 1 << 30))
+        n = int(rng.integers(1, 13))
+        g = synth.tiny_random(seed, n, p_axon=float(rng.uniform(0.3, 1.0)),
+                              max_fan=int(rng.integers(1, 6)), w_max=int(rng.integers(1, 4)))
+        _compare_with_brute(g, _tiny_limits(rng))
+
+
+def test_oracle_matches_brute_force_dense_ties():
+    # every weight 1 and full fan-out: ties decide every candidate
+    for seed in range(20):
+        g = synth.tiny_random(seed, 9, p_axon=1.0, max_fan=8, w_max=1)
+        _compare_with_brute(g, hgcheck.BIG)
+        _compare_with_brute(g, synth.Limits(3, 100, 100))
+
+
+def test_score_symmetry_and_candidates_subset():
+    g = synth.uniform(7, 300, 3, 12)
+    L = oracle.level0(g)
+    lim = synth.LIMITS["layered"]
+    cand, cscore = oracle.candidates(L, lim)
+    q = np.array([5, 17, 299, 0, 123], np.int32)
+    c2, s2 = oracle.candidates(L, lim, query=q)
+    assert np.array_equal(c2, cand[q]) and np.array_equal(s2, cscore[q])
+    edges = brute.edges_of(L.eoff, L.pins)
+    for n in q.tolist():
+        m = int(cand[n])
+        if m >= 0:
+            assert brute.score(edges, L.w, n, m) == brute.score(edges, L.w, m, n) == cscore[n]
+
+
+def test_connectivity_closed_forms():
+    g = synth.uniform(3, 500, 2, 20)
+    L = oracle.level0(g)
+    lens = np.diff(L.eoff)
+    singletons = int(np.sum(L.w.astype(np.int64) * (lens - 1)))
+    assert oracle.connectivity(L.eoff, L.pins, L.w, np.arange(g.n_vertices, dtype=np.int32)) == singletons
+    assert oracle.connectivity(L.eoff, L.pins, L.w, np.zeros(g.n_vertices, np.int32)) == 0
+    rng = np.random.default_rng(0)
+    part = rng.integers(0, 37, g.n_vertices).astype(np.int32)
+    assert oracle.connectivity(L.eoff, L.pins, L.w, part) == hgcheck.connectivity_numpy(
+        L.eoff, L.pins, L.w, part)
+    edges = brute.edges_of(L.eoff, L.pins)
+    assert oracle.connectivity(L.eoff, L.pins, L.w, part) == brute.connectivity(edges, L.w, part)
+
+
+def test_contract_general_partition_vs_brute():
+    rng = np.random.default_rng(5)
+    for seed in range(40):
+        g = synth.tiny_random(seed, int(rng.integers(2, 14)), max_fan=5, w_max=9)
+        L = oracle.level0(g)
+        k = int(rng.integers(1, g.n_vertices + 1))
+        part = rng.integers(0, k, g.n_vertices)
+        # compact to [0, nc)
+        uniq = np.unique(part)
+        vmap = np.searchsorted(uniq, part).astype(np.int32)
+        c = oracle.contract(L, vmap, len(uniq))
+        be, bw, bm = brute.contract(brute.edges_of(L.eoff, L.pins), L.w, L.mult, vmap.tolist())
+        assert hgcheck.edge_lists(c.eoff, c.pins) == [[[v, int(d)] for v, d in pl] for pl in be]
+        assert c.w.tolist() == bw and c.mult.tolist() == bm
+        orig = brute.Orig(g.n_vertices, g.eoff, g.pins)
+        for b in range(len(uniq)):
+            mem = set(np.nonzero(vmap == b)[0].tolist())
+            assert c.size[b] == orig.size(mem)
+            assert c.syn[b] == orig.synapses(mem)
+            assert c.ax[b] == orig.axons(mem)
