@@ -1,0 +1,188 @@
+/*
+ * hg.h — C ABI of the MI355X SNN-hypergraph coarsening library.
+ *
+ * One coarsening level of the multi-level partitioner of Ronzani & Silvano,
+ * "GPU-Accelerated Hypergraph Partitioning and Placement to Map SNNs on
+ * Neuromorphic Hardware", plus the (lambda - 1) connectivity objective.
+ *
+ * Model (paper, Section 2 "SNN and Hardware Models"): a spiking network is a
+ * hypergraph with one hyperedge per axon; its pins are the source neuron and
+ * the synapse targets; the hyperedge weight is the spike rate.  Every level
+ * of the hierarchy keeps this shape, with super-nodes for vertices.
+ *
+ * Data layout (all arrays are DEVICE memory owned by the caller):
+ *   edge_offsets  int64  [E+1]  CSR offsets of hyperedges into `pins`
+ *   pins          uint32 [P]    vertex_id | (flag << 31); ids strictly
+ *                               ascending inside each hyperedge; flag = 1
+ *                               when the vertex holds a destination of the
+ *                               hyperedge's axon(s), 0 for the source only
+ *   edge_weight   int32  [E]    spike rate, >= 1; the sum over all hyperedges
+ *                               must stay below 2^31
+ *   edge_mult     int32  [E]    number of original axons merged into the
+ *                               hyperedge (1 at level 0)
+ *   v_size        int32  [V]    neurons in the super-node
+ *   v_syn         int32  [V]    inbound synapses (sum of in-degrees)
+ *   v_axons       int32  [V]    distinct original axons with a destination
+ *                               inside the super-node
+ *
+ * Limits (Section 3, "Partitioning Definition"): a super-node p must satisfy
+ * |p| <= Omega, sum |in(n)| <= Phi, |U in(n)| <= Delta; a merge is valid iff
+ * all three hold for the union (inclusive bounds).
+ *
+ * Execution: every call is asynchronous on the context's HIP stream unless
+ * stated; scalar results are written to device memory.  The library owns
+ * only its scratch arena, grown on demand and freed by hg_destroy.  A context
+ * must not be used from two host threads at once.  No call throws; each
+ * returns an hg_status and hg_last_error() holds a message.
+ */
+#ifndef HG_H_
+#define HG_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HG_OK = 0,
+  HG_ERR_INVALID_ARG = 1,   /* null pointer, negative size, bad limits      */
+  HG_ERR_OVERFLOW = 2,      /* V >= 2^31, E >= 2^31, sum of weights >= 2^31  */
+  HG_ERR_CAPACITY = 3,      /* an output capacity is smaller than needed     */
+  HG_ERR_NO_MEMORY = 4,     /* the scratch arena could not be grown          */
+  HG_ERR_HIP = 5,           /* a HIP runtime call failed                     */
+  HG_ERR_UNIMPLEMENTED = 6,
+  HG_ERR_INVALID_LEVEL = 7, /* hg_validate_level found a malformed level     */
+  HG_ERR_INTERNAL = 8       /* a kernel reached an internal bound (reported
+                               by hg_sync); results of the calls since the
+                               previous hg_sync are not to be used         */
+} hg_status;
+
+typedef struct hg_ctx hg_ctx;
+
+typedef struct {
+  int32_t max_neurons;  /* Omega */
+  int32_t max_synapses; /* Phi   */
+  int32_t max_axons;    /* Delta */
+} hg_limits;
+
+/* A read-only level.  Sizes are host values. */
+typedef struct {
+  int32_t n_vertices;
+  int32_t n_edges;
+  int64_t n_pins;
+  const int64_t* edge_offsets;
+  const uint32_t* pins;
+  const int32_t* edge_weight;
+  const int32_t* edge_mult;
+  const int32_t* v_size;
+  const int32_t* v_syn;
+  const int32_t* v_axons;
+} hg_level;
+
+/* Output level of hg_contract.  Capacities are host values; a contraction
+ * never grows a level, so capacities equal to the input's sizes always
+ * suffice.  `sizes` is device int64[3] receiving (V', E', P'). */
+typedef struct {
+  int32_t cap_vertices;
+  int32_t cap_edges;
+  int64_t cap_pins;
+  int64_t* edge_offsets;
+  uint32_t* pins;
+  int32_t* edge_weight;
+  int32_t* edge_mult;
+  int32_t* v_size;
+  int32_t* v_syn;
+  int32_t* v_axons;
+  int64_t* sizes;
+} hg_level_out;
+
+/* Context on device `device`, issuing work on `hip_stream` (a hipStream_t;
+ * NULL means the default stream). */
+int hg_create(int device, void* hip_stream, hg_ctx** out);
+int hg_destroy(hg_ctx* ctx);
+int hg_set_stream(hg_ctx* ctx, void* hip_stream);
+/* Message of the last failing call on this context (never NULL). */
+const char* hg_last_error(hg_ctx* ctx);
+/* Blocks until all work queued on the context's stream is done, then checks
+ * the context's device error word: every data-dependent loop in the kernels
+ * is bounded, and a kernel that reaches a bound records it there instead of
+ * spinning; hg_sync then returns HG_ERR_INTERNAL and clears the word. */
+int hg_sync(hg_ctx* ctx);
+/* Bytes currently held by the scratch arena. */
+int64_t hg_scratch_bytes(hg_ctx* ctx);
+
+/*
+ * Level-0 state (Section 2 model; Section 3 constraint quantities):
+ * v_size = 1, v_syn = v_axons = number of hyperedges in which the vertex has
+ * the destination flag, edge_mult = 1.  Outputs are device arrays of V, V, V
+ * and E entries.
+ */
+int hg_init_state(hg_ctx* ctx, int32_t n_vertices, int32_t n_edges, int64_t n_pins,
+                  const int64_t* edge_offsets, const uint32_t* pins, int32_t* v_size,
+                  int32_t* v_syn, int32_t* v_axons, int32_t* edge_mult);
+
+/*
+ * One coarsening level (Section 4.1, "Coarsening"):
+ *   score(n, m) = sum of edge_weight over hyperedges holding both n and m
+ *                 (Eq. 12; symmetric);
+ *   cand(n)     = the neighbour m maximising score(n, m) among those whose
+ *                 merge with n is valid (limits above; the distinct-axon
+ *                 count of the union is v_axons[n] + v_axons[m] minus the
+ *                 edge_mult of hyperedges where both carry the destination
+ *                 flag), lowest id on ties; -1 if none;
+ *   match       = Eq. 13: two-cycles match; otherwise a vertex is taken by
+ *                 its candidate when the candidate is not itself taken and
+ *                 picked it as best proposer (score, then lowest id); a
+ *                 vertex not taken takes its best proposer; else -1;
+ *   vmap[n]     = rank, among representatives (unmatched vertices and the
+ *                 smaller vertex of each pair), of n's representative.
+ * Outputs (device): cand, cscore (may be NULL; cscore = score(n, cand(n)) or
+ * 0), match [V], vmap [V], n_coarse (int32 scalar), any_candidate (int32
+ * scalar, 1 iff some vertex has a candidate; 0 means the level is final).
+ */
+int hg_coarsen_level(hg_ctx* ctx, const hg_level* in, const hg_limits* limits,
+                     int32_t* cand, int32_t* cscore, int32_t* match, int32_t* vmap,
+                     int32_t* n_coarse, int32_t* any_candidate);
+
+/*
+ * Contraction G -> G_P for any vertex map (Section 3, "Partitioning
+ * Definition"; Section 4.1 state propagation).  `vmap` [V] holds values in
+ * [0, n_coarse); `n_coarse` is a device int32 scalar (e.g. written by
+ * hg_coarsen_level) and must not exceed out->cap_vertices.
+ *   * a fine hyperedge becomes its distinct coarse vertices, ascending, the
+ *     flag of a coarse vertex being the OR of its members' flags; if fewer
+ *     than two remain it is dropped;
+ *   * coarse hyperedges with identical (vertex, flag) lists are merged:
+ *     weights summed (eta of G_P) and multiplicities summed;
+ *   * coarse hyperedges are numbered by their smallest fine hyperedge;
+ *   * v_size and v_syn are summed; v_axons of a coarse vertex counts the
+ *     original axons with a destination in it, recomputed from the flags.
+ * Output sizes go to out->sizes.  Fails with HG_ERR_CAPACITY when a capacity
+ * is below the input's size (checked on the host before any work).
+ */
+int hg_contract(hg_ctx* ctx, const hg_level* in, const int32_t* vmap,
+                const int32_t* n_coarse, hg_level_out* out);
+
+/*
+ * Connectivity (Section 3, Eq. 1):
+ *   conn = sum over hyperedges e of edge_weight[e] * (number of distinct
+ *          part[v] over the pins v of e, minus 1).
+ * `part` [V] holds values in [0, V).  Writes the int64 result to device
+ * memory `conn`.  Uses only offsets, pins and weights of the level.
+ */
+int hg_connectivity(hg_ctx* ctx, const hg_level* lvl, const int32_t* part, int64_t* conn);
+
+/*
+ * Synchronous structural check of a level: offsets non-decreasing and within
+ * P, ids < V and strictly ascending per hyperedge, weights and multiplicities
+ * >= 1, total weight < 2^31, state values >= 0 when present (state pointers
+ * may be NULL).  Returns HG_OK or HG_ERR_INVALID_LEVEL / HG_ERR_OVERFLOW.
+ */
+int hg_validate_level(hg_ctx* ctx, const hg_level* lvl);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HG_H_ */

@@ -1,0 +1,451 @@
+// C ABI entry points: context, scratch arena, argument checks, dispatch.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "hg_internal.h"
+
+struct hg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  int32_t* dev_err = nullptr;  // device error word (bounds reached by kernels)
+};
+
+namespace hg {
+namespace {
+
+// Bump allocator over the arena; every block 256-byte aligned.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(int64_t n) {
+    size_t bytes = ((size_t)(n > 0 ? n : 1) * sizeof(T) + 255) & ~(size_t)255;
+    T* p = reinterpret_cast<T*>(base + off);
+    off += bytes;
+    return p;
+  }
+};
+
+// Sizing pass: same sequence of take() calls with a null base.
+struct Sizer {
+  size_t off = 0;
+  template <typename T>
+  T* take(int64_t n) {
+    off += ((size_t)(n > 0 ? n : 1) * sizeof(T) + 255) & ~(size_t)255;
+    return nullptr;
+  }
+};
+
+int fail(hg_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(hg_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+int hip_fail(hg_ctx* c, hipError_t e, const char* what) {
+  return fail(c, HG_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int ensure_arena(hg_ctx* c, size_t bytes) {
+  if (bytes <= c->arena_bytes) return HG_OK;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  if (c->arena) {
+    (void)hipFree(c->arena);
+    c->arena = nullptr;
+    c->arena_bytes = 0;
+  }
+  size_t want = bytes + bytes / 8;
+  e = hipMalloc((void**)&c->arena, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    c->arena = nullptr;
+    return fail(c, HG_ERR_NO_MEMORY, "cannot allocate %zu bytes of scratch", want);
+  }
+  c->arena_bytes = want;
+  return HG_OK;
+}
+
+int launch_status(hg_ctx* c) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return HG_OK;
+}
+
+int check_level(hg_ctx* c, const hg_level* L, bool need_state) {
+  if (!L) return fail(c, HG_ERR_INVALID_ARG, "level is null");
+  if (L->n_vertices < 0 || L->n_edges < 0 || L->n_pins < 0)
+    return fail(c, HG_ERR_INVALID_ARG, "negative level size");
+  if (L->n_vertices > 0x7FFFFFFE) return fail(c, HG_ERR_OVERFLOW, "too many vertices");
+  if (!L->edge_offsets) return fail(c, HG_ERR_INVALID_ARG, "edge_offsets is null");
+  if (L->n_pins > 0 && !L->pins) return fail(c, HG_ERR_INVALID_ARG, "pins is null");
+  if (L->n_edges > 0 && !L->edge_weight) return fail(c, HG_ERR_INVALID_ARG, "edge_weight is null");
+  if (need_state) {
+    if (L->n_edges > 0 && !L->edge_mult) return fail(c, HG_ERR_INVALID_ARG, "edge_mult is null");
+    if (L->n_vertices > 0 && (!L->v_size || !L->v_syn || !L->v_axons))
+      return fail(c, HG_ERR_INVALID_ARG, "vertex state is null");
+  }
+  return HG_OK;
+}
+
+__global__ void set_graph_const_kernel(GraphConst* gc, hg_limits lim) {
+  gc->omega = lim.max_neurons;
+  gc->phi = lim.max_synapses;
+  gc->delta = lim.max_axons;
+  gc->max_size = gc->max_syn = gc->max_ax = 0;
+}
+
+LevelView view_of(const hg_level* L, const Dims* d) {
+  return LevelView{d, L->edge_offsets, L->pins, L->edge_weight, L->edge_mult,
+                   L->v_size, L->v_syn, L->v_axons, nullptr};
+}
+
+// ---- scratch layouts -------------------------------------------------------
+template <typename A>
+struct CoarsenScratch {
+  Dims* dims;
+  GraphConst* gc;
+  int32_t* vcount;
+  int64_t* voff;
+  uint32_t* vinc;
+  int64_t* xn;
+  int32_t* bcount;
+  int32_t* blist;
+  int32_t* work;
+  int32_t* cursor;
+  int32_t* cand;
+  int32_t* cscore;
+  uint64_t* bkey;
+  uint32_t* jump;
+  int32_t* flags;
+  int32_t* rep;
+  int64_t* rank;
+  int64_t* partials;
+  void carve(A& a, int64_t V, int64_t E, int64_t P) {
+    (void)E;
+    dims = a.template take<Dims>(1);
+    gc = a.template take<GraphConst>(1);
+    vcount = a.template take<int32_t>(V);
+    voff = a.template take<int64_t>(V + 1);
+    vinc = a.template take<uint32_t>(P);
+    xn = a.template take<int64_t>(V);
+    bcount = a.template take<int32_t>(kNumBuckets);
+    blist = a.template take<int32_t>(kNumBuckets * V);
+    work = a.template take<int32_t>(kNumBuckets);
+    cursor = a.template take<int32_t>(2 * P);
+    cand = a.template take<int32_t>(V);
+    cscore = a.template take<int32_t>(V);
+    bkey = a.template take<uint64_t>(V);
+    jump = a.template take<uint32_t>(V);
+    flags = a.template take<int32_t>(32);
+    rep = a.template take<int32_t>(V);
+    rank = a.template take<int64_t>(V + 1);
+    partials = a.template take<int64_t>(scan_partials_size());
+  }
+};
+
+int64_t pow2_at_least(int64_t x) {
+  int64_t c = 64;
+  while (c < x) c <<= 1;
+  return c;
+}
+
+template <typename A>
+struct ContractLayout {
+  Dims* dims;
+  ContractScratch cs;
+  void carve(A& a, int64_t V, int64_t E, int64_t P) {
+    dims = a.template take<Dims>(1);
+    cs.out_dims = a.template take<Dims>(1);
+    cs.dstmult = a.template take<int32_t>(V);
+    cs.tpin = a.template take<uint32_t>(P);
+    cs.tlen = a.template take<int32_t>(E);
+    cs.fp = a.template take<uint64_t>(E);
+    cs.ebucket = a.template take<int32_t>(3 * E);
+    cs.ecount = a.template take<int32_t>(8);
+    cs.work = a.template take<int32_t>(4);
+    cs.htab_cap = pow2_at_least(2 * E);
+    cs.htab_key = a.template take<uint64_t>(cs.htab_cap);
+    cs.htab_lead = a.template take<int32_t>(cs.htab_cap);
+    cs.slot = a.template take<int32_t>(E);
+    cs.group = a.template take<int32_t>(E);
+    cs.mism = a.template take<int32_t>(E);
+    cs.lflag = a.template take<int32_t>(E);
+    cs.lrank = a.template take<int64_t>(E + 1);
+    cs.leader_at = a.template take<int32_t>(E);
+    cs.llen = a.template take<int64_t>(E);
+    cs.partials = a.template take<int64_t>(scan_partials_size());
+    cs.bitmap_words = (V + 31) / 32 + 1;
+    cs.bitmap = a.template take<uint32_t>((int64_t)kHugeWG * 2 * cs.bitmap_words);
+  }
+};
+
+template <typename A>
+struct ConnLayout {
+  Dims* dims;
+  ConnScratch cs;
+  void carve(A& a, int64_t V, int64_t E) {
+    dims = a.template take<Dims>(1);
+    cs.ebucket = a.template take<int32_t>(3 * E);
+    cs.ecount = a.template take<int32_t>(4);
+    cs.work = a.template take<int32_t>(4);
+    cs.bitmap_words = (V + 31) / 32 + 1;
+    cs.bitmap = a.template take<uint32_t>((int64_t)kHugeWG * cs.bitmap_words);
+  }
+};
+
+// ---- validation kernel -----------------------------------------------------
+__global__ void validate_kernel(LevelView L, int64_t V, int64_t E, int64_t P,
+                                unsigned long long* wsum, int32_t* bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (i == 0 && (L.eoff[0] != 0 || L.eoff[E] != P)) atomicOr(bad, 1);
+  for (int64_t e = i; e < E; e += stride) {
+    int64_t s = L.eoff[e], t = L.eoff[e + 1];
+    if (t < s || s < 0 || t > P) {
+      atomicOr(bad, 1);
+      continue;
+    }
+    if (L.w[e] < 1) atomicOr(bad, 4);
+    if (L.mult && L.mult[e] < 1) atomicOr(bad, 4);
+    atomicAdd(wsum, (unsigned long long)(L.w[e] > 0 ? L.w[e] : 0));
+    uint32_t prev = 0;
+    for (int64_t k = s; k < t; ++k) {
+      uint32_t id = L.pins[k] & kIdMask;
+      if ((int64_t)id >= V) atomicOr(bad, 2);
+      if (k > s && id <= prev) atomicOr(bad, 2);
+      prev = id;
+    }
+  }
+  for (int64_t v = i; v < V; v += stride) {
+    if (L.size && (L.size[v] < 1)) atomicOr(bad, 8);
+    if (L.syn && L.syn[v] < 0) atomicOr(bad, 8);
+    if (L.ax && L.ax[v] < 0) atomicOr(bad, 8);
+  }
+}
+
+}  // namespace
+}  // namespace hg
+
+using namespace hg;
+
+extern "C" {
+
+int hg_create(int device, void* hip_stream, hg_ctx** out) {
+  if (!out) return HG_ERR_INVALID_ARG;
+  *out = nullptr;
+  hg_ctx* c = new (std::nothrow) hg_ctx();
+  if (!c) return HG_ERR_NO_MEMORY;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->dev_err, 256);
+  if (e != hipSuccess) {
+    delete c;
+    return HG_ERR_HIP;
+  }
+  fill_i32(c->dev_err, 0, 1, c->stream);
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(c->dev_err);
+    delete c;
+    return HG_ERR_HIP;
+  }
+  *out = c;
+  return HG_OK;
+}
+
+int hg_destroy(hg_ctx* c) {
+  if (!c) return HG_OK;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->arena) (void)hipFree(c->arena);
+  if (c->dev_err) (void)hipFree(c->dev_err);
+  delete c;
+  return HG_OK;
+}
+
+int hg_set_stream(hg_ctx* c, void* hip_stream) {
+  if (!c) return HG_ERR_INVALID_ARG;
+  c->stream = (hipStream_t)hip_stream;
+  return HG_OK;
+}
+
+const char* hg_last_error(hg_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+int hg_sync(hg_ctx* c) {
+  if (!c) return HG_ERR_INVALID_ARG;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  int32_t flags = 0;
+  e = hipMemcpy(&flags, c->dev_err, sizeof flags, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "error word read-back");
+  if (flags) {
+    fill_i32(c->dev_err, 0, 1, c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    return fail(c, HG_ERR_INTERNAL,
+                "a kernel reached an internal bound (flags 0x%x: 1 score table, 2 passes, "
+                "4 distinct set, 8 fingerprint table, 16 work count, 32 list length)",
+                flags);
+  }
+  return HG_OK;
+}
+
+int64_t hg_scratch_bytes(hg_ctx* c) { return c ? (int64_t)c->arena_bytes : 0; }
+
+int hg_init_state(hg_ctx* c, int32_t V, int32_t E, int64_t P, const int64_t* eoff,
+                  const uint32_t* pins, int32_t* size, int32_t* syn, int32_t* ax,
+                  int32_t* mult) {
+  if (!c) return HG_ERR_INVALID_ARG;
+  if (V < 0 || E < 0 || P < 0) return fail(c, HG_ERR_INVALID_ARG, "negative size");
+  if (!eoff || (P > 0 && !pins) || (V > 0 && (!size || !syn || !ax)) || (E > 0 && !mult))
+    return fail(c, HG_ERR_INVALID_ARG, "null pointer");
+  Sizer sz;
+  sz.take<Dims>(1);
+  int rc = ensure_arena(c, sz.off);
+  if (rc) return rc;
+  Carver cv{c->arena};
+  Dims* d = cv.take<Dims>(1);
+  set_dims(d, V, E, P, c->stream);
+  level0_state(d, eoff, pins, V, E, size, syn, ax, mult, c->stream);
+  return launch_status(c);
+}
+
+int hg_coarsen_level(hg_ctx* c, const hg_level* in, const hg_limits* lim, int32_t* cand,
+                     int32_t* cscore, int32_t* match, int32_t* vmap, int32_t* n_coarse,
+                     int32_t* any_candidate) {
+  if (!c) return HG_ERR_INVALID_ARG;
+  int rc = check_level(c, in, true);
+  if (rc) return rc;
+  if (!lim || lim->max_neurons < 0 || lim->max_synapses < 0 || lim->max_axons < 0)
+    return fail(c, HG_ERR_INVALID_ARG, "bad limits");
+  if ((in->n_vertices > 0 && (!match || !vmap)) || !n_coarse || !any_candidate)
+    return fail(c, HG_ERR_INVALID_ARG, "null output");
+  const int64_t V = in->n_vertices, E = in->n_edges, P = in->n_pins;
+  Sizer sz;
+  CoarsenScratch<Sizer> ls;
+  ls.carve(sz, V, E, P);
+  rc = ensure_arena(c, sz.off);
+  if (rc) return rc;
+  Carver cv{c->arena};
+  CoarsenScratch<Carver> S;
+  S.carve(cv, V, E, P);
+  hipStream_t s = c->stream;
+  set_dims(S.dims, V, E, P, s);
+  set_graph_const_kernel<<<1, 1, 0, s>>>(S.gc, *lim);
+  LevelView L = view_of(in, S.dims);
+  // S0, S1
+  build_incidence(L, V, E, P, S.vcount, S.voff, S.vinc, S.partials, s);
+  Buckets b{S.bcount, S.blist};
+  expansion_and_buckets(L, S.voff, S.vinc, V, S.xn, S.gc, 1, b, s);
+  // S2
+  int32_t* cd = cand ? cand : S.cand;
+  int32_t* cs = cscore ? cscore : S.cscore;
+  ScoreArgs sa{L, S.voff, S.vinc, S.xn, S.gc, S.cursor, cd, cs, S.work, b, c->dev_err};
+  score_candidates(sa, V, P, s);
+  // S3-S5
+  MatchArgs ma{S.dims, cd, cs, S.bkey, S.jump, S.jump, S.flags, match, vmap, S.rep, S.rank,
+               S.partials, n_coarse, any_candidate};
+  match_and_vmap(ma, V, s);
+  return launch_status(c);
+}
+
+int hg_contract(hg_ctx* c, const hg_level* in, const int32_t* vmap, const int32_t* n_coarse,
+                hg_level_out* out) {
+  if (!c) return HG_ERR_INVALID_ARG;
+  int rc = check_level(c, in, true);
+  if (rc) return rc;
+  if ((in->n_vertices > 0 && !vmap) || !n_coarse || !out)
+    return fail(c, HG_ERR_INVALID_ARG, "null argument");
+  if (!out->edge_offsets || !out->pins || !out->edge_weight || !out->edge_mult ||
+      !out->v_size || !out->v_syn || !out->v_axons || !out->sizes)
+    return fail(c, HG_ERR_INVALID_ARG, "null output array");
+  const int64_t V = in->n_vertices, E = in->n_edges, P = in->n_pins;
+  if (out->cap_vertices < V || out->cap_edges < E || out->cap_pins < P)
+    return fail(c, HG_ERR_CAPACITY, "output capacities (%d, %d, %lld) below input sizes",
+                out->cap_vertices, out->cap_edges, (long long)out->cap_pins);
+  Sizer sz;
+  ContractLayout<Sizer> ls;
+  ls.carve(sz, V, E, P);
+  rc = ensure_arena(c, sz.off);
+  if (rc) return rc;
+  Carver cv{c->arena};
+  ContractLayout<Carver> S;
+  S.carve(cv, V, E, P);
+  hipStream_t s = c->stream;
+  set_dims(S.dims, V, E, P, s);
+  LevelView L = view_of(in, S.dims);
+  S.cs.err = c->dev_err;
+  contract_level(L, V, E, P, vmap, n_coarse, out, S.cs, s);
+  return launch_status(c);
+}
+
+int hg_connectivity(hg_ctx* c, const hg_level* lvl, const int32_t* part, int64_t* conn) {
+  if (!c) return HG_ERR_INVALID_ARG;
+  int rc = check_level(c, lvl, false);
+  if (rc) return rc;
+  if ((lvl->n_vertices > 0 && !part) || !conn) return fail(c, HG_ERR_INVALID_ARG, "null argument");
+  const int64_t V = lvl->n_vertices, E = lvl->n_edges, P = lvl->n_pins;
+  Sizer sz;
+  ConnLayout<Sizer> ls;
+  ls.carve(sz, V, E);
+  rc = ensure_arena(c, sz.off);
+  if (rc) return rc;
+  Carver cv{c->arena};
+  ConnLayout<Carver> S;
+  S.carve(cv, V, E);
+  hipStream_t s = c->stream;
+  set_dims(S.dims, V, E, P, s);
+  LevelView L = view_of(lvl, S.dims);
+  S.cs.err = c->dev_err;
+  connectivity(L, E, V, part, conn, S.cs, s);
+  return launch_status(c);
+}
+
+int hg_validate_level(hg_ctx* c, const hg_level* L) {
+  if (!c) return HG_ERR_INVALID_ARG;
+  int rc = check_level(c, L, false);
+  if (rc) return rc;
+  Sizer sz;
+  sz.take<unsigned long long>(1);
+  sz.take<int32_t>(1);
+  rc = ensure_arena(c, sz.off);
+  if (rc) return rc;
+  Carver cv{c->arena};
+  unsigned long long* wsum = cv.take<unsigned long long>(1);
+  int32_t* bad = cv.take<int32_t>(1);
+  hipStream_t s = c->stream;
+  fill_u64((uint64_t*)wsum, 0, 1, s);
+  fill_i32(bad, 0, 1, s);
+  LevelView lv{nullptr, L->edge_offsets, L->pins, L->edge_weight, L->edge_mult,
+               L->v_size, L->v_syn, L->v_axons, nullptr};
+  validate_kernel<<<grid_for(L->n_edges > L->n_vertices ? L->n_edges : L->n_vertices, 256, 4096),
+                    256, 0, s>>>(lv, L->n_vertices, L->n_edges, L->n_pins, wsum, bad);
+  rc = launch_status(c);
+  if (rc) return rc;
+  unsigned long long hw = 0;
+  int32_t hb = 0;
+  hipError_t e = hipMemcpyAsync(&hw, wsum, sizeof hw, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof hb, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "validate read-back");
+  if (hb) return fail(c, HG_ERR_INVALID_LEVEL, "malformed level (flags 0x%x)", hb);
+  if (hw >= (1ull << 31)) return fail(c, HG_ERR_OVERFLOW, "total weight %llu >= 2^31", hw);
+  return HG_OK;
+}
+
+}  // extern "C"

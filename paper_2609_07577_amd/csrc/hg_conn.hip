@@ -1,0 +1,190 @@
+// S8: connectivity (paper, Section 3, Eq. 1):
+//   Conn = sum over hyperedges e of w(e) * (lambda(e) - 1),
+//   lambda(e) = number of distinct part[v] over the pins v of e.
+// Three size classes: a wave with one pin per lane sorts the block ids by
+// shuffles (<= 64 pins); a work-group counts distinct ids in an LDS hash set
+// (<= 16384 pins); larger hyperedges use a bitmap over the block-id range.
+// Sums are int64 and combined with integer atomics, so the result does not
+// depend on scheduling.
+#include "hg_internal.h"
+
+namespace hg {
+
+namespace {
+
+constexpr int kSmallMax = 64;
+constexpr int kBlockMax = 16384;
+constexpr int kThreads = 256;
+constexpr int kSetSlots = 2 * kBlockMax;
+constexpr uint32_t kEmptySlot = 0xFFFFFFFFu;
+
+__global__ void conn_classify_kernel(const Dims* __restrict__ d, const int64_t* __restrict__ eoff,
+                                     int32_t* __restrict__ list, int32_t* __restrict__ count,
+                                     int64_t maxE) {
+  int64_t E = d->E;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < E; i += stride) {
+    int64_t s = eoff[i + 1] - eoff[i];
+    if (s < 2) continue;  // lambda <= 1 contributes nothing
+    int b = s <= kSmallMax ? 0 : (s <= kBlockMax ? 1 : 2);
+    int pos = atomicAdd(&count[b], 1);
+    list[(int64_t)b * maxE + pos] = (int32_t)i;
+  }
+}
+
+struct ConnArgs {
+  LevelView L;
+  const int32_t* part;
+  const int32_t* list;
+  const int32_t* count;
+  int32_t* work;
+  int64_t* conn;
+  uint32_t* bitmap;
+  int64_t bitmap_words;
+  int64_t part_words;
+  int32_t* err;
+  int64_t max_items;
+};
+
+__global__ void conn_small_kernel(ConnArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+  const int64_t cnt = a.count[0] < a.max_items ? a.count[0] : a.max_items;
+  int64_t acc = 0;
+  for (int64_t it = wave; it < cnt; it += nw) {
+    const int64_t e = a.list[it];
+    const int64_t s0 = a.L.eoff[e];
+    const int len = (int)(a.L.eoff[e + 1] - s0);
+    uint32_t key = 0xFFFFFFFFu;
+    if (lane < len) key = (uint32_t)a.part[a.L.pins[s0 + lane] & kIdMask];
+#pragma unroll
+    for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        uint32_t other = __shfl_xor(key, j, kWave);
+        bool up = (lane & k) == 0;
+        bool lower = (lane & j) == 0;
+        uint32_t mn = key < other ? key : other;
+        uint32_t mx = key < other ? other : key;
+        key = (lower == up) ? mn : mx;
+      }
+    }
+    uint32_t prev = __shfl_up(key, 1, kWave);
+    bool head = lane < len && (lane == 0 || prev != key);
+    int lambda = __popcll(__ballot(head));
+    acc += (int64_t)a.L.w[e] * (lambda - 1);  // same value in every lane
+  }
+  if (lane == 0 && acc) atomicAdd((unsigned long long*)a.conn, (unsigned long long)acc);
+}
+
+__global__ __launch_bounds__(kThreads) void conn_block_kernel(ConnArgs a) {
+  __shared__ uint32_t set[kSetSlots];
+  __shared__ int32_t s_item;
+  __shared__ int32_t s_new;
+  const int tid = threadIdx.x;
+  int32_t cnt = a.count[1];
+  if (cnt > a.max_items) {
+    if (tid == 0) atomicOr(a.err, kErrWorkCount);
+    cnt = (int32_t)a.max_items;
+  }
+  for (int i = tid; i < kSetSlots; i += kThreads) set[i] = kEmptySlot;
+  int64_t acc = 0;
+  while (true) {
+    __syncthreads();
+    if (tid == 0) {
+      s_item = atomicAdd(&a.work[1], 1);
+      s_new = 0;
+    }
+    __syncthreads();
+    const int32_t item = s_item;
+    if (item >= cnt) break;
+    const int64_t e = a.list[item];
+    const int64_t s0 = a.L.eoff[e], s1 = a.L.eoff[e + 1];
+    uint32_t cap = 128;
+    while (cap < 2 * (uint64_t)(s1 - s0) && cap < (uint32_t)kSetSlots) cap <<= 1;
+    const uint32_t mask = cap - 1;
+    int mine = 0;
+    for (int64_t k = s0 + tid; k < s1; k += kThreads) {
+      uint32_t b = (uint32_t)a.part[a.L.pins[k] & kIdMask];
+      uint32_t h = (b * 0x9E3779B1u) & mask;
+      uint32_t probe = 0;
+      for (; probe <= mask; ++probe) {
+        uint32_t old = atomicCAS(&set[h], kEmptySlot, b);
+        if (old == kEmptySlot) {
+          ++mine;
+          break;
+        }
+        if (old == b) break;
+        h = (h + 1) & mask;
+      }
+      if (probe > mask) atomicOr(a.err, kErrSetFull);
+    }
+    if (mine) atomicAdd(&s_new, mine);
+    __syncthreads();
+    if (tid == 0) acc += (int64_t)a.L.w[e] * (s_new - 1);
+    for (uint32_t i = tid; i < cap; i += kThreads) set[i] = kEmptySlot;
+  }
+  if (tid == 0 && acc) atomicAdd((unsigned long long*)a.conn, (unsigned long long)acc);
+}
+
+__global__ __launch_bounds__(kThreads) void conn_huge_kernel(ConnArgs a) {
+  __shared__ int32_t s_item;
+  __shared__ int32_t s_new;
+  const int tid = threadIdx.x;
+  int32_t cnt = a.count[2];
+  if (cnt > a.max_items) {
+    if (tid == 0) atomicOr(a.err, kErrWorkCount);
+    cnt = (int32_t)a.max_items;
+  }
+  uint32_t* bm = a.bitmap + (int64_t)blockIdx.x * a.bitmap_words;
+  for (int64_t w = tid; w < a.part_words; w += kThreads) bm[w] = 0;
+  int64_t acc = 0;
+  while (true) {
+    __syncthreads();
+    if (tid == 0) {
+      s_item = atomicAdd(&a.work[2], 1);
+      s_new = 0;
+    }
+    __syncthreads();
+    const int32_t item = s_item;
+    if (item >= cnt) break;
+    const int64_t e = a.list[item];
+    int mine = 0;
+    for (int64_t k = a.L.eoff[e] + tid; k < a.L.eoff[e + 1]; k += kThreads) {
+      uint32_t b = (uint32_t)a.part[a.L.pins[k] & kIdMask];
+      uint32_t bit = 1u << (b & 31);
+      uint32_t old = atomicOr(&bm[b >> 5], bit);
+      if (!(old & bit)) ++mine;
+    }
+    if (mine) atomicAdd(&s_new, mine);
+    __syncthreads();
+    if (tid == 0) acc += (int64_t)a.L.w[e] * (s_new - 1);
+    for (int64_t k = a.L.eoff[e] + tid; k < a.L.eoff[e + 1]; k += kThreads) {
+      uint32_t b = (uint32_t)a.part[a.L.pins[k] & kIdMask];
+      bm[b >> 5] = 0;
+    }
+  }
+  if (tid == 0 && acc) atomicAdd((unsigned long long*)a.conn, (unsigned long long)acc);
+}
+
+}  // namespace
+
+void connectivity(const LevelView& L, int64_t maxE, int64_t part_range, const int32_t* part,
+                  int64_t* conn, const ConnScratch& cs, hipStream_t s) {
+  fill_i64(conn, 0, 1, s);
+  fill_i32(cs.ecount, 0, 4, s);
+  fill_i32(cs.work, 0, 4, s);
+  conn_classify_kernel<<<grid_for(maxE, 256, 16384), 256, 0, s>>>(L.dims, L.eoff, cs.ebucket,
+                                                                  cs.ecount, maxE);
+  ConnArgs a{L, part, cs.ebucket, cs.ecount, cs.work, conn, cs.bitmap, cs.bitmap_words,
+             (part_range + 31) / 32, cs.err, maxE};
+  conn_small_kernel<<<grid_for(maxE, 4, 16384), 256, 0, s>>>(a);
+  a.list = cs.ebucket + maxE;
+  conn_block_kernel<<<device_cu_count(), kThreads, 0, s>>>(a);
+  a.list = cs.ebucket + 2 * maxE;
+  conn_huge_kernel<<<kHugeWG, kThreads, 0, s>>>(a);
+}
+
+}  // namespace hg

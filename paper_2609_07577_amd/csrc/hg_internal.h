@@ -1,0 +1,185 @@
+// Internal declarations shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hg.h"
+
+namespace hg {
+
+constexpr uint32_t kDst = 0x80000000u;
+constexpr uint32_t kIdMask = 0x7FFFFFFFu;
+constexpr int kWave = 64;
+
+// Device error word.  Every data-dependent loop in the library has a bound;
+// a kernel that reaches one ORs its bit in here (instead of spinning) and the
+// host reports it from hg_sync.
+enum : int32_t {
+  kErrTableFull = 1,    // S2 score table probe bound
+  kErrPassLimit = 2,    // S2 multipass pass bound
+  kErrSetFull = 4,      // S8 distinct-set probe bound
+  kErrHashFull = 8,     // S7 fingerprint table probe bound
+  kErrWorkCount = 16,   // a work-list count above its capacity
+  kErrListLength = 32,  // S7 list longer than its source hyperedge
+};
+
+// Level sizes kept in device memory so that a chain of kernels can run
+// without reading them back on the host.
+struct Dims {
+  int64_t V;
+  int64_t E;
+  int64_t P;
+};
+
+// Per-graph constants.  A context works on one graph at a time; a batch lays
+// several graphs side by side in one level and gives every vertex its graph
+// index, so the kernels look the limits up per vertex.
+struct GraphConst {
+  int32_t omega, phi, delta;
+  int32_t max_size, max_syn, max_ax;  // level maxima (validity shortcut)
+};
+
+// Device views of a level.
+struct LevelView {
+  const Dims* dims;
+  const int64_t* eoff;
+  const uint32_t* pins;
+  const int32_t* w;
+  const int32_t* mult;
+  const int32_t* size;
+  const int32_t* syn;
+  const int32_t* ax;
+  const int32_t* gid;  // graph index per vertex, or null (graph 0)
+};
+
+// Simple grid sizing: enough blocks to cover n items with `per_block` items
+// per block, capped at `cap` (kernels then loop grid-stride).
+inline int grid_for(int64_t n, int per_block, int cap = 65536) {
+  int64_t g = (n + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+int device_cu_count();
+
+// ---- primitives (hg_prims.hip) --------------------------------------------
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
+void fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
+void set_dims(Dims* d, int64_t V, int64_t E, int64_t P, hipStream_t s);
+
+// Exclusive scan of n = *count entries of `in` into out[0..n], out[n] = total.
+// `partials` needs scan_partials_size() int64 entries.  `count` is device.
+int scan_partials_size();
+void exclusive_scan_i32(const int32_t* in, int64_t* out, const int64_t* count,
+                        int64_t max_count, int64_t* partials, hipStream_t s);
+void exclusive_scan_i64(const int64_t* in, int64_t* out, const int64_t* count,
+                        int64_t max_count, int64_t* partials, hipStream_t s);
+
+// ---- S0/S1 (hg_transpose.hip) ----------------------------------------------
+// Incidence lists: voff [V+1], vinc [P] = edge | flag << 31.
+void build_incidence(const LevelView& L, int64_t maxV, int64_t maxE, int64_t maxP,
+                     int32_t* vcount, int64_t* voff, uint32_t* vinc, int64_t* partials,
+                     hipStream_t s);
+void level0_state(const Dims* d, const int64_t* eoff, const uint32_t* pins, int64_t maxV,
+                  int64_t maxE, int32_t* size, int32_t* syn, int32_t* ax, int32_t* mult,
+                  hipStream_t s);
+
+// Expansion X_n = sum over incident hyperedges of their size; level maxima;
+// bucket lists for the scoring kernels.
+// Buckets 0-2 without, 3-5 with the shared-inbound count: single pass in the
+// small table, single pass in the big table, multipass in the big table.
+constexpr int kNumBuckets = 6;
+constexpr int kSmallSlots = 4096;
+constexpr int kBigSlots = 16384;
+constexpr int kBigSlotsOv = 8192;
+struct Buckets {
+  int32_t* count;  // [kNumBuckets] device counters
+  int32_t* list;   // [kNumBuckets * maxV]
+};
+void expansion_and_buckets(const LevelView& L, const int64_t* voff, const uint32_t* vinc,
+                           int64_t maxV, int64_t* xn, GraphConst* gc, int32_t n_graphs,
+                           Buckets b, hipStream_t s);
+
+// ---- S2 (hg_score.hip) ----------------------------------------------------
+struct ScoreArgs {
+  LevelView L;
+  const int64_t* voff;
+  const uint32_t* vinc;
+  const int64_t* xn;
+  const GraphConst* gc;
+  int32_t* cursor;   // [2 * P] scratch for multipass cursors
+  int32_t* cand;
+  int32_t* cscore;
+  int32_t* work;     // [kNumBuckets] work counters (zeroed by the launcher)
+  Buckets b;
+  int32_t* err;
+};
+void score_candidates(const ScoreArgs& a, int64_t maxV, int64_t maxP, hipStream_t s);
+
+// ---- S3-S5 (hg_match.hip) ---------------------------------------------------
+struct MatchArgs {
+  const Dims* dims;
+  const int32_t* cand;
+  const int32_t* cscore;
+  uint64_t* bkey;      // [V]
+  uint32_t* jump0;     // [V]
+  uint32_t* jump1;     // [V]
+  int32_t* flag;       // [4] device flags
+  int32_t* match;      // [V] out
+  int32_t* vmap;       // [V] out
+  int32_t* rep;        // [V] scratch
+  int64_t* rank;       // [V+1] scratch
+  int64_t* partials;
+  int32_t* n_coarse;   // device scalar out
+  int32_t* any_cand;   // device scalar out
+};
+void match_and_vmap(const MatchArgs& a, int64_t maxV, hipStream_t s);
+
+// ---- S6/S7 + state (hg_contract.hip) --------------------------------------
+struct ContractScratch {
+  int32_t* dstmult;     // [V]
+  uint32_t* tpin;       // [P]
+  int32_t* tlen;        // [E]
+  uint64_t* fp;         // [E]
+  int32_t* ebucket;     // [3 * E] size-bucket lists
+  int32_t* ecount;      // [4] counters
+  int32_t* work;        // [4] work counters
+  uint64_t* htab_key;   // [T]
+  int32_t* htab_lead;   // [T]
+  int64_t htab_cap;     // T (power of two)
+  int32_t* slot;        // [E]
+  int32_t* group;       // [E]
+  int32_t* mism;        // [E] mismatch list
+  int32_t* lflag;       // [E]
+  int64_t* lrank;       // [E+1]
+  int32_t* leader_at;   // [E]
+  int64_t* llen;        // [E]
+  int64_t* partials;
+  uint32_t* bitmap;     // huge-hyperedge fallback [n_wg * words]
+  int64_t bitmap_words; // per work-group
+  Dims* out_dims;       // device Dims of the output level
+  int32_t* err;
+};
+int contract_level(const LevelView& L, int64_t maxV, int64_t maxE, int64_t maxP,
+                   const int32_t* vmap, const int32_t* n_coarse, hg_level_out* out,
+                   const ContractScratch& cs, hipStream_t s);
+
+// ---- S8 (hg_conn.hip) -----------------------------------------------------
+struct ConnScratch {
+  int32_t* ebucket;     // [3 * E]
+  int32_t* ecount;      // [4]
+  int32_t* work;        // [4]
+  uint32_t* bitmap;
+  int64_t bitmap_words;
+  int32_t* err;
+};
+void connectivity(const LevelView& L, int64_t maxE, int64_t part_range, const int32_t* part,
+                  int64_t* conn, const ConnScratch& cs, hipStream_t s);
+
+// Number of work-groups of the huge-segment fallback kernels.
+constexpr int kHugeWG = 64;
+
+}  // namespace hg

@@ -1,0 +1,382 @@
+// S2: neighbour scores and candidate selection (paper, Section 4.1,
+// "Coarsening", Eq. 12).
+//
+// For a vertex n the score of a neighbour m is the summed weight of the
+// hyperedges holding both.  A work-group owns one vertex at a time and
+// accumulates its histogram in an LDS hash table of packed 64-bit slots
+// (key = neighbour id in the high half, score in the low half; scores never
+// carry into the key because the total weight of a level is < 2^31).
+//
+// Neighbourhoods larger than the table are processed in passes over
+// contiguous ranges of neighbour ids.  Pins are ascending inside every
+// hyperedge, so one cursor per incident hyperedge walks it across the passes
+// and every pin is read once per pass that contains it.  A pass that would
+// overfill the table is abandoned and retried with half the id range; a
+// nearly empty pass doubles the range.
+//
+// Candidate = valid neighbour with the largest (score, -id), i.e. lowest id
+// on ties.  Validity (Section 3 limits on the merged super-node) is tested
+// only for table entries that beat the current best, and skipped entirely
+// when the level maxima show that every neighbour of n is valid.  The
+// distinct-axon overlap of n and m is needed only when ax_n + ax_m exceeds
+// Delta; it is then the summed multiplicity of hyperedges in which both n and
+// m carry the destination flag, found by binary search of m in n's inbound
+// hyperedges.
+#include "hg_internal.h"
+
+namespace hg {
+
+namespace {
+
+constexpr uint64_t kEmpty = 0xFFFFFFFF00000000ull;
+
+__device__ inline uint32_t slot_hash(uint32_t id, int shift) {
+  return (id * 0x9E3779B1u) >> shift;
+}
+
+constexpr uint32_t kNoSlot = 0x40000000u;
+constexpr int kMaxPasses = 1 << 16;
+
+// Adds `wt` to the score of `id`; returns the slot, with bit 31 set when the
+// entry is new.  The callers keep the table at most about half full, so the
+// probe bound (the table size) is never reached by a correct run; if it is,
+// the error word says so and kNoSlot is returned.
+__device__ inline uint32_t table_add(uint64_t* table, uint32_t mask, int shift, uint32_t id,
+                                     uint32_t wt, int32_t* err) {
+  uint32_t h = slot_hash(id, shift) & mask;
+  const uint64_t mine = ((uint64_t)id << 32) | wt;
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    uint64_t old = atomicCAS((unsigned long long*)&table[h], (unsigned long long)kEmpty,
+                             (unsigned long long)mine);
+    if (old == kEmpty) return h | 0x80000000u;
+    if ((uint32_t)(old >> 32) == id) {
+      atomicAdd((unsigned long long*)&table[h], (unsigned long long)wt);
+      return h;
+    }
+    h = (h + 1) & mask;
+  }
+  atomicOr(err, kErrTableFull);
+  return kNoSlot;
+}
+
+__device__ inline int log2_pow2(uint32_t c) { return 31 - __clz(c); }
+
+struct VertexCtx {
+  int32_t n;
+  int64_t beg, deg;
+  int32_t size_n, syn_n, ax_n;
+  GraphConst G;
+  bool all_valid;
+};
+
+// Section 3 limits on the union of n and m; `ov` is the number of original
+// axons with a destination in both (0 when the distinct-axon bound cannot
+// bind for this vertex).
+__device__ inline bool merge_valid(const ScoreArgs& a, const VertexCtx& v, uint32_t m,
+                                   int64_t ov) {
+  if ((int64_t)v.size_n + a.L.size[m] > v.G.omega) return false;
+  if ((int64_t)v.syn_n + a.L.syn[m] > v.G.phi) return false;
+  return (int64_t)v.ax_n + a.L.ax[m] - ov <= v.G.delta;
+}
+
+// Scans the first `cap` slots: folds entries into `best`, empties them.
+template <bool OV>
+__device__ inline void drain_table(uint64_t* table, uint32_t* ovtab, int cap,
+                                   const ScoreArgs& a, const VertexCtx& v, uint64_t& best,
+                                   int tid, int nthreads) {
+  for (int i = tid; i < cap; i += nthreads) {
+    uint64_t s = table[i];
+    if (s != kEmpty) {
+      uint32_t id = (uint32_t)(s >> 32);
+      uint64_t key = ((s & 0xFFFFFFFFull) << 32) | (uint64_t)(0x7FFFFFFFu - id);
+      int64_t ov = 0;
+      if (OV) {
+        ov = ovtab[i];
+        ovtab[i] = 0;
+      }
+      if (key > best && (v.all_valid || merge_valid(a, v, id, ov))) best = key;
+      table[i] = kEmpty;
+    }
+  }
+}
+
+template <int THREADS>
+__device__ inline uint64_t block_max_u64(uint64_t x, uint64_t* red) {
+  constexpr int NW = THREADS / kWave;
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    uint64_t o = __shfl_xor(x, d, kWave);
+    x = o > x ? o : x;
+  }
+  int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  if (lane == 0) red[wid] = x;
+  __syncthreads();
+  uint64_t r = red[0];
+#pragma unroll
+  for (int k = 1; k < NW; ++k) r = red[k] > r ? red[k] : r;
+  __syncthreads();
+  return r;
+}
+
+template <int THREADS>
+__device__ inline void block_min_max_i64(int64_t& mn, int64_t& mx, int64_t* red) {
+  constexpr int NW = THREADS / kWave;
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    int64_t a = __shfl_xor(mn, d, kWave), b = __shfl_xor(mx, d, kWave);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  if (lane == 0) {
+    red[wid] = mn;
+    red[NW + wid] = mx;
+  }
+  __syncthreads();
+  mn = red[0];
+  mx = red[NW];
+#pragma unroll
+  for (int k = 1; k < NW; ++k) {
+    mn = red[k] < mn ? red[k] : mn;
+    mx = red[NW + k] > mx ? red[NW + k] : mx;
+  }
+  __syncthreads();
+}
+
+// One work-group per vertex, persistent over the bucket's work list.
+// MULTI = false: the whole neighbourhood fits (X_n <= SLOTS / 2).
+// OV = true: the distinct-axon bound can bind for these vertices, so the
+// table also accumulates, per neighbour m, the multiplicity of hyperedges in
+// which both n and m carry the destination flag (the shared inbound count).
+template <int THREADS, int SLOTS, bool MULTI, bool OV>
+__global__ __launch_bounds__(THREADS) void score_block_kernel(ScoreArgs a, int bucket,
+                                                             int64_t maxV, int64_t maxP) {
+  // Work inside a wave never depends on lane-specific control flow around a
+  // cross-lane operation: hyperedges are dealt to waves statically (no
+  // shuffled work counter), and per-wave bookkeeping in LDS is written by all
+  // lanes of the wave with the same value.  A cursor is only ever written and
+  // read by the wave that owns its hyperedge.
+  constexpr int NW = THREADS / kWave;
+  constexpr int MAXFILL = SLOTS / 2;
+  static_assert(MAXFILL + NW * kWave < SLOTS, "table must never fill up");
+  __shared__ uint64_t table[SLOTS];
+  __shared__ uint32_t ovtab[OV ? SLOTS : 1];
+  __shared__ uint64_t red[2 * NW];
+  __shared__ int32_t s_item;
+  __shared__ int32_t s_wfill[NW];  // fresh entries per wave in this pass
+  __shared__ int32_t s_wover[NW];  // wave saw the pass overflow
+
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  int32_t count = a.b.count[bucket];
+  if (count > maxV) {
+    if (tid == 0) atomicOr(a.err, kErrWorkCount);
+    count = (int32_t)maxV;
+  }
+  const int32_t* list = a.b.list + (int64_t)bucket * maxV;
+
+  for (int i = tid; i < SLOTS; i += THREADS) {
+    table[i] = kEmpty;
+    if (OV) ovtab[i] = 0;
+  }
+
+  while (true) {
+    __syncthreads();
+    if (tid == 0) s_item = atomicAdd(&a.work[bucket], 1);
+    __syncthreads();
+    const int32_t item = s_item;
+    if (item >= count) break;
+
+    VertexCtx v;
+    v.n = list[item];
+    v.beg = a.voff[v.n];
+    v.deg = a.voff[v.n + 1] - v.beg;
+    v.size_n = a.L.size[v.n];
+    v.syn_n = a.L.syn[v.n];
+    v.ax_n = a.L.ax[v.n];
+    v.G = a.gc[a.L.gid ? a.L.gid[v.n] : 0];
+    v.all_valid = (int64_t)v.size_n + v.G.max_size <= v.G.omega &&
+                  (int64_t)v.syn_n + v.G.max_syn <= v.G.phi &&
+                  (int64_t)v.ax_n + v.G.max_ax <= v.G.delta;
+    const int64_t x = a.xn[v.n];
+    const uint32_t n = (uint32_t)v.n;
+    uint64_t best = 0;
+
+    if (!MULTI) {
+      uint32_t cap = 64;
+      while (cap < 2 * (uint64_t)x && cap < (uint32_t)SLOTS) cap <<= 1;
+      const int shift = 32 - log2_pow2(cap);
+      for (int64_t j = wid; j < v.deg; j += NW) {
+        const uint32_t ent = a.vinc[v.beg + j];
+        const uint32_t e = ent & kIdMask;
+        const int64_t s0 = a.L.eoff[e], e0 = a.L.eoff[e + 1];
+        const uint32_t wt = (uint32_t)a.L.w[e];
+        const bool dn = OV && (ent & kDst);
+        const int32_t mu = dn ? a.L.mult[e] : 0;
+        for (int64_t p = s0 + lane; p < e0; p += kWave) {
+          const uint32_t pin = a.L.pins[p];
+          const uint32_t id = pin & kIdMask;
+          if (id != n) {
+            uint32_t h = table_add(table, cap - 1, shift, id, wt, a.err);
+            if (dn && (pin & kDst) && h != kNoSlot) atomicAdd(&ovtab[h & kIdMask], (uint32_t)mu);
+          }
+        }
+      }
+      __syncthreads();
+      drain_table<OV>(table, ovtab, (int)cap, a, v, best, tid, THREADS);
+    } else {
+      constexpr uint32_t cap = SLOTS;
+      const int shift = 32 - log2_pow2(cap);
+      int32_t* cur = a.cursor + v.beg;          // committed cursors
+      int32_t* tent = a.cursor + maxP + v.beg;  // cursors reached in this pass
+      // Hyperedge j belongs to wave j % NW; within the wave, bookkeeping
+      // loops spread a wave's hyperedges over its lanes.
+      const int64_t own_step = (int64_t)NW * kWave;
+      int64_t mn = INT64_MAX, mx = -1;
+      for (int64_t j = wid + (int64_t)NW * lane; j < v.deg; j += own_step) {
+        uint32_t e = a.vinc[v.beg + j] & kIdMask;
+        int64_t s0 = a.L.eoff[e], e0 = a.L.eoff[e + 1];
+        int64_t f = a.L.pins[s0] & kIdMask, l = a.L.pins[e0 - 1] & kIdMask;
+        mn = f < mn ? f : mn;
+        mx = l > mx ? l : mx;
+        cur[j] = 0;
+      }
+      block_min_max_i64<THREADS>(mn, mx, (int64_t*)red);
+      const int64_t hi_all = mx + 1;
+      int64_t lo = mn;
+      int64_t width = (hi_all - lo) * (int64_t)(MAXFILL / 2) / (x > 0 ? x : 1);
+      if (width < 1) width = 1;
+      int passes = 0;
+      while (lo < hi_all) {
+        const int64_t hi = lo + width < hi_all ? lo + width : hi_all;
+        __syncthreads();  // previous pass fully drained / cleared and flags read
+        if (++passes > kMaxPasses) {
+          if (tid == 0) atomicOr(a.err, kErrPassLimit);
+          break;
+        }
+        __hip_atomic_store(&s_wfill[wid], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __syncthreads();
+        int32_t wfill = 0;
+        bool wover = false;
+        for (int64_t j = wid; j < v.deg && !wover; j += NW) {
+          const uint32_t ent = a.vinc[v.beg + j];
+          const uint32_t e = ent & kIdMask;
+          const int64_t s0 = a.L.eoff[e], e0 = a.L.eoff[e + 1];
+          const uint32_t wt = (uint32_t)a.L.w[e];
+          const bool dn = OV && (ent & kDst);
+          const int32_t mu = dn ? a.L.mult[e] : 0;
+          int64_t c = s0 + cur[j];
+          while (true) {
+            int32_t total = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+              total += __hip_atomic_load(&s_wfill[w], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (total > MAXFILL) {
+              wover = true;
+              break;
+            }
+            const int64_t p = c + lane;
+            const uint32_t pin = p < e0 ? a.L.pins[p] : 0x7FFFFFFFu;
+            const uint32_t id = pin & kIdMask;
+            const bool in = p < e0 && (int64_t)id < hi;
+            bool fresh = false;
+            if (in && id != n) {
+              uint32_t h = table_add(table, cap - 1, shift, id, wt, a.err);
+              fresh = (h & 0x80000000u) != 0;
+              if (dn && (pin & kDst) && h != kNoSlot) atomicAdd(&ovtab[h & kIdMask], (uint32_t)mu);
+            }
+            const int cnt = __popcll(__ballot(in));
+            wfill += __popcll(__ballot(fresh));
+            __hip_atomic_store(&s_wfill[wid], wfill, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+            c += cnt;
+            if (cnt < kWave) break;
+          }
+          tent[j] = (int32_t)(c - s0);  // every lane stores the same value
+        }
+        s_wover[wid] = wover ? 1 : 0;  // every lane stores the same value
+        __syncthreads();
+        bool over = false;
+        int32_t fill = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          over |= s_wover[w] != 0;
+          fill += s_wfill[w];
+        }
+        if (over) {
+          for (int i = tid; i < (int)cap; i += THREADS) {
+            table[i] = kEmpty;
+            if (OV) ovtab[i] = 0;
+          }
+          width = width / 2 > 0 ? width / 2 : 1;
+          continue;  // the loop head synchronises before the next pass
+        }
+        drain_table<OV>(table, ovtab, (int)cap, a, v, best, tid, THREADS);
+        for (int64_t j = wid + (int64_t)NW * lane; j < v.deg; j += own_step) cur[j] = tent[j];
+        lo = hi;
+        if (fill < MAXFILL / 4 && width < hi_all) width *= 2;
+      }
+    }
+    best = block_max_u64<THREADS>(best, red);
+    if (tid == 0) {
+      if (best == 0) {
+        a.cand[v.n] = -1;
+        a.cscore[v.n] = 0;
+      } else {
+        a.cand[v.n] = (int32_t)(0x7FFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull));
+        a.cscore[v.n] = (int32_t)(best >> 32);
+      }
+    }
+  }
+}
+
+__global__ void no_candidate_kernel(const Dims* __restrict__ d, int32_t* __restrict__ cand,
+                                    int32_t* __restrict__ cscore, int32_t* __restrict__ work) {
+  int64_t V = d->V;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (i < kNumBuckets) work[i] = 0;
+  for (; i < V; i += stride) {
+    cand[i] = -1;
+    cscore[i] = 0;
+  }
+}
+
+template <typename K>
+int persistent_grid(K kernel, int threads) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return per_cu * device_cu_count();
+}
+
+}  // namespace
+
+void score_candidates(const ScoreArgs& a, int64_t maxV, int64_t maxP, hipStream_t s) {
+  no_candidate_kernel<<<grid_for(maxV, 256, 8192), 256, 0, s>>>(a.L.dims, a.cand, a.cscore,
+                                                               a.work);
+  static int g[kNumBuckets] = {0};
+  auto k0 = score_block_kernel<256, kSmallSlots, false, false>;
+  auto k1 = score_block_kernel<512, kBigSlots, false, false>;
+  auto k2 = score_block_kernel<512, kBigSlots, true, false>;
+  auto k3 = score_block_kernel<256, kSmallSlots, false, true>;
+  auto k4 = score_block_kernel<512, kBigSlotsOv, false, true>;
+  auto k5 = score_block_kernel<512, kBigSlotsOv, true, true>;
+  if (!g[0]) {
+    g[0] = persistent_grid(k0, 256);
+    g[1] = persistent_grid(k1, 512);
+    g[2] = persistent_grid(k2, 512);
+    g[3] = persistent_grid(k3, 256);
+    g[4] = persistent_grid(k4, 512);
+    g[5] = persistent_grid(k5, 512);
+  }
+  k0<<<g[0], 256, 0, s>>>(a, 0, maxV, maxP);
+  k1<<<g[1], 512, 0, s>>>(a, 1, maxV, maxP);
+  k2<<<g[2], 512, 0, s>>>(a, 2, maxV, maxP);
+  k3<<<g[3], 256, 0, s>>>(a, 3, maxV, maxP);
+  k4<<<g[4], 512, 0, s>>>(a, 4, maxV, maxP);
+  k5<<<g[5], 512, 0, s>>>(a, 5, maxV, maxP);
+}
+
+}  // namespace hg

@@ -1,0 +1,154 @@
+// S0: incidence lists I(n) (paper, Section 2: in(n) U out(n)) by counting
+// and atomic scatter; order inside a list is not fixed and does not matter
+// to any result (all later uses are integer sums or set tests).
+// S1: expansion sizes X_n = sum over I(n) of |e|, level maxima of the
+// super-node state, and the work lists of the scoring kernels.
+// Level-0 state (Section 2 model; Section 3 constraint quantities).
+#include "hg_internal.h"
+
+namespace hg {
+
+namespace {
+
+__global__ void count_pins_kernel(const Dims* __restrict__ d, const uint32_t* __restrict__ pins,
+                                  int32_t* __restrict__ vcount) {
+  int64_t P = d->P;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < P; i += stride) atomicAdd(&vcount[pins[i] & kIdMask], 1);
+}
+
+// One wave per hyperedge: every pin gets a slot in its vertex's list.
+__global__ void scatter_incidence_kernel(const Dims* __restrict__ d,
+                                         const int64_t* __restrict__ eoff,
+                                         const uint32_t* __restrict__ pins,
+                                         const int64_t* __restrict__ voff,
+                                         int32_t* __restrict__ cursor,
+                                         uint32_t* __restrict__ vinc) {
+  int64_t E = d->E;
+  int lane = threadIdx.x & (kWave - 1);
+  int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t e = wave; e < E; e += nwaves) {
+    int64_t s = eoff[e], t = eoff[e + 1];
+    for (int64_t k = s + lane; k < t; k += kWave) {
+      uint32_t p = pins[k];
+      uint32_t v = p & kIdMask;
+      int32_t pos = atomicAdd(&cursor[v], 1);
+      vinc[voff[v] + pos] = (uint32_t)e | (p & kDst);
+    }
+  }
+}
+
+__global__ void level0_flags_kernel(const Dims* __restrict__ d, const uint32_t* __restrict__ pins,
+                                    int32_t* __restrict__ syn) {
+  int64_t P = d->P;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < P; i += stride) {
+    uint32_t p = pins[i];
+    if (p & kDst) atomicAdd(&syn[p & kIdMask], 1);
+  }
+}
+
+__global__ void level0_finish_kernel(const Dims* __restrict__ d, int32_t* __restrict__ size,
+                                     const int32_t* __restrict__ syn, int32_t* __restrict__ ax,
+                                     int32_t* __restrict__ mult) {
+  int64_t V = d->V, E = d->E;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = i; v < V; v += stride) {
+    size[v] = 1;
+    ax[v] = syn[v];
+  }
+  for (int64_t e = i; e < E; e += stride) mult[e] = 1;
+}
+
+__global__ void reset_maxima_kernel(GraphConst* gc, int32_t n_graphs, int32_t* bcount) {
+  int i = threadIdx.x;
+  for (int g = i; g < n_graphs; g += blockDim.x) {
+    gc[g].max_size = 0;
+    gc[g].max_syn = 0;
+    gc[g].max_ax = 0;
+  }
+  if (i < kNumBuckets) bcount[i] = 0;
+}
+
+// Thread per vertex.  Bucket by the expansion X_n: single pass in the small
+// table (X_n <= half of it), single pass in the big table, or multipass; +3
+// when the distinct-axon bound can bind for n (ax_n + level max > Delta), so
+// the shared inbound count must be accumulated.  Vertices with X_n = 0 have
+// no neighbour and are in no list.
+__global__ void expansion_kernel(LevelView L, const int64_t* __restrict__ voff,
+                                 const uint32_t* __restrict__ vinc, int64_t* __restrict__ xn,
+                                 GraphConst* __restrict__ gc, Buckets b, int64_t maxV) {
+  int64_t V = L.dims->V;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = i; v < V; v += stride) {
+    int64_t s = voff[v], t = voff[v + 1];
+    int64_t x = 0;
+    for (int64_t j = s; j < t; ++j) {
+      uint32_t a = vinc[j] & kIdMask;
+      x += L.eoff[a + 1] - L.eoff[a] - 1;  // neighbours visited through a (n excluded)
+    }
+    xn[v] = x;
+    int g = L.gid ? L.gid[v] : 0;
+    atomicMax(&gc[g].max_size, L.size[v]);
+    atomicMax(&gc[g].max_syn, L.syn[v]);
+    atomicMax(&gc[g].max_ax, L.ax[v]);
+  }
+}
+
+__global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
+                              const GraphConst* __restrict__ gc, Buckets b, int64_t maxV) {
+  int64_t V = L.dims->V;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = i; v < V; v += stride) {
+    int64_t x = xn[v];
+    if (x <= 0) continue;
+    const GraphConst G = gc[L.gid ? L.gid[v] : 0];
+    const bool ov = (int64_t)L.ax[v] + G.max_ax > G.delta;
+    int bk;
+    if (x <= kSmallSlots / 2) bk = 0;
+    else if (x <= (ov ? kBigSlotsOv : kBigSlots) / 2) bk = 1;
+    else bk = 2;
+    if (ov) bk += 3;
+    int pos = atomicAdd(&b.count[bk], 1);
+    b.list[(int64_t)bk * maxV + pos] = (int32_t)v;
+  }
+}
+
+}  // namespace
+
+void build_incidence(const LevelView& L, int64_t maxV, int64_t maxE, int64_t maxP,
+                     int32_t* vcount, int64_t* voff, uint32_t* vinc, int64_t* partials,
+                     hipStream_t s) {
+  fill_i32(vcount, 0, maxV, s);
+  count_pins_kernel<<<grid_for(maxP, 256 * 8, 8192), 256, 0, s>>>(L.dims, L.pins, vcount);
+  exclusive_scan_i32(vcount, voff, &L.dims->V, maxV, partials, s);
+  fill_i32(vcount, 0, maxV, s);
+  scatter_incidence_kernel<<<grid_for(maxE, 4, 16384), 256, 0, s>>>(L.dims, L.eoff, L.pins,
+                                                                     voff, vcount, vinc);
+}
+
+void level0_state(const Dims* d, const int64_t* eoff, const uint32_t* pins, int64_t maxV,
+                  int64_t maxE, int32_t* size, int32_t* syn, int32_t* ax, int32_t* mult,
+                  hipStream_t s) {
+  (void)eoff;
+  fill_i32(syn, 0, maxV, s);
+  level0_flags_kernel<<<4096, 256, 0, s>>>(d, pins, syn);
+  int64_t m = maxV > maxE ? maxV : maxE;
+  level0_finish_kernel<<<grid_for(m, 256, 8192), 256, 0, s>>>(d, size, syn, ax, mult);
+}
+
+void expansion_and_buckets(const LevelView& L, const int64_t* voff, const uint32_t* vinc,
+                           int64_t maxV, int64_t* xn, GraphConst* gc, int32_t n_graphs,
+                           Buckets b, hipStream_t s) {
+  reset_maxima_kernel<<<1, 256, 0, s>>>(gc, n_graphs, b.count);
+  expansion_kernel<<<grid_for(maxV, 256, 16384), 256, 0, s>>>(L, voff, vinc, xn, gc, b, maxV);
+  bucket_kernel<<<grid_for(maxV, 256, 16384), 256, 0, s>>>(L, xn, gc, b, maxV);
+}
+
+}  // namespace hg

@@ -1,0 +1,250 @@
+"""Python binding of the C ABI in ``include/hg.h`` (argument marshalling only).
+
+Device memory and streams come from PyTorch; every step of the coarsening
+level and of the connectivity evaluation runs in the HIP kernels of
+``libhgcoarsen.so``.  There is no fallback: if the library is missing or no
+GPU is present, the calls raise.
+
+Pins travel as int32 tensors holding the uint32 bit pattern
+``vertex_id | flag << 31``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhgcoarsen.so")
+
+HG_OK = 0
+STATUS = {0: "HG_OK", 1: "HG_ERR_INVALID_ARG", 2: "HG_ERR_OVERFLOW", 3: "HG_ERR_CAPACITY",
+          4: "HG_ERR_NO_MEMORY", 5: "HG_ERR_HIP", 6: "HG_ERR_UNIMPLEMENTED",
+          7: "HG_ERR_INVALID_LEVEL", 8: "HG_ERR_INTERNAL"}
+
+_P = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+# Every symbol declared in include/hg.h.
+EXPORTED = ("hg_create", "hg_destroy", "hg_set_stream", "hg_last_error", "hg_sync",
+            "hg_scratch_bytes", "hg_init_state", "hg_coarsen_level", "hg_contract",
+            "hg_connectivity", "hg_validate_level")
+
+
+class HgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Limits(ctypes.Structure):
+    _fields_ = [("max_neurons", _i32), ("max_synapses", _i32), ("max_axons", _i32)]
+
+
+class _Level(ctypes.Structure):
+    _fields_ = [("n_vertices", _i32), ("n_edges", _i32), ("n_pins", _i64),
+                ("edge_offsets", _P), ("pins", _P), ("edge_weight", _P), ("edge_mult", _P),
+                ("v_size", _P), ("v_syn", _P), ("v_axons", _P)]
+
+
+class _LevelOut(ctypes.Structure):
+    _fields_ = [("cap_vertices", _i32), ("cap_edges", _i32), ("cap_pins", _i64),
+                ("edge_offsets", _P), ("pins", _P), ("edge_weight", _P), ("edge_mult", _P),
+                ("v_size", _P), ("v_syn", _P), ("v_axons", _P), ("sizes", _P)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhgcoarsen.so and declare the ABI.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing; build it with paper_2609_07577_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    lib.hg_create.argtypes = [ctypes.c_int, _P, ctypes.POINTER(_P)]
+    lib.hg_destroy.argtypes = [_P]
+    lib.hg_set_stream.argtypes = [_P, _P]
+    lib.hg_last_error.argtypes = [_P]
+    lib.hg_last_error.restype = ctypes.c_char_p
+    lib.hg_sync.argtypes = [_P]
+    lib.hg_scratch_bytes.argtypes = [_P]
+    lib.hg_scratch_bytes.restype = _i64
+    lib.hg_init_state.argtypes = [_P, _i32, _i32, _i64, _P, _P, _P, _P, _P, _P]
+    lib.hg_coarsen_level.argtypes = [_P, ctypes.POINTER(_Level), ctypes.POINTER(Limits), _P, _P,
+                                     _P, _P, _P, _P]
+    lib.hg_contract.argtypes = [_P, ctypes.POINTER(_Level), _P, _P, ctypes.POINTER(_LevelOut)]
+    lib.hg_connectivity.argtypes = [_P, ctypes.POINTER(_Level), _P, _P]
+    lib.hg_validate_level.argtypes = [_P, ctypes.POINTER(_Level)]
+    for name in EXPORTED:
+        getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous()
+    return t.data_ptr()
+
+
+@dataclass
+class DeviceLevel:
+    """A level resident in device memory (torch tensors)."""
+    V: int
+    E: int
+    P: int
+    eoff: torch.Tensor   # int64 [E+1]
+    pins: torch.Tensor   # int32 [P] (uint32 bit pattern)
+    w: torch.Tensor      # int32 [E]
+    mult: torch.Tensor   # int32 [E]
+    size: torch.Tensor   # int32 [V]
+    syn: torch.Tensor    # int32 [V]
+    ax: torch.Tensor     # int32 [V]
+
+    def c_struct(self) -> _Level:
+        return _Level(self.V, self.E, self.P, _ptr(self.eoff), _ptr(self.pins), _ptr(self.w),
+                      _ptr(self.mult), _ptr(self.size), _ptr(self.syn), _ptr(self.ax))
+
+    def to_host(self) -> dict:
+        return dict(V=self.V, eoff=self.eoff.cpu().numpy(),
+                    pins=self.pins.cpu().numpy().view(np.uint32), w=self.w.cpu().numpy(),
+                    mult=self.mult.cpu().numpy(), size=self.size.cpu().numpy(),
+                    syn=self.syn.cpu().numpy(), ax=self.ax.cpu().numpy())
+
+
+class Context:
+    """One hg_ctx bound to a device and a HIP stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the coarsening library runs on the GPU only")
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _P()
+        rc = self.lib.hg_create(device, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != HG_OK:
+            raise HgError(rc, "hg_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != HG_OK:
+            raise HgError(rc, self.lib.hg_last_error(self.h).decode())
+
+    def sync(self):
+        self._check(self.lib.hg_sync(self.h))
+
+    def scratch_bytes(self) -> int:
+        return int(self.lib.hg_scratch_bytes(self.h))
+
+    # -- level construction -------------------------------------------------
+    def upload(self, g) -> DeviceLevel:
+        """Level 0 from a generated SNN (host arrays): copy and set the state."""
+        dev = self.device
+        V, E, P = g.n_vertices, g.n_edges, g.n_pins
+        with torch.cuda.stream(self.stream):
+            eoff = torch.from_numpy(np.ascontiguousarray(g.eoff, dtype=np.int64)).to(dev)
+            pins = torch.from_numpy(
+                np.ascontiguousarray(g.pins, dtype=np.uint32).view(np.int32)).to(dev)
+            w = torch.from_numpy(np.ascontiguousarray(g.weight, dtype=np.int32)).to(dev)
+            mult = torch.empty(max(E, 1), dtype=torch.int32, device=dev)[:E]
+            size = torch.empty(max(V, 1), dtype=torch.int32, device=dev)[:V]
+            syn = torch.empty_like(size)
+            ax = torch.empty_like(size)
+            self._check(self.lib.hg_init_state(self.h, V, E, P, _ptr(eoff), _ptr(pins),
+                                               _ptr(size), _ptr(syn), _ptr(ax), _ptr(mult)))
+        return DeviceLevel(V, E, P, eoff, pins, w, mult, size, syn, ax)
+
+    def level_from_host(self, d: dict) -> DeviceLevel:
+        """Any level from host arrays (keys as in DeviceLevel.to_host)."""
+        dev = self.device
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).astype(dt, copy=False)).to(dev)
+        with torch.cuda.stream(self.stream):
+            eoff = t(d["eoff"], np.int64)
+            pins = torch.from_numpy(
+                np.ascontiguousarray(d["pins"], dtype=np.uint32).view(np.int32)).to(dev)
+            E = int(eoff.shape[0] - 1)
+            return DeviceLevel(int(d["V"]), E, int(pins.shape[0]), eoff, pins,
+                               t(d["w"], np.int32), t(d["mult"], np.int32),
+                               t(d["size"], np.int32), t(d["syn"], np.int32),
+                               t(d["ax"], np.int32))
+
+    # -- the three operations ---------------------------------------------
+    def coarsen_level(self, L: DeviceLevel, limits, want_candidates: bool = True) -> dict:
+        dev = self.device
+        V = L.V
+        i32 = lambda n: torch.empty(max(n, 1), dtype=torch.int32, device=dev)[:n]
+        lim = Limits(limits.max_neurons, limits.max_synapses, limits.max_axons)
+        lv = L.c_struct()
+        with torch.cuda.stream(self.stream):
+            cand = i32(V) if want_candidates else None
+            cscore = i32(V) if want_candidates else None
+            match, vmap = i32(V), i32(V)
+            scal = torch.zeros(2, dtype=torch.int32, device=dev)
+            self._check(self.lib.hg_coarsen_level(self.h, ctypes.byref(lv), ctypes.byref(lim),
+                                                  _ptr(cand), _ptr(cscore), _ptr(match),
+                                                  _ptr(vmap), scal.data_ptr(),
+                                                  scal.data_ptr() + 4))
+        return dict(cand=cand, cscore=cscore, match=match, vmap=vmap, n_coarse=scal[0:1],
+                    any_candidate=scal[1:2], scalars=scal)
+
+    def contract(self, L: DeviceLevel, vmap: torch.Tensor, n_coarse: torch.Tensor,
+                 trim: bool = True):
+        """Coarse level for ``vmap``.  With ``trim`` the sizes are read back
+        (one stream synchronisation) and the tensors are views of that size."""
+        dev = self.device
+        V, E, P = L.V, L.E, L.P
+        assert vmap.dtype == torch.int32 and n_coarse.dtype == torch.int32
+        with torch.cuda.stream(self.stream):
+            eoff = torch.empty(E + 1, dtype=torch.int64, device=dev)
+            pins = torch.empty(max(P, 1), dtype=torch.int32, device=dev)
+            w = torch.empty(max(E, 1), dtype=torch.int32, device=dev)
+            mult = torch.empty(max(E, 1), dtype=torch.int32, device=dev)
+            size = torch.empty(max(V, 1), dtype=torch.int32, device=dev)
+            syn = torch.empty_like(size)
+            ax = torch.empty_like(size)
+            sizes = torch.zeros(3, dtype=torch.int64, device=dev)
+            out = _LevelOut(V, E, P, _ptr(eoff), _ptr(pins), _ptr(w), _ptr(mult), _ptr(size),
+                            _ptr(syn), _ptr(ax), _ptr(sizes))
+            lv = L.c_struct()
+            self._check(self.lib.hg_contract(self.h, ctypes.byref(lv), _ptr(vmap),
+                                             _ptr(n_coarse), ctypes.byref(out)))
+        if not trim:
+            return eoff, pins, w, mult, size, syn, ax, sizes
+        self.sync()
+        V2, E2, P2 = (int(x) for x in sizes.cpu().tolist())
+        return DeviceLevel(V2, E2, P2, eoff[: E2 + 1], pins[:P2], w[:E2], mult[:E2], size[:V2],
+                           syn[:V2], ax[:V2])
+
+    def connectivity(self, L: DeviceLevel, part: torch.Tensor) -> torch.Tensor:
+        """Eq. (1) of the level under ``part``; returns a device int64 scalar."""
+        lv = L.c_struct()
+        assert part.dtype == torch.int32
+        with torch.cuda.stream(self.stream):
+            conn = torch.zeros(1, dtype=torch.int64, device=self.device)
+            self._check(self.lib.hg_connectivity(self.h, ctypes.byref(lv), _ptr(part),
+                                                 _ptr(conn)))
+        return conn
+
+    def validate(self, L: DeviceLevel):
+        lv = L.c_struct()
+        self._check(self.lib.hg_validate_level(self.h, ctypes.byref(lv)))

@@ -1,0 +1,231 @@
+"""GPU library vs CPU oracle, element by element (bit-exact integer results).
+
+Every call goes through the C ABI (ctypes binding); the oracle is the plain
+C++ reference under oracle/.  Inputs come from the seeded generator only.
+"""
+import numpy as np
+import pytest
+
+import hgcheck
+import oracle
+from paper_2609_07577_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_07577_amd import hg
+    oracle.build(force=False)
+    return hg.Context(0)
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def assert_level_equal(gpu_level, olev, where=""):
+    g = gpu_level.to_host()
+    assert g["V"] == olev.V, where
+    np.testing.assert_array_equal(g["eoff"], olev.eoff, err_msg=f"eoff {where}")
+    np.testing.assert_array_equal(g["pins"], olev.pins, err_msg=f"pins {where}")
+    np.testing.assert_array_equal(g["w"], olev.w, err_msg=f"w {where}")
+    np.testing.assert_array_equal(g["mult"], olev.mult, err_msg=f"mult {where}")
+    np.testing.assert_array_equal(g["size"], olev.size, err_msg=f"size {where}")
+    np.testing.assert_array_equal(g["syn"], olev.syn, err_msg=f"syn {where}")
+    np.testing.assert_array_equal(g["ax"], olev.ax, err_msg=f"ax {where}")
+
+
+def run_hierarchy_parity(ctx, g, lim, max_levels=64, check_conn=True, verbose=False):
+    """Run GPU and oracle level by level from the same level 0; compare all.
+    Each level's outputs are checked before the next GPU step consumes them."""
+    from paper_2609_07577_amd import hg  # noqa: F401
+    oh = oracle.hierarchy(g, lim, max_levels=max_levels)
+    if verbose:
+        print(f"  {g.name}: V={g.n_vertices} P={g.n_pins}, oracle levels={len(oh.levels)}",
+              flush=True)
+    L = ctx.upload(g)
+    ctx.sync()
+    assert_level_equal(L, oh.levels[0].level, "level 0 state")
+    for li, r in enumerate(oh.levels):
+        where = f"{g.name} level {li}"
+        if verbose:
+            print(f"  {where}: coarsen V={L.V} E={L.E} P={L.P}", flush=True)
+        out = ctx.coarsen_level(L, lim)
+        ctx.sync()
+        np.testing.assert_array_equal(_np(out["cand"]), r.cand, err_msg=f"cand {where}")
+        np.testing.assert_array_equal(_np(out["cscore"]), r.cscore, err_msg=f"cscore {where}")
+        np.testing.assert_array_equal(_np(out["match"]), r.match, err_msg=f"match {where}")
+        np.testing.assert_array_equal(_np(out["vmap"]), r.vmap, err_msg=f"vmap {where}")
+        assert int(out["n_coarse"].item()) == r.n_coarse, where
+        assert bool(out["any_candidate"].item()) == r.any_candidate, where
+        hgcheck.check_matching(L.V, r.cand, r.cscore, _np(out["match"]))
+        if check_conn:
+            if verbose:
+                print(f"  {where}: connectivity", flush=True)
+            conn = int(ctx.connectivity(L, out["vmap"]).item())
+            ctx.sync()
+            assert conn == oracle.connectivity(r.level.eoff, r.level.pins, r.level.w, r.vmap), where
+        if not r.any_candidate:
+            break
+        if verbose:
+            print(f"  {where}: contract", flush=True)
+        C = ctx.contract(L, out["vmap"], out["n_coarse"])
+        assert_level_equal(C, r.coarse, f"coarse of {where}")
+        L = C
+    return oh
+
+
+# --------------------------------------------------------------------------
+def test_hand_cases(ctx):
+    cases = hgcheck.load_hand_cases()
+    for name in ["H1_path_increasing", "H2_path_ties", "H3_neuron_limit", "H4_axon_overlap"]:
+        case = cases[name]
+        lim = hgcheck.limits_of(case["limits"])
+        g = hgcheck.level_from_case(case)
+        L = ctx.upload(g)
+        out = ctx.coarsen_level(L, lim)
+        assert _np(out["cand"]).tolist() == case["cand"], name
+        assert _np(out["match"]).tolist() == case["match"], name
+        run_hierarchy_parity(ctx, g, lim)
+
+
+def test_hand_case_destination_flags(ctx):
+    import torch as T
+    case = hgcheck.load_hand_cases()["H5_destination_flags"]
+    g = hgcheck.level_from_case(case)
+    L = ctx.upload(g)
+    vmap = T.tensor(case["vmap"], dtype=T.int32, device="cuda")
+    nc = T.tensor([case["n_coarse"]], dtype=T.int32, device="cuda")
+    C = ctx.contract(L, vmap, nc)
+    assert hgcheck.edge_lists(_np(C.eoff), _np(C.pins).view(np.uint32)) == case["coarse_edges"]
+    assert _np(C.ax).tolist() == case["coarse_ax"]
+    C2 = ctx.contract(C, T.zeros(2, dtype=T.int32, device="cuda"),
+                      T.tensor([1], dtype=T.int32, device="cuda"))
+    assert _np(C2.ax).tolist() == [case["merged_ax_after_second_contraction"]]
+    assert C2.E == 0
+
+
+def test_connectivity_hand_case(ctx):
+    import torch as T
+    case = hgcheck.load_hand_cases()["H6_connectivity"]
+    g = hgcheck.level_from_case(case)
+    L = ctx.upload(g)
+    part = T.tensor(case["part"], dtype=T.int32, device="cuda")
+    assert int(ctx.connectivity(L, part).item()) == case["conn"]
+
+
+@pytest.mark.parametrize("block", range(4))
+def test_tiny_random_graphs(ctx, block):
+    rng = np.random.default_rng(77 + block)
+    for i in range(40):
+        n = int(rng.integers(1, 40))
+        g = synth.tiny_random(int(rng.integers(0, 1 << 30)), n, p_axon=float(rng.uniform(0.3, 1)),
+                              max_fan=int(rng.integers(1, 8)), w_max=int(rng.integers(1, 5)))
+        kind = rng.integers(0, 3)
+        lim = hgcheck.BIG if kind == 0 else synth.Limits(int(rng.integers(2, 8)),
+                                                         int(rng.integers(1, 20)),
+                                                         int(rng.integers(1, 12)))
+        run_hierarchy_parity(ctx, g, lim)
+
+
+def test_layered_full_hierarchy(ctx):
+    g = synth.layered(1)
+    oh = run_hierarchy_parity(ctx, g, synth.LIMITS["layered"], verbose=True)
+    assert oh.n_levels >= 8
+
+
+def test_conv_small_hierarchy(ctx):
+    g = synth.conv(2, layers=4, height=12, width=12, channels=8)
+    run_hierarchy_parity(ctx, g, synth.Limits(256, 8192, 1024), verbose=True)
+
+
+def test_uniform_tight_axon_limit(ctx):
+    # Delta binds early, so the overlap test on candidate merges is exercised
+    g = synth.uniform(5, 3000, 4, 40)
+    run_hierarchy_parity(ctx, g, synth.Limits(64, 100000, 60))
+
+
+def test_powerlaw_multipass(ctx):
+    # neighbourhoods well above one table's capacity -> id-range passes
+    g = synth.powerlaw(3, n=12000, dmin=20, dmax=3000)
+    L0 = oracle.level0(g)
+    lens = np.diff(L0.eoff)
+    deg_in = np.bincount((L0.pins & 0x7FFFFFFF).astype(np.int64), minlength=g.n_vertices)
+    # X_n = sum over incident hyperedges of (|e| - 1)
+    edge_of_pin = np.repeat(np.arange(L0.E), lens)
+    xn = np.bincount((L0.pins & 0x7FFFFFFF).astype(np.int64), weights=(lens - 1)[edge_of_pin],
+                     minlength=g.n_vertices)
+    assert (xn > 8192).sum() > 1000 and deg_in.min() >= 0
+    run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=3, verbose=True)
+
+
+def test_huge_hyperedges_contract_and_connectivity(ctx):
+    import torch as T
+    rng = np.random.default_rng(3)
+    n = 60000
+    axons = [(0, sorted(rng.choice(np.arange(1, n), 20000, replace=False).tolist()), 5),
+             (1, sorted(rng.choice(np.arange(2, n), 17000, replace=False).tolist()), 3)]
+    for s in range(2, 400):
+        k = int(rng.integers(1, 30))
+        tg = sorted(set(rng.choice(np.arange(n), k, replace=False).tolist()) - {s})
+        axons.append((s, tg, int(rng.integers(1, 9))))
+    g = synth.from_axons(n, axons)
+    L = ctx.upload(g)
+    OL = oracle.level0(g)
+    for k in (7, 3000, 45000):
+        part = rng.integers(0, k, n).astype(np.int32)
+        uniq = np.unique(part)
+        vmap = np.searchsorted(uniq, part).astype(np.int32)
+        tv = T.from_numpy(vmap).cuda()
+        assert int(ctx.connectivity(L, tv).item()) == oracle.connectivity(OL.eoff, OL.pins, OL.w, vmap)
+        C = ctx.contract(L, tv, T.tensor([len(uniq)], dtype=T.int32, device="cuda"))
+        assert_level_equal(C, oracle.contract(OL, vmap, len(uniq)), f"huge k={k}")
+
+
+def test_contract_general_partitions(ctx):
+    import torch as T
+    rng = np.random.default_rng(11)
+    for seed in range(6):
+        g = synth.uniform(seed, 5000, 1, 60)
+        L = ctx.upload(g)
+        OL = oracle.level0(g)
+        for k in (1, 2, 50, 4999):
+            part = rng.integers(0, k, g.n_vertices)
+            uniq = np.unique(part)
+            vmap = np.searchsorted(uniq, part).astype(np.int32)
+            C = ctx.contract(L, T.from_numpy(vmap).cuda(),
+                             T.tensor([len(uniq)], dtype=T.int32, device="cuda"))
+            assert_level_equal(C, oracle.contract(OL, vmap, len(uniq)), f"seed {seed} k {k}")
+
+
+def test_deterministic_repeat(ctx):
+    g = synth.powerlaw(9, n=8000, dmin=20, dmax=2000)
+    L = ctx.upload(g)
+    lim = synth.LIMITS["powerlaw"]
+    a = ctx.coarsen_level(L, lim)
+    b = ctx.coarsen_level(L, lim)
+    for k in ("cand", "cscore", "match", "vmap"):
+        assert torch.equal(a[k], b[k]), k
+    C1 = ctx.contract(L, a["vmap"], a["n_coarse"])
+    C2 = ctx.contract(L, b["vmap"], b["n_coarse"])
+    assert torch.equal(C1.pins, C2.pins) and torch.equal(C1.eoff, C2.eoff)
+
+
+def test_empty_and_degenerate(ctx):
+    # no hyperedges at all
+    g = synth.from_axons(5, [])
+    run_hierarchy_parity(ctx, g, hgcheck.BIG)
+    # only single-pin hyperedges (axons without targets)
+    g = synth.from_axons(4, [(0, [], 3), (2, [], 1)])
+    run_hierarchy_parity(ctx, g, hgcheck.BIG)
+    # one vertex
+    g = synth.from_axons(1, [(0, [], 1)])
+    run_hierarchy_parity(ctx, g, hgcheck.BIG)
+    # limits that forbid every merge
+    g = synth.uniform(1, 200, 2, 6)
+    run_hierarchy_parity(ctx, g, synth.Limits(1, 1000, 1000))
