@@ -112,6 +112,20 @@ int hg_sync(hg_ctx* ctx);
 /* Bytes currently held by the scratch arena. */
 int64_t hg_scratch_bytes(hg_ctx* ctx);
 
+/* Phase timing.  When enabled, the calls record HIP events on the context
+ * stream around their phases; hg_phase_times synchronises the stream and
+ * writes the device time in milliseconds of each phase of the most recent
+ * calls since the previous query (0 when a phase did not run):
+ *   ms[0] incidence lists and expansion sizes (hg_coarsen_level)
+ *   ms[1] scores and candidates, Eq. 12 (hg_coarsen_level)
+ *   ms[2] matching and coarse vertex map, Eq. 13 (hg_coarsen_level)
+ *   ms[3] contraction (hg_contract)
+ *   ms[4] connectivity, Eq. 1 (hg_connectivity)
+ * `ms` has HG_NUM_PHASES entries. */
+#define HG_NUM_PHASES 5
+int hg_enable_timing(hg_ctx* ctx, int on);
+int hg_phase_times(hg_ctx* ctx, float* ms);
+
 /*
  * Level-0 state (Section 2 model; Section 3 constraint quantities):
  * v_size = 1, v_syn = v_axons = number of hyperedges in which the vertex has

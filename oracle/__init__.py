@@ -57,7 +57,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         lib.oracle_level0_state.argtypes = [_i32, _i32, _P, _P, _P, _P, _P, _P, _P]
         lib.oracle_candidates.argtypes = [_i32, _i32, _P, _P, _P, _P, _P, _P, _P,
-                                          _i32, _i32, _i32, _i32, _P, _P, _P, _i32]
+                                          _i32, _i32, _i32, _i32, _P, _P, _P, _i32, _P]
         lib.oracle_match.argtypes = [_i32, _P, _P, _P]
         lib.oracle_vmap_from_match.argtypes = [_i32, _P, _P]
         lib.oracle_vmap_from_match.restype = _i32
@@ -122,8 +122,10 @@ def level0(g) -> OLevel:
                   syn, soff, sids)
 
 
-def candidates(L: OLevel, limits, query=None, nthreads: int = 0):
-    """cand[n], cscore[n] per Eq. (12) for all vertices, or for ``query``."""
+def candidates(L: OLevel, limits, query=None, nthreads: int = 0, seconds=None):
+    """cand[n], cscore[n] per Eq. (12) for all vertices, or for ``query``.
+    ``seconds``: optional float64 array of 2 receiving the wall time of the
+    incidence build and of the per-vertex loop."""
     lib = _load()
     if query is None:
         nq, qp = L.V, None
@@ -135,7 +137,7 @@ def candidates(L: OLevel, limits, query=None, nthreads: int = 0):
     lib.oracle_candidates(L.V, L.E, _ptr(L.eoff), _ptr(L.pins), _ptr(L.w), _ptr(L.size),
                           _ptr(L.syn), _ptr(L.soff), _ptr(L.sids), limits.max_neurons,
                           limits.max_synapses, limits.max_axons, nq, qp, _ptr(cand),
-                          _ptr(cscore), nthreads)
+                          _ptr(cscore), nthreads, None if seconds is None else _ptr(seconds))
     return cand, cscore
 
 

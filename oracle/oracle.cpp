@@ -39,6 +39,7 @@
 // grouping, explicit sets for inbound axons.  The only parallelism is an
 // OpenMP loop over vertices in the candidate step.
 #include <algorithm>
+#include <chrono>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -156,15 +157,18 @@ int oracle_level0_state(int32_t V, int32_t E, const int64_t* eoff, const uint32_
 //                 tie (R1); -1 when no neighbour is valid.
 // Computes cand/cscore for the `nq` vertices listed in `query` (all vertices
 // when query is null; then nq must equal V).  cscore is score(n, cand(n)), or
-// 0 when there is no candidate.
+// 0 when there is no candidate.  `seconds` (may be null) receives the wall
+// time of building the incidence lists and of the per-vertex loop.
 int oracle_candidates(int32_t V, int32_t E, const int64_t* eoff, const uint32_t* pins,
                       const int32_t* w, const int32_t* size, const int32_t* syn,
                       const int64_t* soff, const int32_t* sids, int32_t omega,
                       int32_t phi, int32_t delta, int32_t nq, const int32_t* query,
-                      int32_t* cand, int32_t* cscore, int32_t nthreads) {
+                      int32_t* cand, int32_t* cscore, int32_t nthreads, double* seconds) {
   Level L{V, E, eoff, pins, w, size, syn, soff, sids};
   Limits lim{omega, phi, delta};
+  auto t0 = std::chrono::steady_clock::now();
   Incidence inc = build_incidence(V, E, eoff, pins);
+  auto t1 = std::chrono::steady_clock::now();
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -201,6 +205,11 @@ int oracle_candidates(int32_t V, int32_t E, const int64_t* eoff, const uint32_t*
       cand[qi] = best;
       cscore[qi] = best < 0 ? 0 : (int32_t)best_s;
     }
+  }
+  auto t2 = std::chrono::steady_clock::now();
+  if (seconds) {
+    seconds[0] = std::chrono::duration<double>(t1 - t0).count();
+    seconds[1] = std::chrono::duration<double>(t2 - t1).count();
   }
   return 0;
 }

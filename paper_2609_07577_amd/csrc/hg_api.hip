@@ -15,6 +15,9 @@ struct hg_ctx {
   char* arena = nullptr;
   size_t arena_bytes = 0;
   int32_t* dev_err = nullptr;  // device error word (bounds reached by kernels)
+  bool timing = false;
+  hipEvent_t ev[2 * HG_NUM_PHASES] = {};
+  bool recorded[HG_NUM_PHASES] = {};
 };
 
 namespace hg {
@@ -76,6 +79,12 @@ int ensure_arena(hg_ctx* c, size_t bytes) {
   }
   c->arena_bytes = want;
   return HG_OK;
+}
+
+void mark(hg_ctx* c, int phase, int end) {
+  if (!c->timing) return;
+  (void)hipEventRecord(c->ev[2 * phase + end], c->stream);
+  if (end) c->recorded[phase] = true;
 }
 
 int launch_status(hg_ctx* c) {
@@ -270,6 +279,8 @@ int hg_create(int device, void* hip_stream, hg_ctx** out) {
 int hg_destroy(hg_ctx* c) {
   if (!c) return HG_OK;
   (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
   if (c->arena) (void)hipFree(c->arena);
   if (c->dev_err) (void)hipFree(c->dev_err);
   delete c;
@@ -306,6 +317,34 @@ int hg_sync(hg_ctx* c) {
 }
 
 int64_t hg_scratch_bytes(hg_ctx* c) { return c ? (int64_t)c->arena_bytes : 0; }
+
+int hg_enable_timing(hg_ctx* c, int on) {
+  if (!c) return HG_ERR_INVALID_ARG;
+  if (on && !c->ev[0]) {
+    for (auto& e : c->ev) {
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return hip_fail(c, r, "hipEventCreate");
+    }
+  }
+  c->timing = on != 0;
+  for (bool& r : c->recorded) r = false;
+  return HG_OK;
+}
+
+int hg_phase_times(hg_ctx* c, float* ms) {
+  if (!c || !ms) return HG_ERR_INVALID_ARG;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  for (int p = 0; p < HG_NUM_PHASES; ++p) {
+    ms[p] = 0.0f;
+    if (c->timing && c->recorded[p]) {
+      e = hipEventElapsedTime(&ms[p], c->ev[2 * p], c->ev[2 * p + 1]);
+      if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
+    }
+    c->recorded[p] = false;
+  }
+  return HG_OK;
+}
 
 int hg_init_state(hg_ctx* c, int32_t V, int32_t E, int64_t P, const int64_t* eoff,
                   const uint32_t* pins, int32_t* size, int32_t* syn, int32_t* ax,
@@ -349,18 +388,24 @@ int hg_coarsen_level(hg_ctx* c, const hg_level* in, const hg_limits* lim, int32_
   set_graph_const_kernel<<<1, 1, 0, s>>>(S.gc, *lim);
   LevelView L = view_of(in, S.dims);
   // S0, S1
+  mark(c, 0, 0);
   build_incidence(L, V, E, P, S.vcount, S.voff, S.vinc, S.partials, s);
   Buckets b{S.bcount, S.blist};
   expansion_and_buckets(L, S.voff, S.vinc, V, S.xn, S.gc, 1, b, s);
+  mark(c, 0, 1);
   // S2
   int32_t* cd = cand ? cand : S.cand;
   int32_t* cs = cscore ? cscore : S.cscore;
   ScoreArgs sa{L, S.voff, S.vinc, S.xn, S.gc, S.cursor, cd, cs, S.work, b, c->dev_err};
+  mark(c, 1, 0);
   score_candidates(sa, V, P, s);
+  mark(c, 1, 1);
   // S3-S5
   MatchArgs ma{S.dims, cd, cs, S.bkey, S.jump, S.jump, S.flags, match, vmap, S.rep, S.rank,
                S.partials, n_coarse, any_candidate};
+  mark(c, 2, 0);
   match_and_vmap(ma, V, s);
+  mark(c, 2, 1);
   return launch_status(c);
 }
 
@@ -390,7 +435,9 @@ int hg_contract(hg_ctx* c, const hg_level* in, const int32_t* vmap, const int32_
   set_dims(S.dims, V, E, P, s);
   LevelView L = view_of(in, S.dims);
   S.cs.err = c->dev_err;
+  mark(c, 3, 0);
   contract_level(L, V, E, P, vmap, n_coarse, out, S.cs, s);
+  mark(c, 3, 1);
   return launch_status(c);
 }
 
@@ -412,7 +459,9 @@ int hg_connectivity(hg_ctx* c, const hg_level* lvl, const int32_t* part, int64_t
   set_dims(S.dims, V, E, P, s);
   LevelView L = view_of(lvl, S.dims);
   S.cs.err = c->dev_err;
+  mark(c, 4, 0);
   connectivity(L, E, V, part, conn, S.cs, s);
+  mark(c, 4, 1);
   return launch_status(c);
 }
 

@@ -31,8 +31,10 @@ _i64 = ctypes.c_int64
 
 # Every symbol declared in include/hg.h.
 EXPORTED = ("hg_create", "hg_destroy", "hg_set_stream", "hg_last_error", "hg_sync",
-            "hg_scratch_bytes", "hg_init_state", "hg_coarsen_level", "hg_contract",
-            "hg_connectivity", "hg_validate_level")
+            "hg_scratch_bytes", "hg_enable_timing", "hg_phase_times", "hg_init_state",
+            "hg_coarsen_level", "hg_contract", "hg_connectivity", "hg_validate_level")
+NUM_PHASES = 5
+PHASES = ("incidence", "score", "match", "contract", "connectivity")
 
 
 class HgError(RuntimeError):
@@ -82,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.hg_contract.argtypes = [_P, ctypes.POINTER(_Level), _P, _P, ctypes.POINTER(_LevelOut)]
     lib.hg_connectivity.argtypes = [_P, ctypes.POINTER(_Level), _P, _P]
     lib.hg_validate_level.argtypes = [_P, ctypes.POINTER(_Level)]
+    lib.hg_enable_timing.argtypes = [_P, ctypes.c_int]
+    lib.hg_phase_times.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTED:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     _lib = lib
@@ -155,6 +159,15 @@ class Context:
 
     def scratch_bytes(self) -> int:
         return int(self.lib.hg_scratch_bytes(self.h))
+
+    def enable_timing(self, on: bool = True):
+        self._check(self.lib.hg_enable_timing(self.h, 1 if on else 0))
+
+    def phase_times(self) -> dict:
+        """Device milliseconds per phase of the calls since the last query."""
+        buf = (ctypes.c_float * NUM_PHASES)()
+        self._check(self.lib.hg_phase_times(self.h, buf))
+        return {name: float(buf[i]) for i, name in enumerate(PHASES)}
 
     # -- level construction -------------------------------------------------
     def upload(self, g) -> DeviceLevel:
