@@ -39,6 +39,12 @@ WORKLOADS = {
               "limits 4096/262144/16384; level 0"),
         make=lambda synth, seed: synth.powerlaw(seed, n=2_000_000, dmin=20, dmax=10_000),
         limits="powerlaw"),
+    "powerlaw200k": dict(
+        desc=("recurrent power-law SNN: 200,000 neurons, out-degree d^-2.1 on [20, 10000], "
+              "uniform distinct targets, exponential weights (mean 50), 20% inhibitory x0.5; "
+              "limits 4096/262144/16384; level 0 (profiling size: same per-vertex work)"),
+        make=lambda synth, seed: synth.powerlaw(seed, n=200_000, dmin=20, dmax=10_000),
+        limits="powerlaw"),
     "conv": dict(
         desc=("convolutional SNN: 4 layers of 64x64x16, 3x3 window over all channels of the "
               "next layer; log-uniform weights 1..1000; limits 1024/65536/4096; level 0"),

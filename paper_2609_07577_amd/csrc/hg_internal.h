@@ -89,12 +89,15 @@ void level0_state(const Dims* d, const int64_t* eoff, const uint32_t* pins, int6
 
 // Expansion X_n = sum over incident hyperedges of their size; level maxima;
 // bucket lists for the scoring kernels.
-// Buckets 0-2 without, 3-5 with the shared-inbound count: single pass in the
-// small table, single pass in the big table, multipass in the big table.
-constexpr int kNumBuckets = 6;
+// Buckets 0-3 without, 4-7 with the shared-inbound count: single pass in the
+// small table, single pass in the big table, multipass with the incident
+// hyperedges staged in LDS (degree <= kMetaDeg), multipass with them read
+// from global memory.
+constexpr int kNumBuckets = 8;
 constexpr int kSmallSlots = 4096;
 constexpr int kBigSlots = 16384;
 constexpr int kBigSlotsOv = 8192;
+constexpr int kMetaDeg = 1280;
 struct Buckets {
   int32_t* count;  // [kNumBuckets] device counters
   int32_t* list;   // [kNumBuckets * maxV]

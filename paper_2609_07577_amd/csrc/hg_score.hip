@@ -330,6 +330,220 @@ __global__ __launch_bounds__(THREADS) void score_block_kernel(ScoreArgs a, int b
   }
 }
 
+// Multipass over neighbour-id ranges for vertices whose incident hyperedges
+// fit in LDS.  Offsets, lengths, weights and cursors of the incident
+// hyperedges are staged in LDS once per vertex; hyperedge j belongs to wave
+// j % NW.  Every pass revisits all incident hyperedges, most of them for a
+// few pins only, so a pass is bound by the latency of the dependent pin
+// loads rather than by their bytes.  A wave therefore loads the first chunk
+// of up to kBatch of its segments before it inserts any of them, and while
+// it inserts a chunk whose last pin still lies in the range it already
+// loads the next one.  Per chunk of 64 pins the work is the probe loop
+// (its trip test is a ballot, so the loop is wave-uniform), two ballots and,
+// only when new entries appeared, one LDS atomic that both publishes the
+// wave's new entries and returns the table fill.
+template <int THREADS, int SLOTS, bool OV>
+__global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int bucket,
+                                                              int64_t maxV) {
+  constexpr int NW = THREADS / kWave;
+  constexpr int kBatch = 8;
+  constexpr int MAXFILL = SLOTS * 5 / 8;
+  constexpr uint32_t kSent = 0x7FFFFFFFu;  // id above every range end, flag clear
+  static_assert(MAXFILL + 2 * NW * kWave < SLOTS, "table must never fill up");
+  __shared__ uint64_t table[SLOTS];
+  __shared__ uint32_t ovtab[OV ? SLOTS : 1];
+  __shared__ int64_t m_start[kMetaDeg];
+  __shared__ int32_t m_len[kMetaDeg];
+  __shared__ int32_t m_w[kMetaDeg];
+  __shared__ int32_t m_cur[kMetaDeg];   // committed cursors
+  __shared__ int32_t m_tent[kMetaDeg];  // cursors reached in the current pass
+  __shared__ int32_t m_mult[OV ? kMetaDeg : 1];
+  __shared__ uint64_t red[2 * NW];
+  __shared__ int32_t s_item;
+  __shared__ int32_t s_fill;
+  __shared__ int32_t s_wover[NW];
+
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  int32_t count = a.b.count[bucket];
+  if (count > maxV) {
+    if (tid == 0) atomicOr(a.err, kErrWorkCount);
+    count = (int32_t)maxV;
+  }
+  const int32_t* list = a.b.list + (int64_t)bucket * maxV;
+  for (int i = tid; i < SLOTS; i += THREADS) {
+    table[i] = kEmpty;
+    if (OV) ovtab[i] = 0;
+  }
+
+  while (true) {
+    __syncthreads();
+    if (tid == 0) s_item = atomicAdd(&a.work[bucket], 1);
+    __syncthreads();
+    const int32_t item = s_item;
+    if (item >= count) break;
+
+    VertexCtx v;
+    v.n = list[item];
+    v.beg = a.voff[v.n];
+    v.deg = a.voff[v.n + 1] - v.beg;
+    v.size_n = a.L.size[v.n];
+    v.syn_n = a.L.syn[v.n];
+    v.ax_n = a.L.ax[v.n];
+    v.G = a.gc[a.L.gid ? a.L.gid[v.n] : 0];
+    v.all_valid = (int64_t)v.size_n + v.G.max_size <= v.G.omega &&
+                  (int64_t)v.syn_n + v.G.max_syn <= v.G.phi &&
+                  (int64_t)v.ax_n + v.G.max_ax <= v.G.delta;
+    const int64_t x = a.xn[v.n];
+    const uint32_t n = (uint32_t)v.n;
+    const int32_t deg = (int32_t)v.deg;  // <= kMetaDeg by the bucket rule
+    uint64_t best = 0;
+    constexpr uint32_t cap = SLOTS;
+    const int shift = 32 - log2_pow2(cap);
+
+    int64_t mn = INT64_MAX, mx = -1;
+    for (int j = tid; j < deg; j += THREADS) {
+      const uint32_t ent = a.vinc[v.beg + j];
+      const uint32_t e = ent & kIdMask;
+      const int64_t s0 = a.L.eoff[e], e0 = a.L.eoff[e + 1];
+      m_start[j] = s0;
+      m_len[j] = (int32_t)(e0 - s0);
+      m_w[j] = a.L.w[e];
+      m_cur[j] = 0;
+      if (OV) m_mult[j] = (ent & kDst) ? a.L.mult[e] : 0;
+      const int64_t f = a.L.pins[s0] & kIdMask, l = a.L.pins[e0 - 1] & kIdMask;
+      mn = f < mn ? f : mn;
+      mx = l > mx ? l : mx;
+    }
+    block_min_max_i64<THREADS>(mn, mx, (int64_t*)red);  // also orders the staging
+    const int64_t hi_all = mx + 1;
+    int64_t lo = mn;
+    int64_t width = x <= 8 * (int64_t)MAXFILL
+                        ? hi_all - lo
+                        : (hi_all - lo) * (int64_t)(MAXFILL * 3 / 4) / (x > 0 ? x : 1);
+    if (width < 1) width = 1;
+    int passes = 0;
+    while (lo < hi_all) {
+      const int64_t hi = lo + width < hi_all ? lo + width : hi_all;
+      __syncthreads();  // previous pass drained / cleared, flags read, cursors committed
+      if (++passes > kMaxPasses) {
+        if (tid == 0) atomicOr(a.err, kErrPassLimit);
+        break;
+      }
+      if (tid == 0) s_fill = 0;
+      __syncthreads();
+      bool over = false;
+      for (int32_t j0 = wid; j0 < deg && !over; j0 += kBatch * NW) {
+        // straight-line code, so that all kBatch loads are in flight at once
+        uint32_t pin[kBatch];
+        bool ok[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const int32_t j = j0 + b * NW;
+          const int32_t js = j < deg ? j : j0;
+          const int64_t st = m_start[js], end = st + m_len[js];
+          const int64_t p = st + m_cur[js] + lane;
+          ok[b] = j < deg && p < end;
+          pin[b] = a.L.pins[p < end ? p : end - 1];  // an incident hyperedge is never empty
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) pin[b] = ok[b] ? pin[b] : kSent;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const int32_t j = j0 + b * NW;
+          if (j >= deg || over) break;  // wave-uniform
+          const int64_t st = m_start[j], end = st + m_len[j];
+          const uint32_t wt = (uint32_t)m_w[j];
+          const int32_t mu = OV ? m_mult[j] : 0;
+          int64_t c = st + m_cur[j];
+          uint32_t cur = pin[b];
+          while (true) {
+            // the segment goes on past this chunk iff its last lane holds a
+            // pin below the range end (pins ascend; a lane past the
+            // hyperedge holds the sentinel)
+            const uint32_t last = __builtin_amdgcn_readlane(cur, kWave - 1);
+            const bool cont = (last & kIdMask) < (uint64_t)hi && c + kWave < end;
+            // issued before the inserts so that its latency hides behind them
+            const int64_t pn = c + kWave + lane;
+            uint32_t nxt = kSent;
+            if (cont) nxt = a.L.pins[pn < end ? pn : end - 1];  // wave-uniform
+            const uint32_t id = cur & kIdMask;
+            const bool in = id < (uint64_t)hi;
+            bool pend = in && id != n;
+            bool fresh = false;
+            uint32_t h = slot_hash(id, shift);
+            const uint64_t mine = ((uint64_t)id << 32) | wt;
+            // the table is never full, so every probe sequence ends within
+            // `cap` rounds; the bound only guards against a broken invariant
+            for (uint32_t probe = 0; probe < cap; ++probe) {
+              if (__ballot(pend) == 0) break;
+              if (pend) {
+                const uint64_t old = atomicCAS((unsigned long long*)&table[h],
+                                               (unsigned long long)kEmpty,
+                                               (unsigned long long)mine);
+                const bool got = old == kEmpty;
+                const bool hit = (uint32_t)(old >> 32) == id;  // an empty key is never an id
+                if (hit) atomicAdd((unsigned long long*)&table[h], (unsigned long long)wt);
+                if (OV && mu && (cur & kDst) && (got || hit)) atomicAdd(&ovtab[h], (uint32_t)mu);
+                fresh = fresh || got;
+                pend = !(got || hit);
+                h = (h + 1) & (cap - 1);
+              }
+            }
+            if (__ballot(pend) != 0 && lane == 0) atomicOr(a.err, kErrTableFull);
+            const int cnt = __popcll(__ballot(in));
+            const int nnew = __popcll(__ballot(fresh));
+            if (nnew > 0) {  // wave-uniform
+              // one lane adds the wave's new entries (a lane-varying operand
+              // would make the compiler scan over all lanes)
+              int32_t old = 0;
+              if (lane == 0) old = atomicAdd(&s_fill, nnew);
+              over = __builtin_amdgcn_readlane(old, 0) + nnew > MAXFILL;
+            }
+            c += cnt;
+            if (!cont || over) break;
+            cur = pn < end ? nxt : kSent;
+          }
+          m_tent[j] = (int32_t)(c - st);  // every lane stores the same value
+        }
+      }
+      s_wover[wid] = over ? 1 : 0;  // every lane stores the same value
+      __syncthreads();
+      bool any_over = false;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) any_over |= s_wover[w] != 0;
+      const int32_t fill = s_fill;
+      if (any_over) {
+        for (int i = tid; i < (int)cap; i += THREADS) {
+          table[i] = kEmpty;
+          if (OV) ovtab[i] = 0;
+        }
+        width = width / 2 > 0 ? width / 2 : 1;
+        continue;  // the loop head synchronises before the next pass
+      }
+      drain_table<OV>(table, ovtab, (int)cap, a, v, best, tid, THREADS);
+      for (int jj = tid; jj < deg; jj += THREADS) m_cur[jj] = m_tent[jj];
+      lo = hi;
+      // aim the next range at three quarters of the fill bound
+      if (width < hi_all) {
+        const int64_t target = MAXFILL * 3 / 4;
+        if (fill < target / 4) width *= 4;
+        else if (fill < target) width = width * target / (fill > 0 ? fill : 1);
+        if (width > hi_all) width = hi_all;
+      }
+    }
+    best = block_max_u64<THREADS>(best, red);
+    if (tid == 0) {
+      if (best == 0) {
+        a.cand[v.n] = -1;
+        a.cscore[v.n] = 0;
+      } else {
+        a.cand[v.n] = (int32_t)(0x7FFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull));
+        a.cscore[v.n] = (int32_t)(best >> 32);
+      }
+    }
+  }
+}
+
 __global__ void no_candidate_kernel(const Dims* __restrict__ d, int32_t* __restrict__ cand,
                                     int32_t* __restrict__ cscore, int32_t* __restrict__ work) {
   int64_t V = d->V;
@@ -359,24 +573,30 @@ void score_candidates(const ScoreArgs& a, int64_t maxV, int64_t maxP, hipStream_
   static int g[kNumBuckets] = {0};
   auto k0 = score_block_kernel<256, kSmallSlots, false, false>;
   auto k1 = score_block_kernel<512, kBigSlots, false, false>;
-  auto k2 = score_block_kernel<512, kBigSlots, true, false>;
-  auto k3 = score_block_kernel<256, kSmallSlots, false, true>;
-  auto k4 = score_block_kernel<512, kBigSlotsOv, false, true>;
-  auto k5 = score_block_kernel<512, kBigSlotsOv, true, true>;
+  auto k2 = score_stream_kernel<1024, kBigSlots, false>;
+  auto k3 = score_block_kernel<512, kBigSlots, true, false>;
+  auto k4 = score_block_kernel<256, kSmallSlots, false, true>;
+  auto k5 = score_block_kernel<512, kBigSlotsOv, false, true>;
+  auto k6 = score_stream_kernel<1024, kBigSlotsOv, true>;
+  auto k7 = score_block_kernel<512, kBigSlotsOv, true, true>;
   if (!g[0]) {
     g[0] = persistent_grid(k0, 256);
     g[1] = persistent_grid(k1, 512);
-    g[2] = persistent_grid(k2, 512);
-    g[3] = persistent_grid(k3, 256);
-    g[4] = persistent_grid(k4, 512);
+    g[2] = persistent_grid(k2, 1024);
+    g[3] = persistent_grid(k3, 512);
+    g[4] = persistent_grid(k4, 256);
     g[5] = persistent_grid(k5, 512);
+    g[6] = persistent_grid(k6, 1024);
+    g[7] = persistent_grid(k7, 512);
   }
   k0<<<g[0], 256, 0, s>>>(a, 0, maxV, maxP);
   k1<<<g[1], 512, 0, s>>>(a, 1, maxV, maxP);
-  k2<<<g[2], 512, 0, s>>>(a, 2, maxV, maxP);
-  k3<<<g[3], 256, 0, s>>>(a, 3, maxV, maxP);
-  k4<<<g[4], 512, 0, s>>>(a, 4, maxV, maxP);
+  k2<<<g[2], 1024, 0, s>>>(a, 2, maxV);
+  k3<<<g[3], 512, 0, s>>>(a, 3, maxV, maxP);
+  k4<<<g[4], 256, 0, s>>>(a, 4, maxV, maxP);
   k5<<<g[5], 512, 0, s>>>(a, 5, maxV, maxP);
+  k6<<<g[6], 1024, 0, s>>>(a, 6, maxV);
+  k7<<<g[7], 512, 0, s>>>(a, 7, maxV, maxP);
 }
 
 }  // namespace hg

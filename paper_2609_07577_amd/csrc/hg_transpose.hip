@@ -101,6 +101,7 @@ __global__ void expansion_kernel(LevelView L, const int64_t* __restrict__ voff,
 }
 
 __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
+                              const int64_t* __restrict__ voff,
                               const GraphConst* __restrict__ gc, Buckets b, int64_t maxV) {
   int64_t V = L.dims->V;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -113,8 +114,8 @@ __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
     int bk;
     if (x <= kSmallSlots / 2) bk = 0;
     else if (x <= (ov ? kBigSlotsOv : kBigSlots) / 2) bk = 1;
-    else bk = 2;
-    if (ov) bk += 3;
+    else bk = (voff[v + 1] - voff[v] <= kMetaDeg) ? 2 : 3;
+    if (ov) bk += 4;
     int pos = atomicAdd(&b.count[bk], 1);
     b.list[(int64_t)bk * maxV + pos] = (int32_t)v;
   }
@@ -148,7 +149,7 @@ void expansion_and_buckets(const LevelView& L, const int64_t* voff, const uint32
                            Buckets b, hipStream_t s) {
   reset_maxima_kernel<<<1, 256, 0, s>>>(gc, n_graphs, b.count);
   expansion_kernel<<<grid_for(maxV, 256, 16384), 256, 0, s>>>(L, voff, vinc, xn, gc, b, maxV);
-  bucket_kernel<<<grid_for(maxV, 256, 16384), 256, 0, s>>>(L, xn, gc, b, maxV);
+  bucket_kernel<<<grid_for(maxV, 256, 16384), 256, 0, s>>>(L, xn, voff, gc, b, maxV);
 }
 
 }  // namespace hg
