@@ -468,28 +468,33 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
             if (cont) nxt = a.L.pins[pn < end ? pn : end - 1];  // wave-uniform
             const uint32_t id = cur & kIdMask;
             const bool in = id < (uint64_t)hi;
-            bool pend = in && id != n;
-            bool fresh = false;
-            uint32_t h = slot_hash(id, shift);
-            const uint64_t mine = ((uint64_t)id << 32) | wt;
-            // the table is never full, so every probe sequence ends within
-            // `cap` rounds; the bound only guards against a broken invariant
-            for (uint32_t probe = 0; probe < cap; ++probe) {
-              if (__ballot(pend) == 0) break;
-              if (pend) {
-                const uint64_t old = atomicCAS((unsigned long long*)&table[h],
-                                               (unsigned long long)kEmpty,
-                                               (unsigned long long)mine);
-                const bool got = old == kEmpty;
-                const bool hit = (uint32_t)(old >> 32) == id;  // an empty key is never an id
-                if (hit) atomicAdd((unsigned long long*)&table[h], (unsigned long long)wt);
-                if (OV && mu && (cur & kDst) && (got || hit)) atomicAdd(&ovtab[h], (uint32_t)mu);
-                fresh = fresh || got;
-                pend = !(got || hit);
+            bool fresh = false, lost = false;
+            if (in && id != n) {
+              // plain divergent probe loop with a single exit: a lane leaves
+              // as soon as its slot is found, and the loop ends when no lane
+              // is left (nothing in it crosses lanes).  The table is never
+              // full, so every probe sequence ends within `cap` rounds; the
+              // bound only guards against a broken invariant.
+              uint32_t h = slot_hash(id, shift);
+              const uint64_t mine = ((uint64_t)id << 32) | wt;
+              uint64_t old;
+              uint32_t probe = 0;
+              while (true) {
+                old = atomicCAS((unsigned long long*)&table[h], (unsigned long long)kEmpty,
+                                (unsigned long long)mine);
+                ++probe;
+                // bitwise, not short-circuit: one exit test, no branches
+                const bool stop = (old == kEmpty) | ((uint32_t)(old >> 32) == id) | (probe >= cap);
+                if (stop) break;
                 h = (h + 1) & (cap - 1);
               }
+              fresh = old == kEmpty;
+              const bool hit = !fresh && (uint32_t)(old >> 32) == id;
+              lost = !fresh && !hit;
+              if (hit) atomicAdd((unsigned long long*)&table[h], (unsigned long long)wt);
+              if (OV && mu && (cur & kDst) && !lost) atomicAdd(&ovtab[h], (uint32_t)mu);
             }
-            if (__ballot(pend) != 0 && lane == 0) atomicOr(a.err, kErrTableFull);
+            if (__ballot(lost) != 0 && lane == 0) atomicOr(a.err, kErrTableFull);
             const int cnt = __popcll(__ballot(in));
             const int nnew = __popcll(__ballot(fresh));
             if (nnew > 0) {  // wave-uniform
