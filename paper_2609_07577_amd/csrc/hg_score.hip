@@ -419,7 +419,7 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
     int64_t lo = mn;
     int64_t width = x <= 8 * (int64_t)MAXFILL
                         ? hi_all - lo
-                        : (hi_all - lo) * (int64_t)(MAXFILL * 3 / 4) / (x > 0 ? x : 1);
+                        : (hi_all - lo) * (int64_t)(MAXFILL / 2) / (x > 0 ? x : 1);
     if (width < 1) width = 1;
     int passes = 0;
     while (lo < hi_all) {
@@ -528,9 +528,9 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
       drain_table<OV>(table, ovtab, (int)cap, a, v, best, tid, THREADS);
       for (int jj = tid; jj < deg; jj += THREADS) m_cur[jj] = m_tent[jj];
       lo = hi;
-      // aim the next range at three quarters of the fill bound
+      // aim the next range at half the fill bound (shorter probe runs)
       if (width < hi_all) {
-        const int64_t target = MAXFILL * 3 / 4;
+        const int64_t target = MAXFILL / 2;
         if (fill < target / 4) width *= 4;
         else if (fill < target) width = width * target / (fill > 0 ? fill : 1);
         if (width > hi_all) width = hi_all;
