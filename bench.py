@@ -250,6 +250,7 @@ def main():
         "level_hbm_frac": b_level / (ms_step / 1000.0) / 1e9 / HBM_PEAK_GBS,
         "phases_ms": phases,
         "levels_per_s": 1000.0 / ms_step,
+        "scratch_bytes": ctx.scratch_bytes(),
         "conn_invariant_ok": conn_ok,
     }
     if not args.no_cpu_baseline:
