@@ -188,6 +188,71 @@ int hg_contract(hg_ctx* ctx, const hg_level* in, const int32_t* vmap,
 int hg_connectivity(hg_ctx* ctx, const hg_level* lvl, const int32_t* part, int64_t* conn);
 
 /*
+ * Score-step tuning of a context.  The score step (Eq. 12) accumulates a
+ * vertex's neighbours in an on-chip table.  Vertices whose expansion (sum of
+ * the sizes of their incident hyperedges) is at most single_pass_load16/16 of
+ * a table's slots are scored in one pass; larger ones in passes over ranges
+ * of neighbour ids, each range aimed at pass_fill16/16 of the table.  Results
+ * never depend on these values, only the speed does.  Defaults 8 and 5;
+ * accepted ranges 1..12 and 1..10 (HG_ERR_INVALID_ARG otherwise).
+ */
+typedef struct {
+  int32_t single_pass_load16;
+  int32_t pass_fill16;
+} hg_tuning;
+int hg_set_tuning(hg_ctx* ctx, const hg_tuning* tuning);
+int hg_get_tuning(hg_ctx* ctx, hg_tuning* tuning);
+
+/*
+ * Batches: many independent hypergraphs coarsened together (Section 4.1 per
+ * graph, each with its own limits).  The graphs are laid side by side as one
+ * level; they share no hyperedge, so every graph's hierarchy, partition and
+ * level count are exactly those of a separate run (hg_coarsen_level +
+ * hg_contract until no candidate).  A graph is finished after the first level
+ * at which none of its vertices proposes a candidate.
+ *
+ * The batch owns all its device memory (hg_batch_create allocates it for the
+ * given totals; hg_batch_bytes reports it) and works on the context's stream
+ * with the context's tuning.  Graphs can be added between steps, also while
+ * others are half-way through their hierarchy.
+ *
+ *   hg_batch_create    capacities are totals over the graphs held at once;
+ *                      max_graphs is the number of slots
+ *   hg_batch_add_graph copies a level with state (device arrays, e.g. from
+ *                      hg_init_state) into a free slot; writes the slot
+ *                      index; HG_ERR_CAPACITY when slots, vertices,
+ *                      hyperedges or pins would exceed the capacities
+ *   hg_batch_step      n_levels levels of every unfinished graph;
+ *                      use_graph != 0 replays one HIP graph per level (the
+ *                      level's kernels read all sizes from device memory)
+ *   hg_batch_done      synchronous; writes up to `cap` slots finished since
+ *                      the last call and the number still running
+ *   hg_batch_result    synchronous; for a reported slot: part[v] (device
+ *                      int32, one entry per vertex of the graph as added) =
+ *                      its final super-node numbered 0..n_parts-1 inside the
+ *                      graph, and the number of contractions performed; then
+ *                      releases the slot
+ *   hg_batch_compact   removes released graphs from the level (their slots
+ *                      become free)
+ *   hg_batch_sizes     synchronous; int64[4]: V, E, P of the current level
+ *                      and the original vertices held for unreleased graphs
+ */
+typedef struct hg_batch hg_batch;
+int hg_batch_create(hg_ctx* ctx, int32_t max_graphs, int32_t cap_vertices, int32_t cap_edges,
+                    int64_t cap_pins, hg_batch** out);
+int hg_batch_destroy(hg_batch* batch);
+int64_t hg_batch_bytes(hg_batch* batch);
+int hg_batch_add_graph(hg_batch* batch, const hg_level* level, const hg_limits* limits,
+                       int32_t* slot);
+int hg_batch_step(hg_batch* batch, int32_t n_levels, int32_t use_graph);
+int hg_batch_done(hg_batch* batch, int32_t* slots, int32_t cap, int32_t* n_done,
+                  int32_t* n_running);
+int hg_batch_result(hg_batch* batch, int32_t slot, int32_t* part, int32_t* n_parts,
+                    int32_t* n_levels);
+int hg_batch_compact(hg_batch* batch);
+int hg_batch_sizes(hg_batch* batch, int64_t* sizes);
+
+/*
  * Synchronous structural check of a level: offsets non-decreasing and within
  * P, ids < V and strictly ascending per hyperedge, weights and multiplicities
  * >= 1, total weight < 2^31, state values >= 0 when present (state pointers

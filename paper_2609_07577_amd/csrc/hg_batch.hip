@@ -1,0 +1,650 @@
+// Batches of independent hypergraphs coarsened together.
+//
+// The graphs of a batch are laid side by side as one level (the "union"):
+// graph k's vertex ids, hyperedges and pins follow those of the graphs before
+// it, every vertex carries its graph's slot, and every slot has its own core
+// limits.  Graphs share no hyperedge, so scores, candidates and the matching
+// (Section 4.1, Eq. 12-13) never cross graphs, and the contraction (Section 3,
+// G_P) keeps every graph's vertices, hyperedges and pins contiguous and in
+// order (coarse vertices are numbered by smallest member, coarse hyperedges by
+// smallest fine hyperedge).  One union level step therefore advances every
+// graph by one level of its own hierarchy, with the same result as a
+// separate run.
+//
+// A graph is finished after the first level at which none of its vertices
+// proposes a candidate (its later levels would be the same level); from then
+// on the score step skips its vertices.  Graphs may be added between steps
+// (graphs at different depths coexist in one union), finished graphs are
+// reported, their partitions read out and their slots released; compaction
+// removes released graphs from the union.
+//
+// Every kernel of a level step reads the level sizes from device memory, so a
+// step never waits for the host; it can be captured once per direction of
+// the two level buffers in a HIP graph and replayed.
+#include <algorithm>
+#include <new>
+#include <type_traits>
+#include <vector>
+
+#include "hg_host.h"
+
+namespace hg {
+namespace {
+
+__global__ void set_slot_kernel(GraphConst* gc, int32_t* nlev, int32_t* active, int32_t slot,
+                                hg_limits lim, int32_t done) {
+  GraphConst& g = gc[slot];
+  g.omega = lim.max_neurons;
+  g.phi = lim.max_synapses;
+  g.delta = lim.max_axons;
+  g.max_size = g.max_syn = g.max_ax = 0;
+  g.done = done;
+  nlev[slot] = 0;
+  active[slot] = 0;
+}
+
+// Appends graph pieces at the end of the union: offsets shifted by the pins
+// before it, vertex ids by the vertices before it (flags kept).
+__global__ void append_offsets_kernel(const int64_t* __restrict__ src, int64_t n, int64_t shift,
+                                      int64_t* __restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) dst[i] = src[i] + shift;
+}
+
+__global__ void append_pins_kernel(const uint32_t* __restrict__ src, int64_t n, uint32_t shift,
+                                   uint32_t* __restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    uint32_t p = src[i];
+    dst[i] = ((p & kIdMask) + shift) | (p & kDst);
+  }
+}
+
+__global__ void iota_kernel(int32_t* __restrict__ dst, int64_t n, int32_t start) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) dst[i] = start + (int32_t)i;
+}
+
+__global__ void set_dims_dev_kernel(Dims* d, int64_t V, int64_t E, int64_t P) {
+  d->V = V;
+  d->E = E;
+  d->P = P;
+}
+
+__global__ void set_i64_kernel(int64_t* p, int64_t v) { *p = v; }
+
+// Graphs with a candidate at this level.
+__global__ void activity_kernel(const Dims* __restrict__ d, const int32_t* __restrict__ cand,
+                                const int32_t* __restrict__ gid, int32_t* __restrict__ active) {
+  int64_t V = d->V;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < V; i += stride)
+    if (cand[i] >= 0) active[gid[i]] = 1;
+}
+
+__global__ void graph_update_kernel(int32_t n_slots, int32_t* __restrict__ active,
+                                    int32_t* __restrict__ nlev, GraphConst* __restrict__ gc) {
+  int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_slots) return;
+  if (!gc[g].done) {
+    if (active[g]) nlev[g] += 1;
+    else gc[g].done = 1;
+  }
+  active[g] = 0;
+}
+
+// The coarse vertex of a pair inherits the pair's graph.
+__global__ void gid_kernel(const Dims* __restrict__ d, const int32_t* __restrict__ vmap,
+                           const int32_t* __restrict__ gid, int32_t* __restrict__ gid_out) {
+  int64_t V = d->V;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < V; i += stride) gid_out[vmap[i]] = gid[i];
+}
+
+// Composed vertex map of every original vertex still owned by a graph.
+__global__ void compose_kernel(const int64_t* __restrict__ pool_n, const int32_t* __restrict__ owner,
+                               const int32_t* __restrict__ vmap, int32_t* __restrict__ part) {
+  int64_t n = *pool_n;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride)
+    if (owner[i] >= 0) part[i] = vmap[part[i]];
+}
+
+// First and last vertex and hyperedge of every graph in the current level.
+__global__ void ranges_kernel(const Dims* __restrict__ d, const int64_t* __restrict__ eoff,
+                              const uint32_t* __restrict__ pins, const int32_t* __restrict__ gid,
+                              int32_t* __restrict__ vmin, int32_t* __restrict__ vmax,
+                              int32_t* __restrict__ emin, int32_t* __restrict__ emax) {
+  int64_t V = d->V, E = d->E;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = i; v < V; v += stride) {
+    int32_t g = gid[v];
+    atomicMin(&vmin[g], (int32_t)v);
+    atomicMax(&vmax[g], (int32_t)v);
+  }
+  for (int64_t e = i; e < E; e += stride) {
+    if (eoff[e + 1] == eoff[e]) continue;
+    int32_t g = gid[pins[eoff[e]] & kIdMask];
+    atomicMin(&emin[g], (int32_t)e);
+    atomicMax(&emax[g], (int32_t)e);
+  }
+}
+
+__global__ void relative_kernel(const int32_t* __restrict__ part, int64_t n, int32_t base,
+                                int32_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) out[i] = part[i] - base;
+}
+
+template <typename T>
+__global__ void copy_kernel(const T* __restrict__ src, int64_t n, T* __restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+__global__ void shift_part_kernel(const int32_t* __restrict__ src, int64_t n, int32_t shift,
+                                  int32_t* __restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) dst[i] = src[i] - shift;
+}
+
+__global__ void shift_pins_kernel(const uint32_t* __restrict__ src, int64_t n, uint32_t shift,
+                                  uint32_t* __restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    uint32_t p = src[i];
+    dst[i] = ((p & kIdMask) - shift) | (p & kDst);
+  }
+}
+
+int blocks_for(int64_t n) { return grid_for(n, 256, 8192); }
+
+}  // namespace
+}  // namespace hg
+
+using namespace hg;
+
+namespace {
+
+struct LevelBuf {
+  Dims* dims;
+  int64_t* eoff;
+  uint32_t* pins;
+  int32_t* w;
+  int32_t* mult;
+  int32_t* size;
+  int32_t* syn;
+  int32_t* ax;
+  int32_t* gid;
+};
+
+enum SlotState : int { kFree = 0, kLive = 1, kReported = 2, kReleased = 3 };
+
+struct SlotInfo {
+  int state = kFree;
+  int64_t pool_off = 0;  // original vertices of the graph in the part pool
+  int64_t v0 = 0;        // number of original vertices
+};
+
+}  // namespace
+
+struct hg_batch {
+  hg_ctx* ctx = nullptr;
+  int32_t max_graphs = 0;
+  int64_t capV = 0, capE = 0, capP = 0;
+  char* mem = nullptr;
+  size_t mem_bytes = 0;
+  LevelBuf buf[2] = {};
+  int cur = 0;
+  // products of a level step
+  int32_t *cand = nullptr, *cscore = nullptr, *match = nullptr, *vmap = nullptr;
+  int32_t *n_coarse = nullptr, *any_cand = nullptr;
+  // per slot
+  GraphConst* gc = nullptr;
+  int32_t *nlev = nullptr, *active = nullptr;
+  int32_t *vmin = nullptr, *vmax = nullptr, *emin = nullptr, *emax = nullptr;
+  // original vertex -> current union vertex, with the owning slot (-1: free)
+  int32_t *part = nullptr, *owner = nullptr, *part_tmp = nullptr;
+  int64_t* pool_n = nullptr;  // device copy of pool_used
+  int64_t pool_used = 0;
+  CoarsenScratch<Carver> cs;
+  ContractLayout<Carver> ks;
+  std::vector<SlotInfo> slots;
+  hipStream_t cap_stream = nullptr;  // private stream used only for capture
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  Tuning captured_tuning;
+  int levels_run = 0;
+};
+
+namespace {
+
+template <typename A>
+void carve_batch(hg_batch* b, A& a) {
+  for (int k = 0; k < 2; ++k) {
+    LevelBuf& L = b->buf[k];
+    L.dims = a.template take<Dims>(1);
+    L.eoff = a.template take<int64_t>(b->capE + 1);
+    L.pins = a.template take<uint32_t>(b->capP);
+    L.w = a.template take<int32_t>(b->capE);
+    L.mult = a.template take<int32_t>(b->capE);
+    L.size = a.template take<int32_t>(b->capV);
+    L.syn = a.template take<int32_t>(b->capV);
+    L.ax = a.template take<int32_t>(b->capV);
+    L.gid = a.template take<int32_t>(b->capV);
+  }
+  b->cand = a.template take<int32_t>(b->capV);
+  b->cscore = a.template take<int32_t>(b->capV);
+  b->match = a.template take<int32_t>(b->capV);
+  b->vmap = a.template take<int32_t>(b->capV);
+  b->n_coarse = a.template take<int32_t>(1);
+  b->any_cand = a.template take<int32_t>(1);
+  b->gc = a.template take<GraphConst>(b->max_graphs);
+  b->nlev = a.template take<int32_t>(b->max_graphs);
+  b->active = a.template take<int32_t>(b->max_graphs);
+  b->vmin = a.template take<int32_t>(b->max_graphs);
+  b->vmax = a.template take<int32_t>(b->max_graphs);
+  b->emin = a.template take<int32_t>(b->max_graphs);
+  b->emax = a.template take<int32_t>(b->max_graphs);
+  b->part = a.template take<int32_t>(b->capV);
+  b->owner = a.template take<int32_t>(b->capV);
+  b->part_tmp = a.template take<int32_t>(b->capV);
+  b->pool_n = a.template take<int64_t>(1);
+  CoarsenScratch<A> cs;
+  cs.carve(a, b->capV, b->capE, b->capP);
+  ContractLayout<A> ks;
+  ks.carve(a, b->capV, b->capE, b->capP);
+  if constexpr (std::is_same<A, Carver>::value) {
+    b->cs = cs;
+    b->ks = ks;
+  }
+}
+
+// One level of every graph in the union: buffer `from` -> buffer `to`.
+void level_step(hg_batch* b, int from, int to) {
+  hg_ctx* c = b->ctx;
+  hipStream_t s = c->stream;
+  const LevelBuf& F = b->buf[from];
+  const LevelBuf& T = b->buf[to];
+  const int64_t V = b->capV, E = b->capE, P = b->capP;
+  auto& S = b->cs;
+  LevelView L{F.dims, F.eoff, F.pins, F.w, F.mult, F.size, F.syn, F.ax, F.gid};
+  build_incidence(L, V, E, P, S.vcount, S.voff, S.vinc, S.partials, s);
+  Buckets bk{S.bcount, S.blist};
+  expansion_and_buckets(L, S.voff, S.vinc, V, S.xn, b->gc, b->max_graphs, bk, c->tuning, s);
+  ScoreArgs sa{L,  S.voff, S.vinc, S.xn,      b->gc, S.cursor,         b->cand,
+               b->cscore, S.work, bk, c->dev_err, c->tuning.fill16};
+  score_candidates(sa, V, P, s);
+  MatchArgs ma{F.dims, b->cand, b->cscore, S.bkey, S.jump, S.jump, S.flags, b->match, b->vmap,
+               S.rep, S.rank, S.partials, b->n_coarse, b->any_cand};
+  match_and_vmap(ma, V, s);
+  activity_kernel<<<blocks_for(V), 256, 0, s>>>(F.dims, b->cand, F.gid, b->active);
+  graph_update_kernel<<<(b->max_graphs + 255) / 256, 256, 0, s>>>(b->max_graphs, b->active,
+                                                                   b->nlev, b->gc);
+  hg_level_out out{(int32_t)V, (int32_t)E, P,    T.eoff, T.pins, T.w,
+                   T.mult,     T.size,     T.syn, T.ax,   reinterpret_cast<int64_t*>(T.dims)};
+  b->ks.cs.err = c->dev_err;
+  contract_level(L, V, E, P, b->vmap, b->n_coarse, &out, b->ks.cs, s);
+  gid_kernel<<<blocks_for(V), 256, 0, s>>>(F.dims, b->vmap, F.gid, T.gid);
+  compose_kernel<<<blocks_for(V), 256, 0, s>>>(b->pool_n, b->owner, b->vmap, b->part);
+}
+
+int read_dims(hg_batch* b, Dims* h) {
+  hipError_t e = hipMemcpyAsync(h, b->buf[b->cur].dims, sizeof(Dims), hipMemcpyDeviceToHost,
+                                b->ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->ctx->stream);
+  if (e != hipSuccess) return hip_fail(b->ctx, e, "reading the batch level sizes");
+  return HG_OK;
+}
+
+void drop_graphs(hg_batch* b) {
+  for (int k = 0; k < 2; ++k) {
+    if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+    if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+    b->exec[k] = nullptr;
+    b->graph[k] = nullptr;
+  }
+}
+
+// Current vertex and hyperedge ranges of every slot (synchronous).
+int read_ranges(hg_batch* b, std::vector<int32_t>& vmn, std::vector<int32_t>& vmx,
+                std::vector<int32_t>& emn, std::vector<int32_t>& emx) {
+  hipStream_t s = b->ctx->stream;
+  const int G = b->max_graphs;
+  fill_i32(b->vmin, 0x7FFFFFFF, G, s);
+  fill_i32(b->vmax, -1, G, s);
+  fill_i32(b->emin, 0x7FFFFFFF, G, s);
+  fill_i32(b->emax, -1, G, s);
+  const LevelBuf& L = b->buf[b->cur];
+  int64_t m = b->capV > b->capE ? b->capV : b->capE;
+  ranges_kernel<<<blocks_for(m), 256, 0, s>>>(L.dims, L.eoff, L.pins, L.gid, b->vmin, b->vmax,
+                                               b->emin, b->emax);
+  vmn.resize(G);
+  vmx.resize(G);
+  emn.resize(G);
+  emx.resize(G);
+  hipError_t e = hipMemcpyAsync(vmn.data(), b->vmin, G * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(vmx.data(), b->vmax, G * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(emn.data(), b->emin, G * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(emx.data(), b->emax, G * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(b->ctx, e, "reading the batch ranges");
+  return HG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hg_batch_create(hg_ctx* c, int32_t max_graphs, int32_t cap_vertices, int32_t cap_edges,
+                    int64_t cap_pins, hg_batch** out) {
+  if (!c || !out) return HG_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (max_graphs < 1 || cap_vertices < 0 || cap_edges < 0 || cap_pins < 0)
+    return fail(c, HG_ERR_INVALID_ARG, "bad batch capacities");
+  if (cap_vertices > 0x7FFFFFFE) return fail(c, HG_ERR_OVERFLOW, "too many vertices");
+  hg_batch* b = new (std::nothrow) hg_batch();
+  if (!b) return fail(c, HG_ERR_NO_MEMORY, "host allocation failed");
+  b->ctx = c;
+  b->max_graphs = max_graphs;
+  b->capV = cap_vertices;
+  b->capE = cap_edges;
+  b->capP = cap_pins;
+  Sizer sz;
+  carve_batch(b, sz);
+  hipError_t e = hipMalloc((void**)&b->mem, sz.off);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    delete b;
+    return fail(c, HG_ERR_NO_MEMORY, "cannot allocate %zu bytes for the batch", sz.off);
+  }
+  b->mem_bytes = sz.off;
+  Carver cv{b->mem};
+  carve_batch(b, cv);
+  b->slots.assign(max_graphs, SlotInfo{});
+  hipStream_t s = c->stream;
+  for (int k = 0; k < 2; ++k) {
+    set_dims_dev_kernel<<<1, 1, 0, s>>>(b->buf[k].dims, 0, 0, 0);
+    fill_i64(b->buf[k].eoff, 0, 1, s);
+  }
+  hg_limits none{0, 0, 0};
+  for (int32_t g = 0; g < max_graphs; ++g)
+    set_slot_kernel<<<1, 1, 0, s>>>(b->gc, b->nlev, b->active, g, none, 1);
+  set_i64_kernel<<<1, 1, 0, s>>>(b->pool_n, 0);
+  fill_i32(b->owner, -1, b->capV, s);
+  fill_i32(b->any_cand, 0, 1, s);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(b->mem);
+    delete b;
+    return hip_fail(c, e, "batch initialisation");
+  }
+  *out = b;
+  return HG_OK;
+}
+
+int hg_batch_destroy(hg_batch* b) {
+  if (!b) return HG_OK;
+  (void)hipStreamSynchronize(b->ctx->stream);
+  drop_graphs(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->mem) (void)hipFree(b->mem);
+  delete b;
+  return HG_OK;
+}
+
+int64_t hg_batch_bytes(hg_batch* b) { return b ? (int64_t)b->mem_bytes : 0; }
+
+int hg_batch_add_graph(hg_batch* b, const hg_level* lvl, const hg_limits* lim, int32_t* slot) {
+  if (!b || !slot) return HG_ERR_INVALID_ARG;
+  hg_ctx* c = b->ctx;
+  int rc = check_level(c, lvl, true);
+  if (rc) return rc;
+  if (!lim || lim->max_neurons < 0 || lim->max_synapses < 0 || lim->max_axons < 0)
+    return fail(c, HG_ERR_INVALID_ARG, "bad limits");
+  int32_t g = -1;
+  for (int32_t k = 0; k < b->max_graphs; ++k)
+    if (b->slots[k].state == kFree) {
+      g = k;
+      break;
+    }
+  if (g < 0) return fail(c, HG_ERR_CAPACITY, "all %d graph slots are in use", b->max_graphs);
+  Dims h;
+  rc = read_dims(b, &h);
+  if (rc) return rc;
+  const int64_t Vg = lvl->n_vertices, Eg = lvl->n_edges, Pg = lvl->n_pins;
+  if (h.V + Vg > b->capV || h.E + Eg > b->capE || h.P + Pg > b->capP)
+    return fail(c, HG_ERR_CAPACITY,
+                "batch level full: (%lld, %lld, %lld) + (%lld, %lld, %lld) above capacity",
+                (long long)h.V, (long long)h.E, (long long)h.P, (long long)Vg, (long long)Eg,
+                (long long)Pg);
+  if (b->pool_used + Vg > b->capV)
+    return fail(c, HG_ERR_CAPACITY, "original-vertex pool full; release or compact first");
+  hipStream_t s = c->stream;
+  LevelBuf& L = b->buf[b->cur];
+  append_offsets_kernel<<<blocks_for(Eg + 1), 256, 0, s>>>(lvl->edge_offsets, Eg + 1, h.P,
+                                                           L.eoff + h.E);
+  if (Pg > 0)
+    append_pins_kernel<<<blocks_for(Pg), 256, 0, s>>>(lvl->pins, Pg, (uint32_t)h.V, L.pins + h.P);
+  if (Eg > 0) {
+    copy_kernel<int32_t><<<blocks_for(Eg), 256, 0, s>>>(lvl->edge_weight, Eg, L.w + h.E);
+    copy_kernel<int32_t><<<blocks_for(Eg), 256, 0, s>>>(lvl->edge_mult, Eg, L.mult + h.E);
+  }
+  if (Vg > 0) {
+    copy_kernel<int32_t><<<blocks_for(Vg), 256, 0, s>>>(lvl->v_size, Vg, L.size + h.V);
+    copy_kernel<int32_t><<<blocks_for(Vg), 256, 0, s>>>(lvl->v_syn, Vg, L.syn + h.V);
+    copy_kernel<int32_t><<<blocks_for(Vg), 256, 0, s>>>(lvl->v_axons, Vg, L.ax + h.V);
+    fill_i32(L.gid + h.V, g, Vg, s);
+    iota_kernel<<<blocks_for(Vg), 256, 0, s>>>(b->part + b->pool_used, Vg, (int32_t)h.V);
+    fill_i32(b->owner + b->pool_used, g, Vg, s);
+  }
+  set_dims_dev_kernel<<<1, 1, 0, s>>>(L.dims, h.V + Vg, h.E + Eg, h.P + Pg);
+  set_slot_kernel<<<1, 1, 0, s>>>(b->gc, b->nlev, b->active, g, *lim, 0);
+  b->slots[g].state = kLive;
+  b->slots[g].pool_off = b->pool_used;
+  b->slots[g].v0 = Vg;
+  b->pool_used += Vg;
+  set_i64_kernel<<<1, 1, 0, s>>>(b->pool_n, b->pool_used);
+  *slot = g;
+  return launch_status(c);
+}
+
+int hg_batch_step(hg_batch* b, int32_t n_levels, int32_t use_graph) {
+  if (!b || n_levels < 0) return HG_ERR_INVALID_ARG;
+  hg_ctx* c = b->ctx;
+  hipStream_t s = c->stream;
+  if (use_graph) {
+    if (b->exec[0] && (b->captured_tuning.load16 != c->tuning.load16 ||
+                       b->captured_tuning.fill16 != c->tuning.fill16))
+      drop_graphs(b);
+    if (!b->exec[0]) {
+      // capture on a private stream (the context's may be the null stream,
+      // which cannot be captured); the graphs are launched on the context's
+      if (!b->cap_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamCreateWithFlags");
+      }
+      for (int from = 0; from < 2; ++from) {
+        hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+        c->stream = b->cap_stream;
+        level_step(b, from, 1 - from);
+        c->stream = s;
+        e = hipStreamEndCapture(b->cap_stream, &b->graph[from]);
+        if (e != hipSuccess) {
+          drop_graphs(b);
+          return hip_fail(c, e, "hipStreamEndCapture");
+        }
+        e = hipGraphInstantiate(&b->exec[from], b->graph[from], nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+          drop_graphs(b);
+          return hip_fail(c, e, "hipGraphInstantiate");
+        }
+      }
+      b->captured_tuning = c->tuning;
+    }
+  }
+  for (int32_t l = 0; l < n_levels; ++l) {
+    const int from = b->cur;
+    if (use_graph) {
+      hipError_t e = hipGraphLaunch(b->exec[from], s);
+      if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+    } else {
+      level_step(b, from, 1 - from);
+      int rc = launch_status(c);
+      if (rc) return rc;
+    }
+    b->cur = 1 - from;
+    b->levels_run += 1;
+  }
+  return HG_OK;
+}
+
+int hg_batch_done(hg_batch* b, int32_t* slots, int32_t cap, int32_t* n_done, int32_t* n_live) {
+  if (!b || !n_done || (cap > 0 && !slots)) return HG_ERR_INVALID_ARG;
+  hg_ctx* c = b->ctx;
+  std::vector<GraphConst> h(b->max_graphs);
+  hipError_t e = hipMemcpyAsync(h.data(), b->gc, sizeof(GraphConst) * b->max_graphs,
+                                hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "reading the batch graph states");
+  int32_t n = 0, live = 0;
+  for (int32_t g = 0; g < b->max_graphs; ++g) {
+    if (b->slots[g].state != kLive) continue;
+    if (h[g].done && n < cap) {
+      slots[n++] = g;
+      b->slots[g].state = kReported;
+    } else {
+      ++live;
+    }
+  }
+  *n_done = n;
+  if (n_live) *n_live = live;
+  return HG_OK;
+}
+
+int hg_batch_result(hg_batch* b, int32_t g, int32_t* part, int32_t* n_parts, int32_t* n_levels) {
+  if (!b || g < 0 || g >= b->max_graphs) return HG_ERR_INVALID_ARG;
+  hg_ctx* c = b->ctx;
+  SlotInfo& si = b->slots[g];
+  if (si.state != kReported)
+    return fail(c, HG_ERR_INVALID_ARG, "slot %d holds no finished graph (poll hg_batch_done)", g);
+  if (si.v0 > 0 && !part) return fail(c, HG_ERR_INVALID_ARG, "part is null");
+  std::vector<int32_t> vmn, vmx, emn, emx;
+  int rc = read_ranges(b, vmn, vmx, emn, emx);
+  if (rc) return rc;
+  hipStream_t s = c->stream;
+  int32_t lv = 0;
+  hipError_t e = hipMemcpyAsync(&lv, b->nlev + g, 4, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(c, e, "reading the level count");
+  if (si.v0 > 0)
+    relative_kernel<<<blocks_for(si.v0), 256, 0, s>>>(b->part + si.pool_off, si.v0, vmn[g], part);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "reading the partition");
+  if (n_parts) *n_parts = si.v0 > 0 ? vmx[g] - vmn[g] + 1 : 0;
+  if (n_levels) *n_levels = lv;
+  // release: the graph's vertices stay in the union (skipped) until compaction
+  if (si.v0 > 0) fill_i32(b->owner + si.pool_off, -1, si.v0, s);
+  si.state = kReleased;
+  return launch_status(c);
+}
+
+int hg_batch_compact(hg_batch* b) {
+  if (!b) return HG_ERR_INVALID_ARG;
+  hg_ctx* c = b->ctx;
+  hipStream_t s = c->stream;
+  std::vector<int32_t> vmn, vmx, emn, emx;
+  int rc = read_ranges(b, vmn, vmx, emn, emx);
+  if (rc) return rc;
+  std::vector<int64_t> eoff_h;
+  // graphs that stay, in union order
+  std::vector<int32_t> keep;
+  for (int32_t g = 0; g < b->max_graphs; ++g)
+    if (b->slots[g].state == kLive || b->slots[g].state == kReported) keep.push_back(g);
+  std::sort(keep.begin(), keep.end(), [&](int32_t x, int32_t y) { return vmn[x] < vmn[y]; });
+  const LevelBuf& F = b->buf[b->cur];
+  const LevelBuf& T = b->buf[1 - b->cur];
+  int64_t V = 0, E = 0, P = 0, pool = 0;
+  for (int32_t g : keep) {
+    SlotInfo& si = b->slots[g];
+    const int64_t vs = vmn[g], vn = vmx[g] >= vmn[g] ? (int64_t)vmx[g] - vmn[g] + 1 : 0;
+    const int64_t es = emn[g], en = emx[g] >= emn[g] ? (int64_t)emx[g] - emn[g] + 1 : 0;
+    int64_t ps = 0, pe = 0;
+    if (en > 0) {
+      int64_t pr[2];
+      hipError_t e = hipMemcpyAsync(&pr[0], F.eoff + es, 8, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(&pr[1], F.eoff + es + en, 8, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_fail(c, e, "reading hyperedge offsets");
+      ps = pr[0];
+      pe = pr[1];
+    }
+    const int64_t pn = pe - ps;
+    if (vn > 0) {
+      copy_kernel<int32_t><<<blocks_for(vn), 256, 0, s>>>(F.size + vs, vn, T.size + V);
+      copy_kernel<int32_t><<<blocks_for(vn), 256, 0, s>>>(F.syn + vs, vn, T.syn + V);
+      copy_kernel<int32_t><<<blocks_for(vn), 256, 0, s>>>(F.ax + vs, vn, T.ax + V);
+      copy_kernel<int32_t><<<blocks_for(vn), 256, 0, s>>>(F.gid + vs, vn, T.gid + V);
+    }
+    if (en > 0) {
+      append_offsets_kernel<<<blocks_for(en), 256, 0, s>>>(F.eoff + es, en, P - ps, T.eoff + E);
+      copy_kernel<int32_t><<<blocks_for(en), 256, 0, s>>>(F.w + es, en, T.w + E);
+      copy_kernel<int32_t><<<blocks_for(en), 256, 0, s>>>(F.mult + es, en, T.mult + E);
+    }
+    if (pn > 0)
+      shift_pins_kernel<<<blocks_for(pn), 256, 0, s>>>(F.pins + ps, pn, (uint32_t)(vs - V),
+                                                       T.pins + P);
+    if (si.v0 > 0) {
+      shift_part_kernel<<<blocks_for(si.v0), 256, 0, s>>>(b->part + si.pool_off, si.v0,
+                                                          (int32_t)(vs - V), b->part_tmp + pool);
+      fill_i32(b->owner + pool, si.state == kLive || si.state == kReported ? g : -1, si.v0, s);
+    }
+    si.pool_off = pool;
+    V += vn;
+    E += en;
+    P += pn;
+    pool += si.v0;
+  }
+  // the part pool moves to the front in the same order
+  if (pool > 0) copy_kernel<int32_t><<<blocks_for(pool), 256, 0, s>>>(b->part_tmp, pool, b->part);
+  if (b->pool_used > pool) fill_i32(b->owner + pool, -1, b->pool_used - pool, s);
+  b->pool_used = pool;
+  set_i64_kernel<<<1, 1, 0, s>>>(b->pool_n, pool);
+  set_i64_kernel<<<1, 1, 0, s>>>(T.eoff + E, P);
+  set_dims_dev_kernel<<<1, 1, 0, s>>>(T.dims, V, E, P);
+  // released slots become free
+  hg_limits none{0, 0, 0};
+  for (int32_t g = 0; g < b->max_graphs; ++g)
+    if (b->slots[g].state == kReleased) {
+      set_slot_kernel<<<1, 1, 0, s>>>(b->gc, b->nlev, b->active, g, none, 1);
+      b->slots[g] = SlotInfo{};
+    }
+  b->cur = 1 - b->cur;
+  return launch_status(c);
+}
+
+int hg_batch_sizes(hg_batch* b, int64_t* sizes) {
+  if (!b || !sizes) return HG_ERR_INVALID_ARG;
+  Dims h;
+  int rc = read_dims(b, &h);
+  if (rc) return rc;
+  sizes[0] = h.V;
+  sizes[1] = h.E;
+  sizes[2] = h.P;
+  sizes[3] = b->pool_used;
+  return HG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+// Host-side pieces shared by the C ABI translation units: the context, the
+// scratch carving, argument checks and the scratch layouts of the calls.
+#pragma once
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "hg_internal.h"
+
+struct hg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  int32_t* dev_err = nullptr;  // device error word (bounds reached by kernels)
+  bool timing = false;
+  hipEvent_t ev[2 * HG_NUM_PHASES] = {};
+  bool recorded[HG_NUM_PHASES] = {};
+  hg::Tuning tuning;
+};
+
+namespace hg {
+
+// Bump allocator over the arena; every block 256-byte aligned.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(int64_t n) {
+    size_t bytes = ((size_t)(n > 0 ? n : 1) * sizeof(T) + 255) & ~(size_t)255;
+    T* p = reinterpret_cast<T*>(base + off);
+    off += bytes;
+    return p;
+  }
+};
+
+// Sizing pass: same sequence of take() calls with a null base.
+struct Sizer {
+  size_t off = 0;
+  template <typename T>
+  T* take(int64_t n) {
+    off += ((size_t)(n > 0 ? n : 1) * sizeof(T) + 255) & ~(size_t)255;
+    return nullptr;
+  }
+};
+
+inline int fail(hg_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+inline int fail(hg_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+inline int hip_fail(hg_ctx* c, hipError_t e, const char* what) {
+  return fail(c, HG_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+inline int ensure_arena(hg_ctx* c, size_t bytes) {
+  if (bytes <= c->arena_bytes) return HG_OK;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  if (c->arena) {
+    (void)hipFree(c->arena);
+    c->arena = nullptr;
+    c->arena_bytes = 0;
+  }
+  size_t want = bytes + bytes / 8;
+  e = hipMalloc((void**)&c->arena, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    c->arena = nullptr;
+    return fail(c, HG_ERR_NO_MEMORY, "cannot allocate %zu bytes of scratch", want);
+  }
+  c->arena_bytes = want;
+  return HG_OK;
+}
+
+inline void mark(hg_ctx* c, int phase, int end) {
+  if (!c->timing) return;
+  (void)hipEventRecord(c->ev[2 * phase + end], c->stream);
+  if (end) c->recorded[phase] = true;
+}
+
+inline int launch_status(hg_ctx* c) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return HG_OK;
+}
+
+inline int check_level(hg_ctx* c, const hg_level* L, bool need_state) {
+  if (!L) return fail(c, HG_ERR_INVALID_ARG, "level is null");
+  if (L->n_vertices < 0 || L->n_edges < 0 || L->n_pins < 0)
+    return fail(c, HG_ERR_INVALID_ARG, "negative level size");
+  if (L->n_vertices > 0x7FFFFFFE) return fail(c, HG_ERR_OVERFLOW, "too many vertices");
+  if (!L->edge_offsets) return fail(c, HG_ERR_INVALID_ARG, "edge_offsets is null");
+  if (L->n_pins > 0 && !L->pins) return fail(c, HG_ERR_INVALID_ARG, "pins is null");
+  if (L->n_edges > 0 && !L->edge_weight) return fail(c, HG_ERR_INVALID_ARG, "edge_weight is null");
+  if (need_state) {
+    if (L->n_edges > 0 && !L->edge_mult) return fail(c, HG_ERR_INVALID_ARG, "edge_mult is null");
+    if (L->n_vertices > 0 && (!L->v_size || !L->v_syn || !L->v_axons))
+      return fail(c, HG_ERR_INVALID_ARG, "vertex state is null");
+  }
+  return HG_OK;
+}
+
+inline LevelView view_of(const hg_level* L, const Dims* d) {
+  return LevelView{d, L->edge_offsets, L->pins, L->edge_weight, L->edge_mult,
+                   L->v_size, L->v_syn, L->v_axons, nullptr};
+}
+
+// ---- scratch layouts -------------------------------------------------------
+template <typename A>
+struct CoarsenScratch {
+  Dims* dims;
+  GraphConst* gc;
+  int32_t* vcount;
+  int64_t* voff;
+  uint32_t* vinc;
+  int64_t* xn;
+  int32_t* bcount;
+  int32_t* blist;
+  int32_t* work;
+  int32_t* cursor;
+  int32_t* cand;
+  int32_t* cscore;
+  uint64_t* bkey;
+  uint32_t* jump;
+  int32_t* flags;
+  int32_t* rep;
+  int64_t* rank;
+  int64_t* partials;
+  void carve(A& a, int64_t V, int64_t E, int64_t P) {
+    (void)E;
+    dims = a.template take<Dims>(1);
+    gc = a.template take<GraphConst>(1);
+    vcount = a.template take<int32_t>(V);
+    voff = a.template take<int64_t>(V + 1);
+    vinc = a.template take<uint32_t>(P);
+    xn = a.template take<int64_t>(V);
+    bcount = a.template take<int32_t>(kNumBuckets);
+    blist = a.template take<int32_t>(kNumBuckets * V);
+    work = a.template take<int32_t>(kNumBuckets);
+    cursor = a.template take<int32_t>(2 * P);
+    cand = a.template take<int32_t>(V);
+    cscore = a.template take<int32_t>(V);
+    bkey = a.template take<uint64_t>(V);
+    jump = a.template take<uint32_t>(V);
+    flags = a.template take<int32_t>(32);
+    rep = a.template take<int32_t>(V);
+    rank = a.template take<int64_t>(V + 1);
+    partials = a.template take<int64_t>(scan_partials_size());
+  }
+};
+
+inline int64_t pow2_at_least(int64_t x) {
+  int64_t c = 64;
+  while (c < x) c <<= 1;
+  return c;
+}
+
+template <typename A>
+struct ContractLayout {
+  Dims* dims;
+  ContractScratch cs;
+  void carve(A& a, int64_t V, int64_t E, int64_t P) {
+    dims = a.template take<Dims>(1);
+    cs.out_dims = a.template take<Dims>(1);
+    cs.dstmult = a.template take<int32_t>(V);
+    cs.tpin = a.template take<uint32_t>(P);
+    cs.tlen = a.template take<int32_t>(E);
+    cs.fp = a.template take<uint64_t>(E);
+    cs.ebucket = a.template take<int32_t>(3 * E);
+    cs.ecount = a.template take<int32_t>(8);
+    cs.work = a.template take<int32_t>(4);
+    cs.htab_cap = pow2_at_least(2 * E);
+    cs.htab_key = a.template take<uint64_t>(cs.htab_cap);
+    cs.htab_lead = a.template take<int32_t>(cs.htab_cap);
+    cs.slot = a.template take<int32_t>(E);
+    cs.group = a.template take<int32_t>(E);
+    cs.mism = a.template take<int32_t>(E);
+    cs.lflag = a.template take<int32_t>(E);
+    cs.lrank = a.template take<int64_t>(E + 1);
+    cs.leader_at = a.template take<int32_t>(E);
+    cs.llen = a.template take<int64_t>(E);
+    cs.partials = a.template take<int64_t>(scan_partials_size());
+    cs.bitmap_words = (V + 31) / 32 + 1;
+    cs.bitmap = a.template take<uint32_t>((int64_t)kHugeWG * 2 * cs.bitmap_words);
+  }
+};
+
+template <typename A>
+struct ConnLayout {
+  Dims* dims;
+  ConnScratch cs;
+  void carve(A& a, int64_t V, int64_t E) {
+    dims = a.template take<Dims>(1);
+    cs.ebucket = a.template take<int32_t>(3 * E);
+    cs.ecount = a.template take<int32_t>(4);
+    cs.work = a.template take<int32_t>(4);
+    cs.bitmap_words = (V + 31) / 32 + 1;
+    cs.bitmap = a.template take<uint32_t>((int64_t)kHugeWG * cs.bitmap_words);
+  }
+};
+
+}  // namespace hg

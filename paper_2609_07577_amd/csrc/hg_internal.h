@@ -38,6 +38,14 @@ struct Dims {
 struct GraphConst {
   int32_t omega, phi, delta;
   int32_t max_size, max_syn, max_ax;  // level maxima (validity shortcut)
+  int32_t done;  // 1 once a level of this graph had no candidate (its later
+                 // levels are the same level, so the score step skips it)
+};
+
+// Run-time choices of the score step (set per context; see hg_tuning).
+struct Tuning {
+  int32_t load16 = 8;  // single-pass tables take X_n up to load16/16 of their slots
+  int32_t fill16 = 5;  // multipass ranges aim at fill16/16 of the stream table
 };
 
 // Device views of a level.
@@ -104,7 +112,7 @@ struct Buckets {
 };
 void expansion_and_buckets(const LevelView& L, const int64_t* voff, const uint32_t* vinc,
                            int64_t maxV, int64_t* xn, GraphConst* gc, int32_t n_graphs,
-                           Buckets b, hipStream_t s);
+                           Buckets b, Tuning t, hipStream_t s);
 
 // ---- S2 (hg_score.hip) ----------------------------------------------------
 struct ScoreArgs {
@@ -119,6 +127,7 @@ struct ScoreArgs {
   int32_t* work;     // [kNumBuckets] work counters (zeroed by the launcher)
   Buckets b;
   int32_t* err;
+  int32_t fill16;    // Tuning::fill16
 };
 void score_candidates(const ScoreArgs& a, int64_t maxV, int64_t maxP, hipStream_t s);
 

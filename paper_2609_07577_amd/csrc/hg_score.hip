@@ -394,6 +394,10 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
                   (int64_t)v.syn_n + v.G.max_syn <= v.G.phi &&
                   (int64_t)v.ax_n + v.G.max_ax <= v.G.delta;
     const int64_t x = a.xn[v.n];
+    // pass target: fill16/16 of the slots, never above the fill bound
+    const int64_t target = (int64_t)SLOTS * (a.fill16 > 0 ? a.fill16 : 1) / 16 < MAXFILL
+                               ? (int64_t)SLOTS * (a.fill16 > 0 ? a.fill16 : 1) / 16
+                               : MAXFILL;
     const uint32_t n = (uint32_t)v.n;
     const int32_t deg = (int32_t)v.deg;  // <= kMetaDeg by the bucket rule
     uint64_t best = 0;
@@ -419,7 +423,7 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
     int64_t lo = mn;
     int64_t width = x <= 8 * (int64_t)MAXFILL
                         ? hi_all - lo
-                        : (hi_all - lo) * (int64_t)(MAXFILL / 2) / (x > 0 ? x : 1);
+                        : (hi_all - lo) * target / (x > 0 ? x : 1);
     if (width < 1) width = 1;
     int passes = 0;
     while (lo < hi_all) {
@@ -528,9 +532,8 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
       drain_table<OV>(table, ovtab, (int)cap, a, v, best, tid, THREADS);
       for (int jj = tid; jj < deg; jj += THREADS) m_cur[jj] = m_tent[jj];
       lo = hi;
-      // aim the next range at half the fill bound (shorter probe runs)
+      // aim the next range at the pass target
       if (width < hi_all) {
-        const int64_t target = MAXFILL / 2;
         if (fill < target / 4) width *= 4;
         else if (fill < target) width = width * target / (fill > 0 ? fill : 1);
         if (width > hi_all) width = hi_all;

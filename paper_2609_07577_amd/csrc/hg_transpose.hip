@@ -75,7 +75,7 @@ __global__ void reset_maxima_kernel(GraphConst* gc, int32_t n_graphs, int32_t* b
 }
 
 // Thread per vertex.  Bucket by the expansion X_n: single pass in the small
-// table (X_n <= half of it), single pass in the big table, or multipass; +3
+// table (X_n <= load16/16 of it), single pass in the big table, or multipass; +4
 // when the distinct-axon bound can bind for n (ax_n + level max > Delta), so
 // the shared inbound count must be accumulated.  Vertices with X_n = 0 have
 // no neighbour and are in no list.
@@ -102,7 +102,8 @@ __global__ void expansion_kernel(LevelView L, const int64_t* __restrict__ voff,
 
 __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
                               const int64_t* __restrict__ voff,
-                              const GraphConst* __restrict__ gc, Buckets b, int64_t maxV) {
+                              const GraphConst* __restrict__ gc, Buckets b, int64_t maxV,
+                              int32_t load16) {
   int64_t V = L.dims->V;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -110,10 +111,11 @@ __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
     int64_t x = xn[v];
     if (x <= 0) continue;
     const GraphConst G = gc[L.gid ? L.gid[v] : 0];
+    if (G.done) continue;  // no vertex of this graph has a candidate any more
     const bool ov = (int64_t)L.ax[v] + G.max_ax > G.delta;
     int bk;
-    if (x <= kSmallSlots / 2) bk = 0;
-    else if (x <= (ov ? kBigSlotsOv : kBigSlots) / 2) bk = 1;
+    if (x <= (int64_t)kSmallSlots * load16 / 16) bk = 0;
+    else if (x <= (int64_t)(ov ? kBigSlotsOv : kBigSlots) * load16 / 16) bk = 1;
     else bk = (voff[v + 1] - voff[v] <= kMetaDeg) ? 2 : 3;
     if (ov) bk += 4;
     int pos = atomicAdd(&b.count[bk], 1);
@@ -146,10 +148,11 @@ void level0_state(const Dims* d, const int64_t* eoff, const uint32_t* pins, int6
 
 void expansion_and_buckets(const LevelView& L, const int64_t* voff, const uint32_t* vinc,
                            int64_t maxV, int64_t* xn, GraphConst* gc, int32_t n_graphs,
-                           Buckets b, hipStream_t s) {
+                           Buckets b, Tuning t, hipStream_t s) {
   reset_maxima_kernel<<<1, 256, 0, s>>>(gc, n_graphs, b.count);
   expansion_kernel<<<grid_for(maxV, 256, 16384), 256, 0, s>>>(L, voff, vinc, xn, gc, b, maxV);
-  bucket_kernel<<<grid_for(maxV, 256, 16384), 256, 0, s>>>(L, xn, voff, gc, b, maxV);
+  bucket_kernel<<<grid_for(maxV, 256, 16384), 256, 0, s>>>(L, xn, voff, gc, b, maxV,
+                                                          t.load16);
 }
 
 }  // namespace hg

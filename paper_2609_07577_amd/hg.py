@@ -32,7 +32,11 @@ _i64 = ctypes.c_int64
 # Every symbol declared in include/hg.h.
 EXPORTED = ("hg_create", "hg_destroy", "hg_set_stream", "hg_last_error", "hg_sync",
             "hg_scratch_bytes", "hg_enable_timing", "hg_phase_times", "hg_init_state",
-            "hg_coarsen_level", "hg_contract", "hg_connectivity", "hg_validate_level")
+            "hg_coarsen_level", "hg_contract", "hg_connectivity", "hg_validate_level",
+            "hg_set_tuning", "hg_get_tuning",
+            "hg_batch_create", "hg_batch_destroy", "hg_batch_bytes", "hg_batch_add_graph",
+            "hg_batch_step", "hg_batch_done", "hg_batch_result", "hg_batch_compact",
+            "hg_batch_sizes")
 NUM_PHASES = 5
 PHASES = ("incidence", "score", "match", "contract", "connectivity")
 
@@ -45,6 +49,11 @@ class HgError(RuntimeError):
 
 class Limits(ctypes.Structure):
     _fields_ = [("max_neurons", _i32), ("max_synapses", _i32), ("max_axons", _i32)]
+
+
+class Tuning(ctypes.Structure):
+    """Score-step tuning (hg_tuning): results never depend on it."""
+    _fields_ = [("single_pass_load16", _i32), ("pass_fill16", _i32)]
 
 
 class _Level(ctypes.Structure):
@@ -86,6 +95,20 @@ def load_library(path: str = LIB_PATH):
     lib.hg_validate_level.argtypes = [_P, ctypes.POINTER(_Level)]
     lib.hg_enable_timing.argtypes = [_P, ctypes.c_int]
     lib.hg_phase_times.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
+    lib.hg_set_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
+    lib.hg_get_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
+    lib.hg_batch_create.argtypes = [_P, _i32, _i32, _i32, _i64, ctypes.POINTER(_P)]
+    lib.hg_batch_destroy.argtypes = [_P]
+    lib.hg_batch_bytes.argtypes = [_P]
+    lib.hg_batch_bytes.restype = _i64
+    lib.hg_batch_add_graph.argtypes = [_P, ctypes.POINTER(_Level), ctypes.POINTER(Limits),
+                                       ctypes.POINTER(_i32)]
+    lib.hg_batch_step.argtypes = [_P, _i32, _i32]
+    lib.hg_batch_done.argtypes = [_P, ctypes.POINTER(_i32), _i32, ctypes.POINTER(_i32),
+                                  ctypes.POINTER(_i32)]
+    lib.hg_batch_result.argtypes = [_P, _i32, _P, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+    lib.hg_batch_compact.argtypes = [_P]
+    lib.hg_batch_sizes.argtypes = [_P, ctypes.POINTER(_i64)]
     for name in EXPORTED:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     _lib = lib
@@ -159,6 +182,15 @@ class Context:
 
     def scratch_bytes(self) -> int:
         return int(self.lib.hg_scratch_bytes(self.h))
+
+    def set_tuning(self, single_pass_load16: int = 8, pass_fill16: int = 5):
+        t = Tuning(single_pass_load16, pass_fill16)
+        self._check(self.lib.hg_set_tuning(self.h, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(self.lib.hg_get_tuning(self.h, ctypes.byref(t)))
+        return dict(single_pass_load16=t.single_pass_load16, pass_fill16=t.pass_fill16)
 
     def enable_timing(self, on: bool = True):
         self._check(self.lib.hg_enable_timing(self.h, 1 if on else 0))
@@ -261,3 +293,75 @@ class Context:
     def validate(self, L: DeviceLevel):
         lv = L.c_struct()
         self._check(self.lib.hg_validate_level(self.h, ctypes.byref(lv)))
+
+
+class Batch:
+    """hg_batch: independent graphs coarsened together in one level per step.
+
+    Graphs are added (as device levels with state) between steps; ``step``
+    advances every unfinished graph; ``done`` lists finished slots;
+    ``result`` returns a finished graph's partition (device int32, numbered
+    inside the graph) and its number of contractions, and frees the slot for
+    ``compact``.
+    """
+
+    def __init__(self, ctx: Context, max_graphs: int, cap_vertices: int, cap_edges: int,
+                 cap_pins: int):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        h = _P()
+        ctx._check(self.lib.hg_batch_create(ctx.h, max_graphs, cap_vertices, cap_edges, cap_pins,
+                                            ctypes.byref(h)))
+        self.h = h
+        self.max_graphs = max_graphs
+        self.v0 = {}  # slot -> original vertex count
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bytes(self) -> int:
+        return int(self.lib.hg_batch_bytes(self.h))
+
+    def add(self, L: DeviceLevel, limits) -> int:
+        lim = Limits(limits.max_neurons, limits.max_synapses, limits.max_axons)
+        lv = L.c_struct()
+        slot = _i32()
+        self.ctx._check(self.lib.hg_batch_add_graph(self.h, ctypes.byref(lv), ctypes.byref(lim),
+                                                    ctypes.byref(slot)))
+        self.v0[slot.value] = L.V
+        return slot.value
+
+    def step(self, n_levels: int = 1, use_graph: bool = True):
+        self.ctx._check(self.lib.hg_batch_step(self.h, n_levels, 1 if use_graph else 0))
+
+    def done(self) -> tuple[list[int], int]:
+        """(slots finished since the last call, number still running)."""
+        buf = (_i32 * self.max_graphs)()
+        n, live = _i32(), _i32()
+        self.ctx._check(self.lib.hg_batch_done(self.h, buf, self.max_graphs, ctypes.byref(n),
+                                               ctypes.byref(live)))
+        return [buf[i] for i in range(n.value)], live.value
+
+    def result(self, slot: int) -> tuple[torch.Tensor, int, int]:
+        v0 = self.v0.pop(slot)
+        part = torch.empty(max(v0, 1), dtype=torch.int32, device=self.ctx.device)[:v0]
+        nparts, nlev = _i32(), _i32()
+        self.ctx._check(self.lib.hg_batch_result(self.h, slot, _ptr(part), ctypes.byref(nparts),
+                                                 ctypes.byref(nlev)))
+        return part, nparts.value, nlev.value
+
+    def compact(self):
+        self.ctx._check(self.lib.hg_batch_compact(self.h))
+
+    def sizes(self) -> tuple[int, int, int, int]:
+        buf = (_i64 * 4)()
+        self.ctx._check(self.lib.hg_batch_sizes(self.h, buf))
+        return tuple(int(x) for x in buf)
