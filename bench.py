@@ -135,6 +135,279 @@ def cpu_baseline(g, lim, X, P, seconds):
     }
 
 
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _pack(sizes, cap_pins):
+    """Consecutive groups whose pin totals stay within cap_pins."""
+    groups, cur, tot = [], [], 0
+    for i, p in enumerate(sizes):
+        if cur and tot + p > cap_pins:
+            groups.append(cur)
+            cur, tot = [], 0
+        cur.append(i)
+        tot += p
+    if cur:
+        groups.append(cur)
+    return groups
+
+
+def run_batch(args):
+    """The mixed batch: 256 graphs, feed-forward or recurrent by a fair coin,
+    neuron count log-uniform in [10k, 500k), fan-out U{16..256}, weights
+    U{1..100}, limits 512/32768/2048 per graph.
+
+    (a) one level of every graph, batched (graphs packed into unions below
+    2^31 pins, one union step each) vs plain (hg_coarsen_level + hg_contract
+    per graph); the score-step tuning is autotuned first and used by both;
+    (b) whole hierarchies of two size-scaled copies of the distribution
+    (neurons in [1k, 20k) with the full fan-out range, and [500, 5000) with
+    fan-out 8..32), batched with the level step replayed from a HIP graph vs
+    plain level-by-level runs, with every partition compared.  Whole
+    hierarchies at full size are out of reach of one run: a graph of the mix
+    needs 100-260 contractions, each costing about as much as its level 0."""
+    import torch
+    from paper_2609_07577_amd import hg, hierarchy, synth, tune
+
+    lim = synth.LIMITS["batch"]
+    ctx = hg.Context(0)
+    # ---- (a) full size, one level -------------------------------------------
+    t0 = time.perf_counter()
+    levels = []
+    for k in range(args.graphs):
+        g = synth.batch_graph(args.seed, k)
+        levels.append(ctx.upload(g))
+        if k % 32 == 31:
+            ctx.sync()
+            _log(f"generated and uploaded {k + 1} graphs")
+    ctx.sync()
+    V = sum(L.V for L in levels)
+    E = sum(L.E for L in levels)
+    P = sum(L.P for L in levels)
+    _log(f"{args.graphs} graphs: V={V} E={E} P={P} ({time.perf_counter() - t0:.1f} s)")
+    sample = sorted(range(len(levels)), key=lambda i: levels[i].P)[:: max(1, len(levels) // 6)]
+    tuned = tune.autotune(ctx, [levels[i] for i in sample], [lim] * len(sample), verbose=True)
+    _log(f"tuning: {tuned['single_pass_load16']}/{tuned['pass_fill16']}")
+
+    def plain_level():
+        for L in levels:
+            out = ctx.coarsen_level(L, lim, want_candidates=False)
+            ctx.contract(L, out["vmap"], out["n_coarse"], trim=False)
+
+    plain_level()  # warm-up
+    ctx.sync()
+    t0 = time.perf_counter()
+    plain_level()
+    ctx.sync()
+    t_plain = time.perf_counter() - t0
+    _log(f"plain: one level of {len(levels)} graphs in {t_plain:.3f} s")
+
+    groups = _pack([L.P for L in levels], (1 << 31) - 1)
+    capV = max(sum(levels[i].V for i in gr) for gr in groups)
+    capE = max(sum(levels[i].E for i in gr) for gr in groups)
+    capP = max(sum(levels[i].P for i in gr) for gr in groups)
+    t_batch = 0.0
+    for rep in range(2):  # first pass is the warm-up
+        t_batch = 0.0
+        for gr in groups:
+            B = hg.Batch(ctx, len(gr), capV, capE, capP)
+            ctx.sync()
+            t0 = time.perf_counter()
+            for i in gr:
+                B.add(levels[i], lim)
+            B.step(1, use_graph=False)
+            ctx.sync()
+            t_batch += time.perf_counter() - t0
+            B.close()
+    ctx.sync()
+    _log(f"batched: one level in {len(groups)} unions in {t_batch:.3f} s")
+    del levels
+    torch.cuda.empty_cache()
+
+    # ---- (b) size-scaled, whole hierarchies ----------------------------------
+    def hierarchies(name, n_min, n_max, fan_min, fan_max, seed):
+        levels_h = []
+        for k in range(args.hier_graphs):
+            g = synth.batch_graph(seed, k, n_min=n_min, n_max=n_max, fan_min=fan_min,
+                                  fan_max=fan_max)
+            levels_h.append(ctx.upload(g))
+        ctx.sync()
+        hP = sum(L.P for L in levels_h)
+        t0 = time.perf_counter()
+        plain_res = []
+        for k, L in enumerate(levels_h):
+            vmaps, nlev, last = hierarchy.plain_hierarchy(ctx, L, lim)
+            plain_res.append((vmaps, nlev, last.V))
+            if k % 16 == 15:
+                _log(f"{name}: plain hierarchies {k + 1} done")
+        ctx.sync()
+        t_p = time.perf_counter() - t0
+        hierarchy.batched_hierarchies(ctx, levels_h[:4], [lim] * 4)  # warm-up (capture)
+        ctx.sync()
+        t0 = time.perf_counter()
+        batch_res = hierarchy.batched_hierarchies(ctx, levels_h, [lim] * len(levels_h))
+        ctx.sync()
+        t_b = time.perf_counter() - t0
+        equal, total_levels = True, 0
+        for (vmaps, nlev, nparts), (part, bparts, blev), L in zip(plain_res, batch_res, levels_h):
+            ref = hierarchy.compose(vmaps, L.V, ctx.device)
+            equal &= bool(torch.equal(ref, part)) and nparts == bparts and nlev == blev
+            total_levels += nlev
+        _log(f"{name}: {len(levels_h)} hierarchies, plain {t_p:.2f} s, batched {t_b:.2f} s, "
+             f"identical={equal}")
+        return {
+            "workload": ("%d graphs of the mix with neurons log-uniform in [%d, %d), fan-out "
+                         "U{%d..%d}, coarsened to the end" % (len(levels_h), n_min, n_max,
+                                                              fan_min, fan_max)),
+            "pins": hP, "contractions": total_levels,
+            "plain_s": t_p, "batched_s": t_b, "batched_vs_plain": t_p / t_b,
+            "plain_pins_per_s": hP / t_p, "batched_pins_per_s": hP / t_b,
+            "identical_partitions": equal,
+        }
+
+    hier_mid = hierarchies("mid", 1000, 20000, 16, 256, args.seed + 1000)
+    hier_small = hierarchies("small", 500, 5000, 8, 32, args.seed + 1100)
+    result = {
+        "metric": METRIC,
+        "value": P / t_batch,
+        "unit": "pins/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": 1000.0 * t_batch,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": ("batch of %d SNN hypergraphs: feed-forward (4 layers) or "
+                                "recurrent by a fair coin, neurons log-uniform in [10k, 500k), "
+                                "fan-out U{16..256}, weights U{1..100}; limits 512/32768/2048; "
+                                "level 0" % args.graphs),
+                   "seed": args.seed, "vertices": V, "hyperedges": E, "pins": P,
+                   "unions": len(groups)},
+        "plain_pins_per_s": P / t_plain,
+        "batched_vs_plain": t_plain / t_batch,
+        "tuning": {k: tuned[k] for k in ("single_pass_load16", "pass_fill16")},
+        "hierarchies_mid": hier_mid,
+        "hierarchies_small": hier_small,
+    }
+    ctx.sync()
+    print(json.dumps(result), flush=True)
+
+
+def run_serve(args):
+    """Served requests: Poisson arrivals at --rate per second for --duration
+    seconds.  A request is one SNN hypergraph to coarsen to the end, drawn
+    from a pool of 1024 graphs of the batch mix scaled down to neurons in
+    [500, 5000) and fan-out 8..32 (98%) plus 2% such graphs of 20,000
+    neurons, all resident on the device.  (A request of the full-size mix
+    costs 0.3-40 GPU-seconds, so a 200/s stream of them cannot be served by
+    one GPU; the scaled mix keeps the offered load below capacity.)  Requests are admitted by footprint into one
+    batch (continuous batching) and stepped 4 levels per union step from a
+    captured HIP graph.  Latency = finish - arrival.  Every served partition
+    of a seeded sample is compared with a plain run of the same graph."""
+    import numpy as np
+    import torch
+    from paper_2609_07577_amd import hg, hierarchy, serve, synth
+
+    ctx = hg.Context(0)
+    rng = np.random.default_rng(args.seed)
+    pool, lims = [], []
+    for k in range(1024):
+        g = synth.batch_graph(args.seed + 2000, k, n_min=500, n_max=5000, fan_min=8, fan_max=32)
+        pool.append(ctx.upload(g))
+        lims.append(synth.LIMITS["batch"])
+    for k in range(8):
+        g = synth.batch_graph(args.seed + 3000, k, n_min=20000, n_max=20001, fan_min=8,
+                              fan_max=32)
+        pool.append(ctx.upload(g))
+        lims.append(synth.LIMITS["batch"])
+    ctx.sync()
+    _log(f"request pool: {len(pool)} graphs on the device")
+    n_req = int(rng.poisson(args.rate * args.duration))
+    arrivals = np.sort(rng.uniform(0.0, args.duration, n_req))
+    big = rng.random(n_req) < 0.02
+    which = np.where(big, 1024 + rng.integers(0, 8, n_req), rng.integers(0, 1024, n_req))
+    srv = serve.Server(ctx, max_graphs=1024, cap_vertices=2_000_000, cap_edges=2_000_000,
+                       cap_pins=64_000_000, levels_per_step=4, use_graph=True)
+    # warm-up: capture and first launches
+    srv.submit(-1, pool[0], lims[0], time.perf_counter())
+    while not srv.idle():
+        srv.step()
+    ctx.sync()
+    _log(f"serving {n_req} requests over {args.duration:.0f} s")
+    lat, pins_done, served = [], 0, {}
+    t0 = time.perf_counter()
+    nxt = 0
+    last_log = t0
+    while nxt < n_req or not srv.idle():
+        now = time.perf_counter() - t0
+        while nxt < n_req and arrivals[nxt] <= now:
+            srv.submit(nxt, pool[which[nxt]], lims[which[nxt]], t0 + arrivals[nxt])
+            nxt += 1
+        for rid, arr, fin, part, n_parts, n_levels, pins in srv.step():
+            lat.append(fin - arr)
+            pins_done += pins
+            if rid % 97 == 0:
+                served[rid] = (part, n_parts, n_levels)
+        if srv.idle() and nxt < n_req:
+            time.sleep(max(0.0, min(0.005, arrivals[nxt] - (time.perf_counter() - t0))))
+        if time.perf_counter() - last_log > 10:
+            last_log = time.perf_counter()
+            _log(f"t={last_log - t0:.0f} s: {len(lat)} served, {len(srv.queue)} queued, "
+                 f"{len(srv.running)} running")
+    wall = time.perf_counter() - t0
+    ctx.sync()
+    # the same graphs alone, plain
+    equal = True
+    for rid, (part, n_parts, n_levels) in served.items():
+        L = pool[which[rid]]
+        vmaps, nlev, last = hierarchy.plain_hierarchy(ctx, L, lims[which[rid]])
+        ref = hierarchy.compose(vmaps, L.V, ctx.device)
+        equal &= bool(torch.equal(ref, part)) and nlev == n_levels and last.V == n_parts
+    # plain service capacity on a sample of the stream
+    sample = [int(x) for x in rng.choice(n_req, size=min(24, n_req), replace=False)]
+    ctx.sync()
+    t1 = time.perf_counter()
+    for r in sample:
+        hierarchy.plain_hierarchy(ctx, pool[which[r]], lims[which[r]], keep_maps=False)
+    ctx.sync()
+    t_plain_req = (time.perf_counter() - t1) / len(sample)
+    lat_ms = np.array(lat) * 1000.0
+    batch_bytes = srv.bytes()
+    srv.close()
+    result = {
+        "metric": METRIC,
+        "value": pins_done / wall,
+        "unit": "pins/s",
+        "n_gpus": 1,
+        "steps": len(lat),
+        "warmup": 1,
+        "ms_per_step": 1000.0 * wall / max(1, len(lat)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": ("served mapping requests, Poisson %.0f/s for %.0f s: 98%% batch-mix "
+                                "graphs with neurons log-uniform in [500, 5000) and fan-out "
+                                "U{8..32}, 2%% such graphs of 20,000 neurons; limits "
+                                "512/32768/2048; each coarsened to the end"
+                                % (args.rate, args.duration)),
+                   "requests": n_req, "seed": args.seed, "batch_bytes": batch_bytes},
+        "p50_ms": float(np.percentile(lat_ms, 50)),
+        "p99_ms": float(np.percentile(lat_ms, 99)),
+        "served_per_s": len(lat) / wall,
+        "plain_mean_service_ms": 1000.0 * t_plain_req,
+        "plain_capacity_per_s": 1.0 / t_plain_req,
+        "served_equal_to_alone": equal,
+        "checked": len(served),
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +417,15 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="level", choices=("level", "batch", "serve"),
+                    help="level: one coarsening level of one graph (default); batch: the "
+                         "256-graph batch, batched vs plain; serve: continuous batching of "
+                         "Poisson-arriving requests")
+    ap.add_argument("--graphs", type=int, default=256, help="batch mode: graphs at full size")
+    ap.add_argument("--hier-graphs", type=int, default=64,
+                    help="batch mode: graphs of the size-scaled full-hierarchy comparison")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve mode: requests per second")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve mode: seconds of arrivals")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times), the "
                          "reference kernel for scaling the FETCH_SIZE/WRITE_SIZE counters")
@@ -164,6 +446,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n * 4, "launches": 5}), flush=True)
+        return
+
+    if args.mode == "batch":
+        run_batch(args)
+        return
+    if args.mode == "serve":
+        run_serve(args)
         return
 
     from paper_2609_07577_amd import hg, synth

@@ -47,7 +47,7 @@ extern "C" {
 typedef enum {
   HG_OK = 0,
   HG_ERR_INVALID_ARG = 1,   /* null pointer, negative size, bad limits      */
-  HG_ERR_OVERFLOW = 2,      /* V >= 2^31, E >= 2^31, sum of weights >= 2^31  */
+  HG_ERR_OVERFLOW = 2,      /* V, E or P >= 2^31, sum of weights >= 2^31     */
   HG_ERR_CAPACITY = 3,      /* an output capacity is smaller than needed     */
   HG_ERR_NO_MEMORY = 4,     /* the scratch arena could not be grown          */
   HG_ERR_HIP = 5,           /* a HIP runtime call failed                     */
@@ -216,8 +216,8 @@ int hg_get_tuning(hg_ctx* ctx, hg_tuning* tuning);
  * with the context's tuning.  Graphs can be added between steps, also while
  * others are half-way through their hierarchy.
  *
- *   hg_batch_create    capacities are totals over the graphs held at once;
- *                      max_graphs is the number of slots
+ *   hg_batch_create    capacities are totals over the graphs held at once
+ *                      (pins below 2^31); max_graphs is the number of slots
  *   hg_batch_add_graph copies a level with state (device arrays, e.g. from
  *                      hg_init_state) into a free slot; writes the slot
  *                      index; HG_ERR_CAPACITY when slots, vertices,

@@ -354,6 +354,7 @@ int hg_batch_create(hg_ctx* c, int32_t max_graphs, int32_t cap_vertices, int32_t
   if (max_graphs < 1 || cap_vertices < 0 || cap_edges < 0 || cap_pins < 0)
     return fail(c, HG_ERR_INVALID_ARG, "bad batch capacities");
   if (cap_vertices > 0x7FFFFFFE) return fail(c, HG_ERR_OVERFLOW, "too many vertices");
+  if (cap_pins > 0x7FFFFFFF) return fail(c, HG_ERR_OVERFLOW, "2^31 or more pins");
   hg_batch* b = new (std::nothrow) hg_batch();
   if (!b) return fail(c, HG_ERR_NO_MEMORY, "host allocation failed");
   b->ctx = c;

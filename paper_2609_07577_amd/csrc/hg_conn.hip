@@ -21,15 +21,23 @@ constexpr uint32_t kEmptySlot = 0xFFFFFFFFu;
 __global__ void conn_classify_kernel(const Dims* __restrict__ d, const int64_t* __restrict__ eoff,
                                      int32_t* __restrict__ list, int32_t* __restrict__ count,
                                      int64_t maxE) {
-  int64_t E = d->E;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < E; i += stride) {
-    int64_t s = eoff[i + 1] - eoff[i];
-    if (s < 2) continue;  // lambda <= 1 contributes nothing
-    int b = s <= kSmallMax ? 0 : (s <= kBlockMax ? 1 : 2);
-    int pos = atomicAdd(&count[b], 1);
-    list[(int64_t)b * maxE + pos] = (int32_t)i;
+  const int64_t E = d->E;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // wave-uniform loop: every lane takes part in the list append
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x & ~(kWave - 1));
+       base < E;
+       base += stride) {
+    const int64_t i = base + lane;
+    int b = -1;
+    if (i < E) {
+      const int64_t s = eoff[i + 1] - eoff[i];
+      // lambda <= 1 contributes nothing
+      if (s >= 2) b = s <= kSmallMax ? 0 : (s <= kBlockMax ? 1 : 2);
+    }
+    const int32_t pos = wave_bucket_slot<3>(b, count);
+    if (b >= 0) list[(int64_t)b * maxE + pos] = (int32_t)i;
   }
 }
 

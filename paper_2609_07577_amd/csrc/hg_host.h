@@ -100,6 +100,7 @@ inline int check_level(hg_ctx* c, const hg_level* L, bool need_state) {
   if (L->n_vertices < 0 || L->n_edges < 0 || L->n_pins < 0)
     return fail(c, HG_ERR_INVALID_ARG, "negative level size");
   if (L->n_vertices > 0x7FFFFFFE) return fail(c, HG_ERR_OVERFLOW, "too many vertices");
+  if (L->n_pins > 0x7FFFFFFF) return fail(c, HG_ERR_OVERFLOW, "2^31 or more pins");
   if (!L->edge_offsets) return fail(c, HG_ERR_INVALID_ARG, "edge_offsets is null");
   if (L->n_pins > 0 && !L->pins) return fail(c, HG_ERR_INVALID_ARG, "pins is null");
   if (L->n_edges > 0 && !L->edge_weight) return fail(c, HG_ERR_INVALID_ARG, "edge_weight is null");

@@ -72,6 +72,28 @@ inline int grid_for(int64_t n, int per_block, int cap = 65536) {
 
 int device_cu_count();
 
+// Work-list append with one atomic per bucket and wave.  Lane l asks for a
+// slot in bucket b (0 <= b < NB, or -1 for none) and gets its position in
+// that bucket.  All 64 lanes of the wave must be active: callers loop with a
+// wave-uniform trip count and pass b = -1 for lanes past the end.
+template <int NB>
+__device__ inline int32_t wave_bucket_slot(int b, int32_t* count) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  int32_t pos = 0;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const uint64_t m = __ballot(b == k);
+    if (m == 0) continue;  // wave-uniform
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(&count[k], (int32_t)__popcll(m));
+    base = __builtin_amdgcn_readlane(base, leader);
+    if (b == k) pos = base + (int32_t)__popcll(m & below);
+  }
+  return pos;
+}
+
 // ---- primitives (hg_prims.hip) --------------------------------------------
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);

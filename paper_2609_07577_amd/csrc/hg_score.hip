@@ -40,20 +40,27 @@ constexpr int kMaxPasses = 1 << 16;
 // Adds `wt` to the score of `id`; returns the slot, with bit 31 set when the
 // entry is new.  The callers keep the table at most about half full, so the
 // probe bound (the table size) is never reached by a correct run; if it is,
-// the error word says so and kNoSlot is returned.
+// the error word says so and kNoSlot is returned.  The probe loop has a
+// single exit test (bitwise, not short-circuit), which keeps the mask
+// bookkeeping of the divergent loop to a few scalar instructions a round.
 __device__ inline uint32_t table_add(uint64_t* table, uint32_t mask, int shift, uint32_t id,
                                      uint32_t wt, int32_t* err) {
   uint32_t h = slot_hash(id, shift) & mask;
   const uint64_t mine = ((uint64_t)id << 32) | wt;
-  for (uint32_t probe = 0; probe <= mask; ++probe) {
-    uint64_t old = atomicCAS((unsigned long long*)&table[h], (unsigned long long)kEmpty,
-                             (unsigned long long)mine);
-    if (old == kEmpty) return h | 0x80000000u;
-    if ((uint32_t)(old >> 32) == id) {
-      atomicAdd((unsigned long long*)&table[h], (unsigned long long)wt);
-      return h;
-    }
+  uint64_t old;
+  uint32_t probe = 0;
+  while (true) {
+    old = atomicCAS((unsigned long long*)&table[h], (unsigned long long)kEmpty,
+                    (unsigned long long)mine);
+    ++probe;
+    const bool stop = (old == kEmpty) | ((uint32_t)(old >> 32) == id) | (probe > mask);
+    if (stop) break;
     h = (h + 1) & mask;
+  }
+  if (old == kEmpty) return h | 0x80000000u;
+  if ((uint32_t)(old >> 32) == id) {
+    atomicAdd((unsigned long long*)&table[h], (unsigned long long)wt);
+    return h;
   }
   atomicOr(err, kErrTableFull);
   return kNoSlot;
@@ -163,7 +170,7 @@ __global__ __launch_bounds__(THREADS) void score_block_kernel(ScoreArgs a, int b
   __shared__ uint32_t ovtab[OV ? SLOTS : 1];
   __shared__ uint64_t red[2 * NW];
   __shared__ int32_t s_item;
-  __shared__ int32_t s_wfill[NW];  // fresh entries per wave in this pass
+  __shared__ int32_t s_fill;       // fresh entries in this pass
   __shared__ int32_t s_wover[NW];  // wave saw the pass overflow
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
@@ -243,7 +250,8 @@ __global__ __launch_bounds__(THREADS) void score_block_kernel(ScoreArgs a, int b
       block_min_max_i64<THREADS>(mn, mx, (int64_t*)red);
       const int64_t hi_all = mx + 1;
       int64_t lo = mn;
-      int64_t width = (hi_all - lo) * (int64_t)(MAXFILL / 2) / (x > 0 ? x : 1);
+      constexpr int64_t target = MAXFILL / 2;
+      int64_t width = (hi_all - lo) * target / (x > 0 ? x : 1);
       if (width < 1) width = 1;
       int passes = 0;
       while (lo < hi_all) {
@@ -253,9 +261,8 @@ __global__ __launch_bounds__(THREADS) void score_block_kernel(ScoreArgs a, int b
           if (tid == 0) atomicOr(a.err, kErrPassLimit);
           break;
         }
-        __hip_atomic_store(&s_wfill[wid], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (tid == 0) s_fill = 0;
         __syncthreads();
-        int32_t wfill = 0;
         bool wover = false;
         for (int64_t j = wid; j < v.deg && !wover; j += NW) {
           const uint32_t ent = a.vinc[v.beg + j];
@@ -266,15 +273,6 @@ __global__ __launch_bounds__(THREADS) void score_block_kernel(ScoreArgs a, int b
           const int32_t mu = dn ? a.L.mult[e] : 0;
           int64_t c = s0 + cur[j];
           while (true) {
-            int32_t total = 0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w)
-              total += __hip_atomic_load(&s_wfill[w], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (total > MAXFILL) {
-              wover = true;
-              break;
-            }
             const int64_t p = c + lane;
             const uint32_t pin = p < e0 ? a.L.pins[p] : 0x7FFFFFFFu;
             const uint32_t id = pin & kIdMask;
@@ -286,23 +284,25 @@ __global__ __launch_bounds__(THREADS) void score_block_kernel(ScoreArgs a, int b
               if (dn && (pin & kDst) && h != kNoSlot) atomicAdd(&ovtab[h & kIdMask], (uint32_t)mu);
             }
             const int cnt = __popcll(__ballot(in));
-            wfill += __popcll(__ballot(fresh));
-            __hip_atomic_store(&s_wfill[wid], wfill, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int nnew = __popcll(__ballot(fresh));
+            if (nnew > 0) {  // wave-uniform
+              // one lane adds the wave's new entries (a lane-varying operand
+              // would make the compiler scan over all lanes)
+              int32_t old = 0;
+              if (lane == 0) old = atomicAdd(&s_fill, nnew);
+              wover = __builtin_amdgcn_readlane(old, 0) + nnew > MAXFILL;
+            }
             c += cnt;
-            if (cnt < kWave) break;
+            if (cnt < kWave || wover) break;
           }
           tent[j] = (int32_t)(c - s0);  // every lane stores the same value
         }
         s_wover[wid] = wover ? 1 : 0;  // every lane stores the same value
         __syncthreads();
         bool over = false;
-        int32_t fill = 0;
+        const int32_t fill = s_fill;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          over |= s_wover[w] != 0;
-          fill += s_wfill[w];
-        }
+        for (int w = 0; w < NW; ++w) over |= s_wover[w] != 0;
         if (over) {
           for (int i = tid; i < (int)cap; i += THREADS) {
             table[i] = kEmpty;
@@ -314,7 +314,12 @@ __global__ __launch_bounds__(THREADS) void score_block_kernel(ScoreArgs a, int b
         drain_table<OV>(table, ovtab, (int)cap, a, v, best, tid, THREADS);
         for (int64_t j = wid + (int64_t)NW * lane; j < v.deg; j += own_step) cur[j] = tent[j];
         lo = hi;
-        if (fill < MAXFILL / 4 && width < hi_all) width *= 2;
+        // aim the next range at the pass target
+        if (width < hi_all) {
+          if (fill < target / 4) width *= 4;
+          else if (fill < target) width = width * target / (fill > 0 ? fill : 1);
+          if (width > hi_all) width = hi_all;
+        }
       }
     }
     best = block_max_u64<THREADS>(best, red);
@@ -338,10 +343,10 @@ __global__ __launch_bounds__(THREADS) void score_block_kernel(ScoreArgs a, int b
 // loads rather than by their bytes.  A wave therefore loads the first chunk
 // of up to kBatch of its segments before it inserts any of them, and while
 // it inserts a chunk whose last pin still lies in the range it already
-// loads the next one.  Per chunk of 64 pins the work is the probe loop
-// (its trip test is a ballot, so the loop is wave-uniform), two ballots and,
-// only when new entries appeared, one LDS atomic that both publishes the
-// wave's new entries and returns the table fill.
+// loads the next one.  Per chunk of 64 pins the work is a divergent probe
+// loop with one exit test, two ballots and, only when new entries appeared,
+// one single-lane LDS atomic that both publishes the wave's new entries and
+// returns the table fill.
 template <int THREADS, int SLOTS, bool OV>
 __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int bucket,
                                                               int64_t maxV) {

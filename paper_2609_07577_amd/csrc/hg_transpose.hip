@@ -82,21 +82,52 @@ __global__ void reset_maxima_kernel(GraphConst* gc, int32_t n_graphs, int32_t* b
 __global__ void expansion_kernel(LevelView L, const int64_t* __restrict__ voff,
                                  const uint32_t* __restrict__ vinc, int64_t* __restrict__ xn,
                                  GraphConst* __restrict__ gc, Buckets b, int64_t maxV) {
-  int64_t V = L.dims->V;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = i; v < V; v += stride) {
-    int64_t s = voff[v], t = voff[v + 1];
-    int64_t x = 0;
-    for (int64_t j = s; j < t; ++j) {
-      uint32_t a = vinc[j] & kIdMask;
-      x += L.eoff[a + 1] - L.eoff[a] - 1;  // neighbours visited through a (n excluded)
+  const int64_t V = L.dims->V;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // wave-uniform loop, so that the per-graph maxima can be reduced per wave
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x & ~(kWave - 1));
+       base < V;
+       base += stride) {
+    const int64_t v = base + lane;
+    const bool ok = v < V;
+    int g = -1;
+    int32_t sz = 0, sy = 0, ax = 0;
+    if (ok) {
+      const int64_t s = voff[v], t = voff[v + 1];
+      int64_t x = 0;
+      for (int64_t j = s; j < t; ++j) {
+        const uint32_t a = vinc[j] & kIdMask;
+        x += L.eoff[a + 1] - L.eoff[a] - 1;  // neighbours visited through a (n excluded)
+      }
+      xn[v] = x;
+      g = L.gid ? L.gid[v] : 0;
+      sz = L.size[v];
+      sy = L.syn[v];
+      ax = L.ax[v];
     }
-    xn[v] = x;
-    int g = L.gid ? L.gid[v] : 0;
-    atomicMax(&gc[g].max_size, L.size[v]);
-    atomicMax(&gc[g].max_syn, L.syn[v]);
-    atomicMax(&gc[g].max_ax, L.ax[v]);
+    // lane 0 is always in range; the wave is one graph unless lanes disagree
+    const int g0 = __builtin_amdgcn_readfirstlane(g);
+    if (__ballot(ok && g != g0) == 0) {  // wave-uniform
+#pragma unroll
+      for (int d = kWave / 2; d > 0; d >>= 1) {
+        const int32_t a = __shfl_xor(sz, d, kWave), b = __shfl_xor(sy, d, kWave),
+                      c = __shfl_xor(ax, d, kWave);
+        sz = a > sz ? a : sz;
+        sy = b > sy ? b : sy;
+        ax = c > ax ? c : ax;
+      }
+      if (lane == 0) {
+        atomicMax(&gc[g0].max_size, sz);
+        atomicMax(&gc[g0].max_syn, sy);
+        atomicMax(&gc[g0].max_ax, ax);
+      }
+    } else if (ok) {
+      atomicMax(&gc[g].max_size, sz);
+      atomicMax(&gc[g].max_syn, sy);
+      atomicMax(&gc[g].max_ax, ax);
+    }
   }
 }
 
@@ -104,22 +135,30 @@ __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
                               const int64_t* __restrict__ voff,
                               const GraphConst* __restrict__ gc, Buckets b, int64_t maxV,
                               int32_t load16) {
-  int64_t V = L.dims->V;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = i; v < V; v += stride) {
-    int64_t x = xn[v];
-    if (x <= 0) continue;
-    const GraphConst G = gc[L.gid ? L.gid[v] : 0];
-    if (G.done) continue;  // no vertex of this graph has a candidate any more
-    const bool ov = (int64_t)L.ax[v] + G.max_ax > G.delta;
-    int bk;
-    if (x <= (int64_t)kSmallSlots * load16 / 16) bk = 0;
-    else if (x <= (int64_t)(ov ? kBigSlotsOv : kBigSlots) * load16 / 16) bk = 1;
-    else bk = (voff[v + 1] - voff[v] <= kMetaDeg) ? 2 : 3;
-    if (ov) bk += 4;
-    int pos = atomicAdd(&b.count[bk], 1);
-    b.list[(int64_t)bk * maxV + pos] = (int32_t)v;
+  const int64_t V = L.dims->V;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // wave-uniform loop: every lane takes part in the list append
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x & ~(kWave - 1));
+       base < V;
+       base += stride) {
+    const int64_t v = base + lane;
+    int bk = -1;
+    if (v < V) {
+      const int64_t x = xn[v];
+      const GraphConst G = gc[L.gid ? L.gid[v] : 0];
+      // no neighbour, or no vertex of this graph has a candidate any more
+      if (x > 0 && !G.done) {
+        const bool ov = (int64_t)L.ax[v] + G.max_ax > G.delta;
+        if (x <= (int64_t)kSmallSlots * load16 / 16) bk = 0;
+        else if (x <= (int64_t)(ov ? kBigSlotsOv : kBigSlots) * load16 / 16) bk = 1;
+        else bk = (voff[v + 1] - voff[v] <= kMetaDeg) ? 2 : 3;
+        if (ov) bk += 4;
+      }
+    }
+    const int32_t pos = wave_bucket_slot<kNumBuckets>(bk, b.count);
+    if (bk >= 0) b.list[(int64_t)bk * maxV + pos] = (int32_t)v;
   }
 }
 

@@ -1,0 +1,51 @@
+"""Autotuner of the score-step settings (``hg_tuning``).
+
+The score step (Eq. 12) scores a vertex in one pass over an on-chip table
+when its expansion is at most ``single_pass_load16``/16 of the table, and in
+passes over ranges of neighbour ids otherwise, each range aimed at
+``pass_fill16``/16 of the table.  Results never depend on these settings;
+the best ones depend on the degree and hyperedge-size mix of the workload.
+``autotune`` times one coarsening level of sample levels under each
+candidate setting and keeps the fastest.
+"""
+from __future__ import annotations
+
+import itertools
+import time
+
+import torch
+
+LOADS = (4, 8, 12)
+FILLS = (3, 5, 8)
+
+
+def time_levels(ctx, levels, limits, repeats: int = 1) -> float:
+    """Seconds for one hg_coarsen_level of every level in ``levels``."""
+    best = float("inf")
+    for _ in range(repeats):
+        ctx.sync()
+        t0 = time.perf_counter()
+        for L, lim in zip(levels, limits):
+            ctx.coarsen_level(L, lim, want_candidates=False)
+        ctx.sync()
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def autotune(ctx, levels, limits, loads=LOADS, fills=FILLS, verbose=False) -> dict:
+    """Set and return the fastest tuning for ``levels`` (device levels with
+    state) under ``limits`` (one per level)."""
+    results = []
+    for load, fill in itertools.product(loads, fills):
+        ctx.set_tuning(load, fill)
+        time_levels(ctx, levels, limits)  # warm-up (first launch, caches)
+        t = time_levels(ctx, levels, limits, repeats=2)
+        results.append((t, load, fill))
+        if verbose:
+            print(f"[tune] load16={load} fill16={fill}: {1e3 * t:.2f} ms", flush=True)
+    t, load, fill = min(results)
+    ctx.set_tuning(load, fill)
+    torch.cuda.synchronize()
+    return dict(single_pass_load16=load, pass_fill16=fill, seconds=t,
+                table=[dict(single_pass_load16=l, pass_fill16=f, seconds=s)
+                       for s, l, f in results])
