@@ -11,6 +11,7 @@ __global__ void set_graph_const_kernel(GraphConst* gc, hg_limits lim) {
   gc->phi = lim.max_synapses;
   gc->delta = lim.max_axons;
   gc->max_size = gc->max_syn = gc->max_ax = 0;
+  gc->nverts = 0;
   gc->done = 0;
 }
 

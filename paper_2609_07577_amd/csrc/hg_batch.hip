@@ -38,6 +38,7 @@ __global__ void set_slot_kernel(GraphConst* gc, int32_t* nlev, int32_t* active, 
   g.phi = lim.max_synapses;
   g.delta = lim.max_axons;
   g.max_size = g.max_syn = g.max_ax = 0;
+  g.nverts = 0;
   g.done = done;
   nlev[slot] = 0;
   active[slot] = 0;

@@ -38,6 +38,8 @@ struct Dims {
 struct GraphConst {
   int32_t omega, phi, delta;
   int32_t max_size, max_syn, max_ax;  // level maxima (validity shortcut)
+  int32_t nverts;  // vertices of the graph in this level: bounds a vertex's
+                   // distinct neighbours (they lie in the same graph)
   int32_t done;  // 1 once a level of this graph had no candidate (its later
                  // levels are the same level, so the score step skips it)
 };

@@ -209,8 +209,11 @@ __global__ __launch_bounds__(THREADS) void score_block_kernel(ScoreArgs a, int b
     uint64_t best = 0;
 
     if (!MULTI) {
+      // distinct neighbours are at most the visits and at most the other
+      // vertices of the graph
+      const int64_t dist = x < (int64_t)v.G.nverts - 1 ? x : (int64_t)v.G.nverts - 1;
       uint32_t cap = 64;
-      while (cap < 2 * (uint64_t)x && cap < (uint32_t)SLOTS) cap <<= 1;
+      while (cap < 2 * (uint64_t)dist && cap < (uint32_t)SLOTS) cap <<= 1;
       const int shift = 32 - log2_pow2(cap);
       for (int64_t j = wid; j < v.deg; j += NW) {
         const uint32_t ent = a.vinc[v.beg + j];

@@ -70,67 +70,65 @@ __global__ void reset_maxima_kernel(GraphConst* gc, int32_t n_graphs, int32_t* b
     gc[g].max_size = 0;
     gc[g].max_syn = 0;
     gc[g].max_ax = 0;
+    gc[g].nverts = 0;
   }
   if (i < kNumBuckets) bcount[i] = 0;
 }
 
-// Thread per vertex.  Bucket by the expansion X_n: single pass in the small
-// table (X_n <= load16/16 of it), single pass in the big table, or multipass; +4
-// when the distinct-axon bound can bind for n (ax_n + level max > Delta), so
-// the shared inbound count must be accumulated.  Vertices with X_n = 0 have
-// no neighbour and are in no list.
 __global__ void expansion_kernel(LevelView L, const int64_t* __restrict__ voff,
                                  const uint32_t* __restrict__ vinc, int64_t* __restrict__ xn,
                                  GraphConst* __restrict__ gc, Buckets b, int64_t maxV) {
+  // A wave per vertex: lanes stride over its incidence list (coarse
+  // super-nodes have tens of thousands of incident hyperedges).  The
+  // per-graph maxima are kept per wave and written when the graph changes.
   const int64_t V = L.dims->V;
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // wave-uniform loop, so that the per-graph maxima can be reduced per wave
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x +
-                      __builtin_amdgcn_readfirstlane(threadIdx.x & ~(kWave - 1));
-       base < V;
-       base += stride) {
-    const int64_t v = base + lane;
-    const bool ok = v < V;
-    int g = -1;
-    int32_t sz = 0, sy = 0, ax = 0;
-    if (ok) {
-      const int64_t s = voff[v], t = voff[v + 1];
-      int64_t x = 0;
-      for (int64_t j = s; j < t; ++j) {
-        const uint32_t a = vinc[j] & kIdMask;
-        x += L.eoff[a + 1] - L.eoff[a] - 1;  // neighbours visited through a (n excluded)
-      }
-      xn[v] = x;
-      g = L.gid ? L.gid[v] : 0;
-      sz = L.size[v];
-      sy = L.syn[v];
-      ax = L.ax[v];
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / kWave) +
+                        __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  int gcur = -1;
+  int32_t msz = 0, msy = 0, max_ = 0, cnt = 0;
+  for (int64_t v = wave0; v < V; v += nwaves) {  // wave-uniform
+    const int64_t s = voff[v], t = voff[v + 1];
+    int64_t x = 0;
+    for (int64_t j = s + lane; j < t; j += kWave) {
+      const uint32_t a = vinc[j] & kIdMask;
+      x += L.eoff[a + 1] - L.eoff[a] - 1;  // neighbours visited through a (n excluded)
     }
-    // lane 0 is always in range; the wave is one graph unless lanes disagree
-    const int g0 = __builtin_amdgcn_readfirstlane(g);
-    if (__ballot(ok && g != g0) == 0) {  // wave-uniform
 #pragma unroll
-      for (int d = kWave / 2; d > 0; d >>= 1) {
-        const int32_t a = __shfl_xor(sz, d, kWave), b = __shfl_xor(sy, d, kWave),
-                      c = __shfl_xor(ax, d, kWave);
-        sz = a > sz ? a : sz;
-        sy = b > sy ? b : sy;
-        ax = c > ax ? c : ax;
+    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+    if (lane == 0) xn[v] = x;
+    const int g = L.gid ? L.gid[v] : 0;
+    if (g != gcur) {  // wave-uniform
+      if (gcur >= 0 && lane == 0) {
+        atomicMax(&gc[gcur].max_size, msz);
+        atomicMax(&gc[gcur].max_syn, msy);
+        atomicMax(&gc[gcur].max_ax, max_);
+        atomicAdd(&gc[gcur].nverts, cnt);
       }
-      if (lane == 0) {
-        atomicMax(&gc[g0].max_size, sz);
-        atomicMax(&gc[g0].max_syn, sy);
-        atomicMax(&gc[g0].max_ax, ax);
-      }
-    } else if (ok) {
-      atomicMax(&gc[g].max_size, sz);
-      atomicMax(&gc[g].max_syn, sy);
-      atomicMax(&gc[g].max_ax, ax);
+      gcur = g;
+      msz = msy = max_ = cnt = 0;
     }
+    ++cnt;
+    const int32_t sz = L.size[v], sy = L.syn[v], ax = L.ax[v];
+    msz = sz > msz ? sz : msz;
+    msy = sy > msy ? sy : msy;
+    max_ = ax > max_ ? ax : max_;
+  }
+  if (gcur >= 0 && lane == 0) {
+    atomicMax(&gc[gcur].max_size, msz);
+    atomicMax(&gc[gcur].max_syn, msy);
+    atomicMax(&gc[gcur].max_ax, max_);
+    atomicAdd(&gc[gcur].nverts, cnt);
   }
 }
 
+// Thread per vertex.  Bucket by a bound on the distinct neighbours (X_n, and
+// the graph's vertex count): single pass in the small table (bound <=
+// load16/16 of it), single pass in the big table, or multipass; +4
+// when the distinct-axon bound can bind for n (ax_n + level max > Delta), so
+// the shared inbound count must be accumulated.  Vertices with X_n = 0 have
+// no neighbour and are in no list.
 __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
                               const int64_t* __restrict__ voff,
                               const GraphConst* __restrict__ gc, Buckets b, int64_t maxV,
@@ -151,8 +149,11 @@ __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
       // no neighbour, or no vertex of this graph has a candidate any more
       if (x > 0 && !G.done) {
         const bool ov = (int64_t)L.ax[v] + G.max_ax > G.delta;
-        if (x <= (int64_t)kSmallSlots * load16 / 16) bk = 0;
-        else if (x <= (int64_t)(ov ? kBigSlotsOv : kBigSlots) * load16 / 16) bk = 1;
+        // distinct neighbours: at most the visits, and at most the other
+        // vertices of the graph (coarse levels revisit few super-nodes often)
+        const int64_t dist = x < (int64_t)G.nverts - 1 ? x : (int64_t)G.nverts - 1;
+        if (dist <= (int64_t)kSmallSlots * load16 / 16) bk = 0;
+        else if (dist <= (int64_t)(ov ? kBigSlotsOv : kBigSlots) * load16 / 16) bk = 1;
         else bk = (voff[v + 1] - voff[v] <= kMetaDeg) ? 2 : 3;
         if (ov) bk += 4;
       }
@@ -189,7 +190,7 @@ void expansion_and_buckets(const LevelView& L, const int64_t* voff, const uint32
                            int64_t maxV, int64_t* xn, GraphConst* gc, int32_t n_graphs,
                            Buckets b, Tuning t, hipStream_t s) {
   reset_maxima_kernel<<<1, 256, 0, s>>>(gc, n_graphs, b.count);
-  expansion_kernel<<<grid_for(maxV, 256, 16384), 256, 0, s>>>(L, voff, vinc, xn, gc, b, maxV);
+  expansion_kernel<<<grid_for(maxV, 4, 16384), 256, 0, s>>>(L, voff, vinc, xn, gc, b, maxV);
   bucket_kernel<<<grid_for(maxV, 256, 16384), 256, 0, s>>>(L, xn, voff, gc, b, maxV,
                                                           t.load16);
 }
