@@ -215,19 +215,54 @@ __global__ __launch_bounds__(THREADS) void score_block_kernel(ScoreArgs a, int b
       uint32_t cap = 64;
       while (cap < 2 * (uint64_t)dist && cap < (uint32_t)SLOTS) cap <<= 1;
       const int shift = 32 - log2_pow2(cap);
-      for (int64_t j = wid; j < v.deg; j += NW) {
-        const uint32_t ent = a.vinc[v.beg + j];
-        const uint32_t e = ent & kIdMask;
-        const int64_t s0 = a.L.eoff[e], e0 = a.L.eoff[e + 1];
-        const uint32_t wt = (uint32_t)a.L.w[e];
-        const bool dn = OV && (ent & kDst);
-        const int32_t mu = dn ? a.L.mult[e] : 0;
-        for (int64_t p = s0 + lane; p < e0; p += kWave) {
-          const uint32_t pin = a.L.pins[p];
-          const uint32_t id = pin & kIdMask;
-          if (id != n) {
-            uint32_t h = table_add(table, cap - 1, shift, id, wt, a.err);
-            if (dn && (pin & kDst) && h != kNoSlot) atomicAdd(&ovtab[h & kIdMask], (uint32_t)mu);
+      // A wave takes 64 incidence entries at a time and sweeps the
+      // concatenation of their pins 64 at a time (coarse hyperedges are
+      // short, so a hyperedge per wave would leave most lanes idle).  Lane
+      // l holds entry l's offset, length and prefix; a pin finds its entry
+      // by a binary search over the lanes' prefixes.
+      for (int64_t j0 = (int64_t)wid * kWave; j0 < v.deg; j0 += (int64_t)NW * kWave) {
+        const int64_t j = j0 + lane;
+        int64_t s0 = 0;
+        int32_t len = 0, mu = 0;
+        uint32_t wt = 0;
+        if (j < v.deg) {
+          const uint32_t ent = a.vinc[v.beg + j];
+          const uint32_t e = ent & kIdMask;
+          s0 = a.L.eoff[e];
+          len = (int32_t)(a.L.eoff[e + 1] - s0);
+          wt = (uint32_t)a.L.w[e];
+          mu = (OV && (ent & kDst)) ? a.L.mult[e] : 0;
+        }
+        int32_t inc = len;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+          const int32_t o = __shfl_up(inc, d, kWave);
+          inc += lane >= d ? o : 0;
+        }
+        const int32_t excl = inc - len;
+        const int32_t total = __builtin_amdgcn_readlane(inc, kWave - 1);
+        for (int32_t c = 0; c < total; c += kWave) {  // wave-uniform
+          const int32_t q = c + lane;
+          // last lane whose prefix is <= q (lanes past the list hold the
+          // total, which no q reaches; no incident hyperedge is empty)
+          int l = 0;
+#pragma unroll
+          for (int step = kWave / 2; step > 0; step >>= 1) {
+            const int32_t ex = __shfl(excl, l + step, kWave);
+            l = ex <= q ? l + step : l;
+          }
+          const int64_t base = __shfl(s0, l, kWave);
+          const int32_t off = q - __shfl(excl, l, kWave);
+          const uint32_t wl = (uint32_t)__shfl((int32_t)wt, l, kWave);
+          const int32_t ml = OV ? __shfl(mu, l, kWave) : 0;
+          if (q < total) {
+            const uint32_t pin = a.L.pins[base + off];
+            const uint32_t id = pin & kIdMask;
+            if (id != n) {
+              const uint32_t h = table_add(table, cap - 1, shift, id, wl, a.err);
+              if (OV && ml && (pin & kDst) && h != kNoSlot)
+                atomicAdd(&ovtab[h & kIdMask], (uint32_t)ml);
+            }
           }
         }
       }
