@@ -118,23 +118,48 @@ __global__ void compose_kernel(const int64_t* __restrict__ pool_n, const int32_t
 }
 
 // First and last vertex and hyperedge of every graph in the current level.
+// Graphs are contiguous, so a wave usually sees one graph: it reduces its
+// range first and makes one atomic per bound.
+__device__ inline void wave_range(int g, int32_t x, bool ok, int32_t* mn, int32_t* mx) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g0 = __builtin_amdgcn_readfirstlane(g);
+  if (__ballot(ok && g != g0) == 0) {  // wave-uniform
+    int32_t lo = ok ? x : 0x7FFFFFFF, hi = ok ? x : -1;
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+      const int32_t a = __shfl_xor(lo, d, kWave), b = __shfl_xor(hi, d, kWave);
+      lo = a < lo ? a : lo;
+      hi = b > hi ? b : hi;
+    }
+    if (lane == 0 && hi >= 0) {
+      atomicMin(&mn[g0], lo);
+      atomicMax(&mx[g0], hi);
+    }
+  } else if (ok) {
+    atomicMin(&mn[g], x);
+    atomicMax(&mx[g], x);
+  }
+}
+
 __global__ void ranges_kernel(const Dims* __restrict__ d, const int64_t* __restrict__ eoff,
                               const uint32_t* __restrict__ pins, const int32_t* __restrict__ gid,
                               int32_t* __restrict__ vmin, int32_t* __restrict__ vmax,
                               int32_t* __restrict__ emin, int32_t* __restrict__ emax) {
-  int64_t V = d->V, E = d->E;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = i; v < V; v += stride) {
-    int32_t g = gid[v];
-    atomicMin(&vmin[g], (int32_t)v);
-    atomicMax(&vmax[g], (int32_t)v);
+  const int64_t V = d->V, E = d->E;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t start = (int64_t)blockIdx.x * blockDim.x +
+                        __builtin_amdgcn_readfirstlane(threadIdx.x & ~(kWave - 1));
+  for (int64_t base = start; base < V; base += stride) {  // wave-uniform
+    const int64_t v = base + lane;
+    const bool ok = v < V;
+    wave_range(ok ? gid[v] : -1, (int32_t)v, ok, vmin, vmax);
   }
-  for (int64_t e = i; e < E; e += stride) {
-    if (eoff[e + 1] == eoff[e]) continue;
-    int32_t g = gid[pins[eoff[e]] & kIdMask];
-    atomicMin(&emin[g], (int32_t)e);
-    atomicMax(&emax[g], (int32_t)e);
+  for (int64_t base = start; base < E; base += stride) {  // wave-uniform
+    const int64_t e = base + lane;
+    bool ok = e < E && eoff[e + 1] > eoff[e];
+    const int g = ok ? gid[pins[eoff[e]] & kIdMask] : -1;
+    wave_range(g, (int32_t)e, ok, emin, emax);
   }
 }
 
@@ -227,6 +252,9 @@ struct hg_batch {
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   Tuning captured_tuning;
   int levels_run = 0;
+  int64_t version = 0;        // bumped whenever the level changes
+  int64_t ranges_version = -1;
+  std::vector<int32_t> rv_min, rv_max, re_min, re_max;  // ranges of `ranges_version`
 };
 
 namespace {
@@ -321,6 +349,13 @@ void drop_graphs(hg_batch* b) {
 // Current vertex and hyperedge ranges of every slot (synchronous).
 int read_ranges(hg_batch* b, std::vector<int32_t>& vmn, std::vector<int32_t>& vmx,
                 std::vector<int32_t>& emn, std::vector<int32_t>& emx) {
+  if (b->ranges_version == b->version) {
+    vmn = b->rv_min;
+    vmx = b->rv_max;
+    emn = b->re_min;
+    emx = b->re_max;
+    return HG_OK;
+  }
   hipStream_t s = b->ctx->stream;
   const int G = b->max_graphs;
   fill_i32(b->vmin, 0x7FFFFFFF, G, s);
@@ -341,6 +376,11 @@ int read_ranges(hg_batch* b, std::vector<int32_t>& vmn, std::vector<int32_t>& vm
   if (e == hipSuccess) e = hipMemcpyAsync(emx.data(), b->emax, G * 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(b->ctx, e, "reading the batch ranges");
+  b->rv_min = vmn;
+  b->rv_max = vmx;
+  b->re_min = emn;
+  b->re_max = emx;
+  b->ranges_version = b->version;
   return HG_OK;
 }
 
@@ -453,6 +493,7 @@ int hg_batch_add_graph(hg_batch* b, const hg_level* lvl, const hg_limits* lim, i
   }
   set_dims_dev_kernel<<<1, 1, 0, s>>>(L.dims, h.V + Vg, h.E + Eg, h.P + Pg);
   set_slot_kernel<<<1, 1, 0, s>>>(b->gc, b->nlev, b->active, g, *lim, 0);
+  b->version += 1;
   b->slots[g].state = kLive;
   b->slots[g].pool_off = b->pool_used;
   b->slots[g].v0 = Vg;
@@ -509,6 +550,7 @@ int hg_batch_step(hg_batch* b, int32_t n_levels, int32_t use_graph) {
     }
     b->cur = 1 - from;
     b->levels_run += 1;
+    b->version += 1;
   }
   return HG_OK;
 }
@@ -634,6 +676,7 @@ int hg_batch_compact(hg_batch* b) {
       b->slots[g] = SlotInfo{};
     }
   b->cur = 1 - b->cur;
+  b->version += 1;
   return launch_status(c);
 }
 
