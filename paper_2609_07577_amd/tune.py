@@ -11,6 +11,7 @@ candidate setting and keeps the fastest.
 from __future__ import annotations
 
 import itertools
+import sys
 import time
 
 import torch
@@ -42,7 +43,8 @@ def autotune(ctx, levels, limits, loads=LOADS, fills=FILLS, verbose=False) -> di
         t = time_levels(ctx, levels, limits, repeats=2)
         results.append((t, load, fill))
         if verbose:
-            print(f"[tune] load16={load} fill16={fill}: {1e3 * t:.2f} ms", flush=True)
+            print(f"[tune] load16={load} fill16={fill}: {1e3 * t:.2f} ms", file=sys.stderr,
+                  flush=True)
     t, load, fill = min(results)
     ctx.set_tuning(load, fill)
     torch.cuda.synchronize()
