@@ -44,29 +44,147 @@ __global__ void set_slot_kernel(GraphConst* gc, int32_t* nlev, int32_t* active, 
   active[slot] = 0;
 }
 
-// Appends graph pieces at the end of the union: offsets shifted by the pins
-// before it, vertex ids by the vertices before it (flags kept).
-__global__ void append_offsets_kernel(const int64_t* __restrict__ src, int64_t n, int64_t shift,
-                                      int64_t* __restrict__ dst) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) dst[i] = src[i] + shift;
-}
-
-__global__ void append_pins_kernel(const uint32_t* __restrict__ src, int64_t n, uint32_t shift,
-                                   uint32_t* __restrict__ dst) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) {
-    uint32_t p = src[i];
-    dst[i] = ((p & kIdMask) + shift) | (p & kDst);
+// Appends graph pieces at the end of the union, whose current sizes are read
+// from device memory (no host synchronisation): offsets shifted by the pins
+// before them, vertex ids by the vertices before them (flags kept).
+__global__ void append_level_kernel(const Dims* __restrict__ d, const int64_t* __restrict__ seoff,
+                                    const uint32_t* __restrict__ spins, const int32_t* __restrict__ sw,
+                                    const int32_t* __restrict__ smult, const int32_t* __restrict__ ssize,
+                                    const int32_t* __restrict__ ssyn, const int32_t* __restrict__ sax,
+                                    int64_t Vg, int64_t Eg, int64_t Pg, int32_t slot,
+                                    int64_t* __restrict__ eoff, uint32_t* __restrict__ pins,
+                                    int32_t* __restrict__ w, int32_t* __restrict__ mult,
+                                    int32_t* __restrict__ size, int32_t* __restrict__ syn,
+                                    int32_t* __restrict__ ax, int32_t* __restrict__ gid,
+                                    int32_t* __restrict__ part, int32_t* __restrict__ owner,
+                                    int64_t pool_off) {
+  const int64_t V = d->V, E = d->E, P = d->P;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = i0; i <= Eg; i += stride) eoff[E + i] = seoff[i] + P;
+  for (int64_t i = i0; i < Pg; i += stride) {
+    const uint32_t p = spins[i];
+    pins[P + i] = ((p & kIdMask) + (uint32_t)V) | (p & kDst);
+  }
+  for (int64_t i = i0; i < Eg; i += stride) {
+    w[E + i] = sw[i];
+    mult[E + i] = smult[i];
+  }
+  for (int64_t i = i0; i < Vg; i += stride) {
+    size[V + i] = ssize[i];
+    syn[V + i] = ssyn[i];
+    ax[V + i] = sax[i];
+    gid[V + i] = slot;
+    part[pool_off + i] = (int32_t)(V + i);
+    owner[pool_off + i] = slot;
   }
 }
 
-__global__ void iota_kernel(int32_t* __restrict__ dst, int64_t n, int32_t start) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) dst[i] = start + (int32_t)i;
+__global__ void grow_dims_kernel(Dims* d, int64_t Vg, int64_t Eg, int64_t Pg) {
+  d->V += Vg;
+  d->E += Eg;
+  d->P += Pg;
+}
+
+// ---- compaction: drop the vertices, hyperedges and pins of released graphs
+__global__ void keep_marks_kernel(const Dims* __restrict__ d, const int64_t* __restrict__ eoff,
+                                  const uint32_t* __restrict__ pins, const int32_t* __restrict__ gid,
+                                  const int32_t* __restrict__ alive, int32_t* __restrict__ keepv,
+                                  int32_t* __restrict__ keepe, int32_t* __restrict__ elen) {
+  const int64_t V = d->V, E = d->E;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = i0; v < V; v += stride) keepv[v] = alive[gid[v]];
+  for (int64_t e = i0; e < E; e += stride) {
+    const int64_t len = eoff[e + 1] - eoff[e];
+    const int32_t k = len > 0 ? alive[gid[pins[eoff[e]] & kIdMask]] : 0;
+    keepe[e] = k;
+    elen[e] = k ? (int32_t)len : 0;
+  }
+}
+
+__global__ void compact_vertices_kernel(const Dims* __restrict__ d, const int32_t* __restrict__ keepv,
+                                        const int64_t* __restrict__ vpos,
+                                        const int32_t* __restrict__ size, const int32_t* __restrict__ syn,
+                                        const int32_t* __restrict__ ax, const int32_t* __restrict__ gid,
+                                        int32_t* __restrict__ osize, int32_t* __restrict__ osyn,
+                                        int32_t* __restrict__ oax, int32_t* __restrict__ ogid) {
+  const int64_t V = d->V;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = i0; v < V; v += stride) {
+    if (!keepv[v]) continue;
+    const int64_t q = vpos[v];
+    osize[q] = size[v];
+    osyn[q] = syn[v];
+    oax[q] = ax[v];
+    ogid[q] = gid[v];
+  }
+}
+
+// A wave per hyperedge: kept hyperedges move to their new slot, their pins
+// are relabelled through the new vertex positions.
+__global__ void compact_edges_kernel(const Dims* __restrict__ d, const int64_t* __restrict__ eoff,
+                                     const uint32_t* __restrict__ pins, const int32_t* __restrict__ w,
+                                     const int32_t* __restrict__ mult, const int32_t* __restrict__ keepe,
+                                     const int64_t* __restrict__ epos, const int64_t* __restrict__ ppos,
+                                     const int64_t* __restrict__ vpos, int64_t* __restrict__ oeoff,
+                                     uint32_t* __restrict__ opins, int32_t* __restrict__ ow,
+                                     int32_t* __restrict__ omult) {
+  const int64_t E = d->E;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x / kWave) +
+                     __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  for (int64_t e = w0; e < E; e += nwaves) {  // wave-uniform
+    if (!keepe[e]) continue;
+    const int64_t q = epos[e], dst = ppos[e];
+    if (lane == 0) {
+      oeoff[q] = dst;
+      ow[q] = w[e];
+      omult[q] = mult[e];
+    }
+    const int64_t s0 = eoff[e], n = eoff[e + 1] - s0;
+    for (int64_t k = lane; k < n; k += kWave) {
+      const uint32_t p = pins[s0 + k];
+      opins[dst + k] = (uint32_t)vpos[p & kIdMask] | (p & kDst);
+    }
+  }
+}
+
+__global__ void compact_finish_kernel(const Dims* __restrict__ d, const int64_t* __restrict__ vpos,
+                                      const int64_t* __restrict__ epos,
+                                      const int64_t* __restrict__ ppos, int64_t* __restrict__ oeoff,
+                                      Dims* __restrict__ od) {
+  const int64_t V2 = vpos[d->V], E2 = epos[d->E], P2 = ppos[d->E];
+  oeoff[E2] = P2;
+  od->V = V2;
+  od->E = E2;
+  od->P = P2;
+}
+
+__global__ void pool_marks_kernel(const int64_t* __restrict__ pool_n,
+                                  const int32_t* __restrict__ owner, int32_t* __restrict__ keep) {
+  const int64_t n = *pool_n;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = i0; i < n; i += stride) keep[i] = owner[i] >= 0;
+}
+
+__global__ void pool_compact_kernel(const int64_t* __restrict__ pool_n,
+                                    const int32_t* __restrict__ keep,
+                                    const int64_t* __restrict__ pos, const int64_t* __restrict__ vpos,
+                                    const int32_t* __restrict__ part, const int32_t* __restrict__ owner,
+                                    int32_t* __restrict__ opart, int32_t* __restrict__ oowner) {
+  const int64_t n = *pool_n;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = i0; i < n; i += stride) {
+    if (!keep[i]) continue;
+    const int64_t q = pos[i];
+    opart[q] = (int32_t)vpos[part[i]];
+    oowner[q] = owner[i];
+  }
 }
 
 __global__ void set_dims_dev_kernel(Dims* d, int64_t V, int64_t E, int64_t P) {
@@ -177,23 +295,6 @@ __global__ void copy_kernel(const T* __restrict__ src, int64_t n, T* __restrict_
   for (; i < n; i += stride) dst[i] = src[i];
 }
 
-__global__ void shift_part_kernel(const int32_t* __restrict__ src, int64_t n, int32_t shift,
-                                  int32_t* __restrict__ dst) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) dst[i] = src[i] - shift;
-}
-
-__global__ void shift_pins_kernel(const uint32_t* __restrict__ src, int64_t n, uint32_t shift,
-                                  uint32_t* __restrict__ dst) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) {
-    uint32_t p = src[i];
-    dst[i] = ((p & kIdMask) - shift) | (p & kDst);
-  }
-}
-
 int blocks_for(int64_t n) { return grid_for(n, 256, 8192); }
 
 }  // namespace
@@ -252,6 +353,15 @@ struct hg_batch {
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   Tuning captured_tuning;
   int levels_run = 0;
+  // compaction scratch
+  int32_t *c_keepv = nullptr, *c_keepe = nullptr, *c_elen = nullptr, *c_alive = nullptr;
+  int32_t *c_pkeep = nullptr, *owner_tmp = nullptr;
+  int64_t *c_vpos = nullptr, *c_epos = nullptr, *c_ppos = nullptr, *c_pool = nullptr;
+  int64_t* c_partials = nullptr;
+  std::vector<int32_t> alive_h;
+  // upper bounds of the current level's sizes (exact after a compaction;
+  // levels only shrink, adds are counted in)
+  int64_t ubV = 0, ubE = 0, ubP = 0;
   int64_t version = 0;        // bumped whenever the level changes
   int64_t ranges_version = -1;
   std::vector<int32_t> rv_min, rv_max, re_min, re_max;  // ranges of `ranges_version`
@@ -290,6 +400,17 @@ void carve_batch(hg_batch* b, A& a) {
   b->owner = a.template take<int32_t>(b->capV);
   b->part_tmp = a.template take<int32_t>(b->capV);
   b->pool_n = a.template take<int64_t>(1);
+  b->c_keepv = a.template take<int32_t>(b->capV);
+  b->c_vpos = a.template take<int64_t>(b->capV + 1);
+  b->c_keepe = a.template take<int32_t>(b->capE);
+  b->c_elen = a.template take<int32_t>(b->capE);
+  b->c_epos = a.template take<int64_t>(b->capE + 1);
+  b->c_ppos = a.template take<int64_t>(b->capE + 1);
+  b->c_alive = a.template take<int32_t>(b->max_graphs);
+  b->c_pkeep = a.template take<int32_t>(b->capV);
+  b->c_pool = a.template take<int64_t>(b->capV + 1);
+  b->owner_tmp = a.template take<int32_t>(b->capV);
+  b->c_partials = a.template take<int64_t>(scan_partials_size());
   CoarsenScratch<A> cs;
   cs.carve(a, b->capV, b->capE, b->capP);
   ContractLayout<A> ks;
@@ -462,37 +583,28 @@ int hg_batch_add_graph(hg_batch* b, const hg_level* lvl, const hg_limits* lim, i
       break;
     }
   if (g < 0) return fail(c, HG_ERR_CAPACITY, "all %d graph slots are in use", b->max_graphs);
-  Dims h;
-  rc = read_dims(b, &h);
-  if (rc) return rc;
   const int64_t Vg = lvl->n_vertices, Eg = lvl->n_edges, Pg = lvl->n_pins;
-  if (h.V + Vg > b->capV || h.E + Eg > b->capE || h.P + Pg > b->capP)
+  if (b->ubV + Vg > b->capV || b->ubE + Eg > b->capE || b->ubP + Pg > b->capP)
     return fail(c, HG_ERR_CAPACITY,
-                "batch level full: (%lld, %lld, %lld) + (%lld, %lld, %lld) above capacity",
-                (long long)h.V, (long long)h.E, (long long)h.P, (long long)Vg, (long long)Eg,
-                (long long)Pg);
+                "batch level full: at most (%lld, %lld, %lld) + (%lld, %lld, %lld) above "
+                "capacity; compact first",
+                (long long)b->ubV, (long long)b->ubE, (long long)b->ubP, (long long)Vg,
+                (long long)Eg, (long long)Pg);
   if (b->pool_used + Vg > b->capV)
     return fail(c, HG_ERR_CAPACITY, "original-vertex pool full; release or compact first");
   hipStream_t s = c->stream;
   LevelBuf& L = b->buf[b->cur];
-  append_offsets_kernel<<<blocks_for(Eg + 1), 256, 0, s>>>(lvl->edge_offsets, Eg + 1, h.P,
-                                                           L.eoff + h.E);
-  if (Pg > 0)
-    append_pins_kernel<<<blocks_for(Pg), 256, 0, s>>>(lvl->pins, Pg, (uint32_t)h.V, L.pins + h.P);
-  if (Eg > 0) {
-    copy_kernel<int32_t><<<blocks_for(Eg), 256, 0, s>>>(lvl->edge_weight, Eg, L.w + h.E);
-    copy_kernel<int32_t><<<blocks_for(Eg), 256, 0, s>>>(lvl->edge_mult, Eg, L.mult + h.E);
-  }
-  if (Vg > 0) {
-    copy_kernel<int32_t><<<blocks_for(Vg), 256, 0, s>>>(lvl->v_size, Vg, L.size + h.V);
-    copy_kernel<int32_t><<<blocks_for(Vg), 256, 0, s>>>(lvl->v_syn, Vg, L.syn + h.V);
-    copy_kernel<int32_t><<<blocks_for(Vg), 256, 0, s>>>(lvl->v_axons, Vg, L.ax + h.V);
-    fill_i32(L.gid + h.V, g, Vg, s);
-    iota_kernel<<<blocks_for(Vg), 256, 0, s>>>(b->part + b->pool_used, Vg, (int32_t)h.V);
-    fill_i32(b->owner + b->pool_used, g, Vg, s);
-  }
-  set_dims_dev_kernel<<<1, 1, 0, s>>>(L.dims, h.V + Vg, h.E + Eg, h.P + Pg);
+  // offsets and ids come from the device sizes: no host synchronisation
+  const int64_t m = std::max(Vg, std::max(Eg + 1, Pg));
+  append_level_kernel<<<blocks_for(m), 256, 0, s>>>(
+      L.dims, lvl->edge_offsets, lvl->pins, lvl->edge_weight, lvl->edge_mult, lvl->v_size,
+      lvl->v_syn, lvl->v_axons, Vg, Eg, Pg, g, L.eoff, L.pins, L.w, L.mult, L.size, L.syn, L.ax,
+      L.gid, b->part, b->owner, b->pool_used);
+  grow_dims_kernel<<<1, 1, 0, s>>>(L.dims, Vg, Eg, Pg);
   set_slot_kernel<<<1, 1, 0, s>>>(b->gc, b->nlev, b->active, g, *lim, 0);
+  b->ubV += Vg;
+  b->ubE += Eg;
+  b->ubP += Pg;
   b->version += 1;
   b->slots[g].state = kLive;
   b->slots[g].pool_off = b->pool_used;
@@ -608,66 +720,50 @@ int hg_batch_compact(hg_batch* b) {
   if (!b) return HG_ERR_INVALID_ARG;
   hg_ctx* c = b->ctx;
   hipStream_t s = c->stream;
-  std::vector<int32_t> vmn, vmx, emn, emx;
-  int rc = read_ranges(b, vmn, vmx, emn, emx);
-  if (rc) return rc;
-  std::vector<int64_t> eoff_h;
-  // graphs that stay, in union order
-  std::vector<int32_t> keep;
+  // graphs that stay: running and reported-but-unread ones
+  b->alive_h.assign(b->max_graphs, 0);
   for (int32_t g = 0; g < b->max_graphs; ++g)
-    if (b->slots[g].state == kLive || b->slots[g].state == kReported) keep.push_back(g);
-  std::sort(keep.begin(), keep.end(), [&](int32_t x, int32_t y) { return vmn[x] < vmn[y]; });
+    b->alive_h[g] = (b->slots[g].state == kLive || b->slots[g].state == kReported) ? 1 : 0;
+  hipError_t e = hipMemcpyAsync(b->c_alive, b->alive_h.data(), 4 * (size_t)b->max_graphs,
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(c, e, "uploading the kept graphs");
   const LevelBuf& F = b->buf[b->cur];
   const LevelBuf& T = b->buf[1 - b->cur];
-  int64_t V = 0, E = 0, P = 0, pool = 0;
-  for (int32_t g : keep) {
-    SlotInfo& si = b->slots[g];
-    const int64_t vs = vmn[g], vn = vmx[g] >= vmn[g] ? (int64_t)vmx[g] - vmn[g] + 1 : 0;
-    const int64_t es = emn[g], en = emx[g] >= emn[g] ? (int64_t)emx[g] - emn[g] + 1 : 0;
-    int64_t ps = 0, pe = 0;
-    if (en > 0) {
-      int64_t pr[2];
-      hipError_t e = hipMemcpyAsync(&pr[0], F.eoff + es, 8, hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(&pr[1], F.eoff + es + en, 8, hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (e != hipSuccess) return hip_fail(c, e, "reading hyperedge offsets");
-      ps = pr[0];
-      pe = pr[1];
-    }
-    const int64_t pn = pe - ps;
-    if (vn > 0) {
-      copy_kernel<int32_t><<<blocks_for(vn), 256, 0, s>>>(F.size + vs, vn, T.size + V);
-      copy_kernel<int32_t><<<blocks_for(vn), 256, 0, s>>>(F.syn + vs, vn, T.syn + V);
-      copy_kernel<int32_t><<<blocks_for(vn), 256, 0, s>>>(F.ax + vs, vn, T.ax + V);
-      copy_kernel<int32_t><<<blocks_for(vn), 256, 0, s>>>(F.gid + vs, vn, T.gid + V);
-    }
-    if (en > 0) {
-      append_offsets_kernel<<<blocks_for(en), 256, 0, s>>>(F.eoff + es, en, P - ps, T.eoff + E);
-      copy_kernel<int32_t><<<blocks_for(en), 256, 0, s>>>(F.w + es, en, T.w + E);
-      copy_kernel<int32_t><<<blocks_for(en), 256, 0, s>>>(F.mult + es, en, T.mult + E);
-    }
-    if (pn > 0)
-      shift_pins_kernel<<<blocks_for(pn), 256, 0, s>>>(F.pins + ps, pn, (uint32_t)(vs - V),
-                                                       T.pins + P);
-    if (si.v0 > 0) {
-      shift_part_kernel<<<blocks_for(si.v0), 256, 0, s>>>(b->part + si.pool_off, si.v0,
-                                                          (int32_t)(vs - V), b->part_tmp + pool);
-      fill_i32(b->owner + pool, si.state == kLive || si.state == kReported ? g : -1, si.v0, s);
-    }
-    si.pool_off = pool;
-    V += vn;
-    E += en;
-    P += pn;
-    pool += si.v0;
+  const int64_t m = std::max(b->capV, b->capE);
+  keep_marks_kernel<<<blocks_for(m), 256, 0, s>>>(F.dims, F.eoff, F.pins, F.gid, b->c_alive,
+                                                  b->c_keepv, b->c_keepe, b->c_elen);
+  exclusive_scan_i32(b->c_keepv, b->c_vpos, &F.dims->V, b->capV, b->c_partials, s);
+  exclusive_scan_i32(b->c_keepe, b->c_epos, &F.dims->E, b->capE, b->c_partials, s);
+  exclusive_scan_i32(b->c_elen, b->c_ppos, &F.dims->E, b->capE, b->c_partials, s);
+  compact_vertices_kernel<<<blocks_for(b->capV), 256, 0, s>>>(
+      F.dims, b->c_keepv, b->c_vpos, F.size, F.syn, F.ax, F.gid, T.size, T.syn, T.ax, T.gid);
+  compact_edges_kernel<<<grid_for(b->capE, 4, 16384), 256, 0, s>>>(
+      F.dims, F.eoff, F.pins, F.w, F.mult, b->c_keepe, b->c_epos, b->c_ppos, b->c_vpos, T.eoff,
+      T.pins, T.w, T.mult);
+  compact_finish_kernel<<<1, 1, 0, s>>>(F.dims, b->c_vpos, b->c_epos, b->c_ppos, T.eoff, T.dims);
+  // the part pool keeps the unreleased graphs, in order, relabelled
+  pool_marks_kernel<<<blocks_for(b->capV), 256, 0, s>>>(b->pool_n, b->owner, b->c_pkeep);
+  exclusive_scan_i32(b->c_pkeep, b->c_pool, b->pool_n, b->capV, b->c_partials, s);
+  pool_compact_kernel<<<blocks_for(b->capV), 256, 0, s>>>(b->pool_n, b->c_pkeep, b->c_pool,
+                                                          b->c_vpos, b->part, b->owner,
+                                                          b->part_tmp, b->owner_tmp);
+  std::vector<int32_t> order;
+  for (int32_t g = 0; g < b->max_graphs; ++g)
+    if (b->alive_h[g]) order.push_back(g);
+  std::sort(order.begin(), order.end(),
+            [&](int32_t x, int32_t y) { return b->slots[x].pool_off < b->slots[y].pool_off; });
+  int64_t pool = 0;
+  for (int32_t g : order) {
+    b->slots[g].pool_off = pool;
+    pool += b->slots[g].v0;
   }
-  // the part pool moves to the front in the same order
-  if (pool > 0) copy_kernel<int32_t><<<blocks_for(pool), 256, 0, s>>>(b->part_tmp, pool, b->part);
+  if (pool > 0) {
+    copy_kernel<int32_t><<<blocks_for(pool), 256, 0, s>>>(b->part_tmp, pool, b->part);
+    copy_kernel<int32_t><<<blocks_for(pool), 256, 0, s>>>(b->owner_tmp, pool, b->owner);
+  }
   if (b->pool_used > pool) fill_i32(b->owner + pool, -1, b->pool_used - pool, s);
   b->pool_used = pool;
   set_i64_kernel<<<1, 1, 0, s>>>(b->pool_n, pool);
-  set_i64_kernel<<<1, 1, 0, s>>>(T.eoff + E, P);
-  set_dims_dev_kernel<<<1, 1, 0, s>>>(T.dims, V, E, P);
   // released slots become free
   hg_limits none{0, 0, 0};
   for (int32_t g = 0; g < b->max_graphs; ++g)
@@ -677,7 +773,16 @@ int hg_batch_compact(hg_batch* b) {
     }
   b->cur = 1 - b->cur;
   b->version += 1;
-  return launch_status(c);
+  int rc = launch_status(c);
+  if (rc) return rc;
+  // exact sizes again for admission
+  Dims h;
+  rc = read_dims(b, &h);
+  if (rc) return rc;
+  b->ubV = h.V;
+  b->ubE = h.E;
+  b->ubP = h.P;
+  return HG_OK;
 }
 
 int hg_batch_sizes(hg_batch* b, int64_t* sizes) {
@@ -689,6 +794,9 @@ int hg_batch_sizes(hg_batch* b, int64_t* sizes) {
   sizes[1] = h.E;
   sizes[2] = h.P;
   sizes[3] = b->pool_used;
+  b->ubV = h.V;  // exact again
+  b->ubE = h.E;
+  b->ubP = h.P;
   return HG_OK;
 }
 

@@ -29,9 +29,7 @@ class Server:
         self.compact_every = compact_every
         self.queue = collections.deque()  # (request id, level, limits, arrival time)
         self.running = {}                  # slot -> (request id, arrival time, pins)
-        self.used = [0, 0, 0, 0]           # slots, V, E, P held (including released)
-        self.pool = 0                      # original vertices of unreleased requests
-        self.released = 0
+        self.released = 0                  # read out since the last compaction
 
     def bytes(self) -> int:
         return self.batch.bytes()
@@ -39,41 +37,31 @@ class Server:
     def submit(self, rid, level: hg.DeviceLevel, limits, arrival: float):
         self.queue.append((rid, level, limits, arrival))
 
-    def _fits(self, L) -> bool:
-        slots, V, E, P = self.used
-        return (slots < self.cap[0] and V + L.V <= self.cap[1] and E + L.E <= self.cap[2]
-                and P + L.P <= self.cap[3] and self.pool + L.V <= self.cap[1])
-
     def _admit(self):
+        """Admit queued requests in arrival order while the batch has room
+        (the library checks slots, vertices, hyperedges and pins against the
+        footprint fixed at creation and reports HG_ERR_CAPACITY)."""
         admitted = 0
         while self.queue:
             rid, L, lim, arr = self.queue[0]
-            if not self._fits(L):
+            try:
+                slot = self.batch.add(L, lim)
+            except hg.HgError as e:
+                if e.code != 3:
+                    raise
                 if self.released:
                     self._compact()
-                    if self._fits(L):
-                        continue
+                    continue
                 if not self.running:
                     raise ValueError(f"request {rid} is larger than the server's capacity")
                 break
-            slot = self.batch.add(L, lim)
             self.queue.popleft()
-            self.running[slot] = (rid, arr, L.P, L.V)
-            self.pool += L.V
-            self.used[0] += 1
-            self.used[1] += L.V
-            self.used[2] += L.E
-            self.used[3] += L.P
+            self.running[slot] = (rid, arr, L.P)
             admitted += 1
         return admitted
 
     def _compact(self):
         self.batch.compact()
-        V, E, P, pool = self.batch.sizes()
-        # after compaction the level holds only unreleased requests, at their
-        # current (coarsened) sizes
-        self.used = [len(self.running), V, E, P]
-        self.pool = pool
         self.released = 0
 
     def step(self):
@@ -87,7 +75,7 @@ class Server:
         now = time.perf_counter()
         out = []
         for s in done:
-            rid, arr, pins, _v0 = self.running.pop(s)
+            rid, arr, pins = self.running.pop(s)
             part, n_parts, n_levels = self.batch.result(s)
             out.append((rid, arr, now, part, n_parts, n_levels, pins))
             self.released += 1
