@@ -382,9 +382,9 @@ __global__ __launch_bounds__(THREADS) void score_block_kernel(ScoreArgs a, int b
 // of up to kBatch of its segments before it inserts any of them, and while
 // it inserts a chunk whose last pin still lies in the range it already
 // loads the next one.  Per chunk of 64 pins the work is a divergent probe
-// loop with one exit test, two ballots and, only when new entries appeared,
-// one single-lane LDS atomic that both publishes the wave's new entries and
-// returns the table fill.
+// loop with one exit test and two ballots; after every SLOTS/128 new entries
+// of a wave, one single-lane LDS atomic both publishes them and returns the
+// table fill.
 template <int THREADS, int SLOTS, bool OV>
 __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int bucket,
                                                               int64_t maxV) {
@@ -392,7 +392,10 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
   constexpr int kBatch = 8;
   constexpr int MAXFILL = SLOTS * 5 / 8;
   constexpr uint32_t kSent = 0x7FFFFFFFu;  // id above every range end, flag clear
-  static_assert(MAXFILL + 2 * NW * kWave < SLOTS, "table must never fill up");
+  // a wave publishes its new entries to the fill count every kPublish of
+  // them, so the table holds at most MAXFILL + NW * (kPublish + 64) entries
+  constexpr int kPublish = SLOTS / 128;
+  static_assert(MAXFILL + NW * (kPublish + kWave) < SLOTS, "table must never fill up");
   __shared__ uint64_t table[SLOTS];
   __shared__ uint32_t ovtab[OV ? SLOTS : 1];
   __shared__ int64_t m_start[kMetaDeg];
@@ -479,6 +482,8 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
       if (tid == 0) s_fill = 0;
       __syncthreads();
       bool over = false;
+      bool lost = false;    // a probe sequence reached its bound (never, if correct)
+      int32_t pending = 0;  // new entries of this wave not yet published
       for (int32_t j0 = wid; j0 < deg && !over; j0 += kBatch * NW) {
         // straight-line code, so that all kBatch loads are in flight at once
         uint32_t pin[kBatch];
@@ -515,7 +520,7 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
             if (cont) nxt = a.L.pins[pn < end ? pn : end - 1];  // wave-uniform
             const uint32_t id = cur & kIdMask;
             const bool in = id < (uint64_t)hi;
-            bool fresh = false, lost = false;
+            bool fresh = false;
             if (in && id != n) {
               // plain divergent probe loop with a single exit: a lane leaves
               // as soon as its slot is found, and the loop ends when no lane
@@ -537,19 +542,21 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
               }
               fresh = old == kEmpty;
               const bool hit = !fresh && (uint32_t)(old >> 32) == id;
-              lost = !fresh && !hit;
-              if (hit) atomicAdd((unsigned long long*)&table[h], (unsigned long long)wt);
-              if (OV && mu && (cur & kDst) && !lost) atomicAdd(&ovtab[h], (uint32_t)mu);
+              lost |= !fresh && !hit;
+              // unconditional: a lane that did not hit adds 0 to its own new
+              // entry (cheaper than another divergent region)
+              atomicAdd((unsigned long long*)&table[h], (unsigned long long)(hit ? wt : 0u));
+              if (OV && mu && (cur & kDst) && (fresh || hit)) atomicAdd(&ovtab[h], (uint32_t)mu);
             }
-            if (__ballot(lost) != 0 && lane == 0) atomicOr(a.err, kErrTableFull);
             const int cnt = __popcll(__ballot(in));
-            const int nnew = __popcll(__ballot(fresh));
-            if (nnew > 0) {  // wave-uniform
-              // one lane adds the wave's new entries (a lane-varying operand
-              // would make the compiler scan over all lanes)
+            pending += __popcll(__ballot(fresh));
+            if (pending >= kPublish) {  // wave-uniform
+              // one lane publishes the wave's new entries (a lane-varying
+              // operand would make the compiler scan over all lanes)
               int32_t old = 0;
-              if (lane == 0) old = atomicAdd(&s_fill, nnew);
-              over = __builtin_amdgcn_readlane(old, 0) + nnew > MAXFILL;
+              if (lane == 0) old = atomicAdd(&s_fill, pending);
+              over = __builtin_amdgcn_readlane(old, 0) + pending > MAXFILL;
+              pending = 0;
             }
             c += cnt;
             if (!cont || over) break;
@@ -557,6 +564,12 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
           }
           m_tent[j] = (int32_t)(c - st);  // every lane stores the same value
         }
+      }
+      if (__ballot(lost) != 0 && lane == 0) atomicOr(a.err, kErrTableFull);
+      if (pending > 0) {  // wave-uniform
+        int32_t old = 0;
+        if (lane == 0) old = atomicAdd(&s_fill, pending);
+        over = over || __builtin_amdgcn_readlane(old, 0) + pending > MAXFILL;
       }
       s_wover[wid] = over ? 1 : 0;  // every lane stores the same value
       __syncthreads();
