@@ -197,3 +197,39 @@ def test_contract_general_partition_vs_brute():
             assert c.size[b] == orig.size(mem)
             assert c.syn[b] == orig.synapses(mem)
             assert c.ax[b] == orig.axons(mem)
+
+
+def _union(graphs):
+    """Graphs side by side: vertex ids and pin offsets shifted, flags kept."""
+    eoff, pins, w = [np.zeros(1, np.int64)], [], []
+    V = P = 0
+    for g in graphs:
+        eoff.append(np.asarray(g.eoff[1:], np.int64) + P)
+        p = np.asarray(g.pins, np.uint32)
+        pins.append(((p & 0x7FFFFFFF) + V) | (p & 0x80000000))
+        w.append(np.asarray(g.weight, np.int32))
+        V += g.n_vertices
+        P += g.n_pins
+    return synth.Level0(V, np.concatenate(eoff), np.concatenate(pins).astype(np.uint32),
+                        np.concatenate(w), "union")
+
+
+def test_union_of_disjoint_graphs_is_separate_runs():
+    """Graphs that share no hyperedge never interact (Eq. 12 scores only
+    pairs inside a hyperedge; Eq. 13 only follows candidate arcs; G_P keeps
+    vertex and hyperedge order), so coarsening their union gives every graph
+    the partition of its own hierarchy, and the union needs as many levels
+    as its deepest graph.  This is what a batch of graphs relies on."""
+    lim = synth.Limits(24, 400, 60)
+    graphs = [synth.uniform(s, n, 1, 9) for s, n in ((1, 150), (2, 90), (3, 200))]
+    graphs.append(synth.tiny_random(4, 30))
+    alone = [oracle.hierarchy(g, lim) for g in graphs]
+    u = oracle.hierarchy(_union(graphs), lim)
+    assert u.n_levels == max(h.n_levels for h in alone)
+    part = u.final_partition()
+    base = 0
+    for g, h in zip(graphs, alone):
+        mine = part[base:base + g.n_vertices]
+        # the union numbers the graph's super-nodes after those of earlier graphs
+        np.testing.assert_array_equal(mine - mine.min(), h.final_partition())
+        base += g.n_vertices
