@@ -474,6 +474,7 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
     int passes = 0;
     while (lo < hi_all) {
       const int64_t hi = lo + width < hi_all ? lo + width : hi_all;
+      const uint32_t hi32 = (uint32_t)hi;  // ids are below 2^31
       __syncthreads();  // previous pass drained / cleared, flags read, cursors committed
       if (++passes > kMaxPasses) {
         if (tid == 0) atomicOr(a.err, kErrPassLimit);
@@ -485,17 +486,19 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
       bool lost = false;    // a probe sequence reached its bound (never, if correct)
       int32_t pending = 0;  // new entries of this wave not yet published
       for (int32_t j0 = wid; j0 < deg && !over; j0 += kBatch * NW) {
-        // straight-line code, so that all kBatch loads are in flight at once
+        // straight-line code, so that all kBatch loads are in flight at once;
+        // positions are 32-bit offsets from each hyperedge's first pin
         uint32_t pin[kBatch];
         bool ok[kBatch];
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
           const int32_t j = j0 + b * NW;
           const int32_t js = j < deg ? j : j0;
-          const int64_t st = m_start[js], end = st + m_len[js];
-          const int64_t p = st + m_cur[js] + lane;
-          ok[b] = j < deg && p < end;
-          pin[b] = a.L.pins[p < end ? p : end - 1];  // an incident hyperedge is never empty
+          const uint32_t* seg = a.L.pins + m_start[js];
+          const int32_t len = m_len[js];
+          const int32_t p = m_cur[js] + lane;
+          ok[b] = j < deg && p < len;
+          pin[b] = seg[p < len ? p : len - 1];  // an incident hyperedge is never empty
         }
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) pin[b] = ok[b] ? pin[b] : kSent;
@@ -503,23 +506,24 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
         for (int b = 0; b < kBatch; ++b) {
           const int32_t j = j0 + b * NW;
           if (j >= deg || over) break;  // wave-uniform
-          const int64_t st = m_start[j], end = st + m_len[j];
+          const uint32_t* seg = a.L.pins + m_start[j];
+          const int32_t len = m_len[j];
           const uint32_t wt = (uint32_t)m_w[j];
           const int32_t mu = OV ? m_mult[j] : 0;
-          int64_t c = st + m_cur[j];
+          int32_t c = m_cur[j];
           uint32_t cur = pin[b];
           while (true) {
             // the segment goes on past this chunk iff its last lane holds a
             // pin below the range end (pins ascend; a lane past the
             // hyperedge holds the sentinel)
             const uint32_t last = __builtin_amdgcn_readlane(cur, kWave - 1);
-            const bool cont = (last & kIdMask) < (uint64_t)hi && c + kWave < end;
+            const bool cont = (last & kIdMask) < hi32 && c + kWave < len;
             // issued before the inserts so that its latency hides behind them
-            const int64_t pn = c + kWave + lane;
+            const int32_t pn = c + kWave + lane;
             uint32_t nxt = kSent;
-            if (cont) nxt = a.L.pins[pn < end ? pn : end - 1];  // wave-uniform
+            if (cont) nxt = seg[pn < len ? pn : len - 1];  // wave-uniform
             const uint32_t id = cur & kIdMask;
-            const bool in = id < (uint64_t)hi;
+            const bool in = id < hi32;
             bool fresh = false;
             if (in && id != n) {
               // plain divergent probe loop with a single exit: a lane leaves
@@ -560,9 +564,9 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
             }
             c += cnt;
             if (!cont || over) break;
-            cur = pn < end ? nxt : kSent;
+            cur = pn < len ? nxt : kSent;
           }
-          m_tent[j] = (int32_t)(c - st);  // every lane stores the same value
+          m_tent[j] = c;  // every lane stores the same value
         }
       }
       if (__ballot(lost) != 0 && lane == 0) atomicOr(a.err, kErrTableFull);
