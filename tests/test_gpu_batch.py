@@ -156,3 +156,31 @@ def test_batch_same_graph_alone_and_mixed(ctx):
     np.testing.assert_array_equal(pa.cpu().numpy(), pm.cpu().numpy())
     assert (na, la) == (nm, lm)
     check_result(2, g, lim, res_mixed[2])
+
+
+def test_server_admits_compacts_and_matches_oracle(ctx):
+    """The request loop of the served mode: a capacity for only a few graphs
+    at a time forces refused admissions and compactions; every request's
+    result must still be its own oracle hierarchy."""
+    import time
+    from paper_2609_07577_amd import serve
+    graphs = mixed_graphs()
+    biggest = max(g.n_pins for g, _ in graphs)
+    srv = serve.Server(ctx, max_graphs=4, cap_vertices=9000, cap_edges=9000,
+                       cap_pins=2 * biggest + 1000, levels_per_step=3, use_graph=True,
+                       compact_every=2)
+    levels = [ctx.upload(g) for g, _ in graphs]
+    for i, (g, lim) in enumerate(graphs):
+        srv.submit(i, levels[i], lim, time.perf_counter())
+    results = {}
+    steps = 0
+    while not srv.idle():
+        for rid, arr, fin, part, n_parts, n_levels, pins in srv.step():
+            results[rid] = (part, n_parts, n_levels)
+        steps += 1
+        assert steps < 5000
+    ctx.sync()
+    srv.close()
+    assert sorted(results) == list(range(len(graphs)))
+    for i, (g, lim) in enumerate(graphs):
+        check_result(i, g, lim, results[i])

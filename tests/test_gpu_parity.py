@@ -229,3 +229,32 @@ def test_empty_and_degenerate(ctx):
     # limits that forbid every merge
     g = synth.uniform(1, 200, 2, 6)
     run_hierarchy_parity(ctx, g, synth.Limits(1, 1000, 1000))
+
+
+def test_tuning_never_changes_results(ctx):
+    """The score-step settings (single-pass load, multipass fill target)
+    choose between table sizes and pass widths; the result is the same."""
+    from paper_2609_07577_amd import hg
+    g = synth.powerlaw(5, n=30_000, dmin=20, dmax=3_000)
+    lim = synth.LIMITS["powerlaw"]
+    L = ctx.upload(g)
+    ref = None
+    try:
+        for load, fill in ((8, 5), (1, 1), (12, 10), (4, 3)):
+            ctx.set_tuning(load, fill)
+            out = ctx.coarsen_level(L, lim)
+            got = tuple(_np(out[k]) for k in ("cand", "cscore", "match", "vmap"))
+            if ref is None:
+                ref = got
+            for a, b in zip(ref, got):
+                np.testing.assert_array_equal(a, b, err_msg=f"tuning {load}/{fill}")
+        for bad in ((0, 5), (13, 5), (8, 0), (8, 11)):
+            with pytest.raises(hg.HgError):
+                ctx.set_tuning(*bad)
+    finally:
+        ctx.set_tuning(8, 5)
+    OL = oracle.level0(g)
+    q = np.sort(np.random.default_rng(3).choice(g.n_vertices, 200, replace=False)).astype(np.int32)
+    oc, ocs = oracle.candidates(OL, lim, query=q)
+    np.testing.assert_array_equal(ref[0][q], oc)
+    np.testing.assert_array_equal(ref[1][q], ocs)
