@@ -46,7 +46,8 @@ extern "C" {
 
 typedef enum {
   HG_OK = 0,
-  HG_ERR_INVALID_ARG = 1,   /* null pointer, negative size, bad limits      */
+  HG_ERR_INVALID_ARG = 1,   /* null pointer, negative size, bad limits,
+                               vmap / part out of range (from hg_sync)     */
   HG_ERR_OVERFLOW = 2,      /* V, E or P >= 2^31, sum of weights >= 2^31     */
   HG_ERR_CAPACITY = 3,      /* an output capacity is smaller than needed     */
   HG_ERR_NO_MEMORY = 4,     /* the scratch arena could not be grown          */
@@ -107,7 +108,9 @@ const char* hg_last_error(hg_ctx* ctx);
 /* Blocks until all work queued on the context's stream is done, then checks
  * the context's device error word: every data-dependent loop in the kernels
  * is bounded, and a kernel that reaches a bound records it there instead of
- * spinning; hg_sync then returns HG_ERR_INTERNAL and clears the word. */
+ * spinning; hg_sync then returns HG_ERR_INTERNAL and clears the word.  A
+ * vmap / part value that the device check found out of range makes it
+ * return HG_ERR_INVALID_ARG instead. */
 int hg_sync(hg_ctx* ctx);
 /* Bytes currently held by the scratch arena. */
 int64_t hg_scratch_bytes(hg_ctx* ctx);
@@ -162,8 +165,11 @@ int hg_coarsen_level(hg_ctx* ctx, const hg_level* in, const hg_limits* limits,
 /*
  * Contraction G -> G_P for any vertex map (Section 3, "Partitioning
  * Definition"; Section 4.1 state propagation).  `vmap` [V] holds values in
- * [0, n_coarse); `n_coarse` is a device int32 scalar (e.g. written by
- * hg_coarsen_level) and must not exceed out->cap_vertices.
+ * [0, n_coarse); `n_coarse` is a device int32 scalar in [1, V] (0 when V is
+ * 0), e.g. written by hg_coarsen_level.  Both are checked on the device
+ * before use: an out-of-range value is recorded in the context's error word
+ * (hg_sync then fails with HG_ERR_INVALID_ARG and the outputs of the call
+ * are undefined, but no memory outside them is written).
  *   * a fine hyperedge becomes its distinct coarse vertices, ascending, the
  *     flag of a coarse vertex being the OR of its members' flags; if fewer
  *     than two remain it is dropped;
@@ -182,7 +188,9 @@ int hg_contract(hg_ctx* ctx, const hg_level* in, const int32_t* vmap,
  * Connectivity (Section 3, Eq. 1):
  *   conn = sum over hyperedges e of edge_weight[e] * (number of distinct
  *          part[v] over the pins v of e, minus 1).
- * `part` [V] holds values in [0, V).  Writes the int64 result to device
+ * `part` [V] holds values in [0, V), checked on the device as `vmap` of
+ * hg_contract is (hg_sync fails with HG_ERR_INVALID_ARG on a value outside
+ * it).  Writes the int64 result to device
  * memory `conn`.  Uses only offsets, pins and weights of the level.
  */
 int hg_connectivity(hg_ctx* ctx, const hg_level* lvl, const int32_t* part, int64_t* conn);

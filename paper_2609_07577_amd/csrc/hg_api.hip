@@ -45,6 +45,39 @@ __global__ void validate_kernel(LevelView L, int64_t V, int64_t E, int64_t P,
   }
 }
 
+// Checked copy of a map supplied by the caller (vmap of hg_contract, part of
+// hg_connectivity).  The range is [0, bound) with bound = *n_range clamped to
+// [min(1, V), V] (or V when n_range is null); a value outside it becomes 0 in
+// the copy, a bound outside that interval is clamped, and either is recorded
+// in the error word.  Every kernel after this one indexes with the copy, so
+// no input can send a write outside the arrays sized from V.
+__global__ void check_map_kernel(const int32_t* __restrict__ in, int64_t V,
+                                 const int32_t* __restrict__ n_range, int32_t* __restrict__ out,
+                                 int32_t* __restrict__ out_range, int32_t* __restrict__ err) {
+  int64_t bound = V;
+  bool bad_bound = false;
+  if (n_range) {
+    const int64_t r = *n_range;
+    const int64_t lo = V > 0 ? 1 : 0;
+    bad_bound = r < 0 || r > V;
+    bound = r < lo ? lo : (r > V ? V : r);
+  }
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    if (out_range) *out_range = (int32_t)bound;
+    if (bad_bound) atomicOr(err, kErrMapRange);
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (; i < V; i += stride) {
+    const int32_t x = in[i];
+    const bool ok = (uint32_t)x < (uint64_t)bound;
+    bad |= !ok;
+    out[i] = ok ? x : 0;
+  }
+  if (bad) atomicOr(err, kErrMapRange);
+}
+
 }  // namespace
 }  // namespace hg
 
@@ -108,6 +141,11 @@ int hg_sync(hg_ctx* c) {
   if (flags) {
     fill_i32(c->dev_err, 0, 1, c->stream);
     (void)hipStreamSynchronize(c->stream);
+    if (flags & kErrMapRange)
+      return fail(c, HG_ERR_INVALID_ARG,
+                  "a vmap or part value, or n_coarse, was outside its range; the outputs of "
+                  "that call are undefined (flags 0x%x)",
+                  flags);
     return fail(c, HG_ERR_INTERNAL,
                 "a kernel reached an internal bound (flags 0x%x: 1 score table, 2 passes, "
                 "4 distinct set, 8 fingerprint table, 16 work count, 32 list length)",
@@ -246,17 +284,23 @@ int hg_contract(hg_ctx* c, const hg_level* in, const int32_t* vmap, const int32_
   Sizer sz;
   ContractLayout<Sizer> ls;
   ls.carve(sz, V, E, P);
+  sz.take<int32_t>(V);
+  sz.take<int32_t>(1);
   rc = ensure_arena(c, sz.off);
   if (rc) return rc;
   Carver cv{c->arena};
   ContractLayout<Carver> S;
   S.carve(cv, V, E, P);
+  int32_t* map = cv.take<int32_t>(V);
+  int32_t* nc = cv.take<int32_t>(1);
   hipStream_t s = c->stream;
   set_dims(S.dims, V, E, P, s);
   LevelView L = view_of(in, S.dims);
   S.cs.err = c->dev_err;
   mark(c, 3, 0);
-  contract_level(L, V, E, P, vmap, n_coarse, out, S.cs, s);
+  check_map_kernel<<<grid_for(V, 256, 4096), 256, 0, s>>>(vmap, V, n_coarse, map, nc,
+                                                        c->dev_err);
+  contract_level(L, V, E, P, map, nc, out, S.cs, s);
   mark(c, 3, 1);
   return launch_status(c);
 }
@@ -270,17 +314,21 @@ int hg_connectivity(hg_ctx* c, const hg_level* lvl, const int32_t* part, int64_t
   Sizer sz;
   ConnLayout<Sizer> ls;
   ls.carve(sz, V, E);
+  sz.take<int32_t>(V);
   rc = ensure_arena(c, sz.off);
   if (rc) return rc;
   Carver cv{c->arena};
   ConnLayout<Carver> S;
   S.carve(cv, V, E);
+  int32_t* map = cv.take<int32_t>(V);
   hipStream_t s = c->stream;
   set_dims(S.dims, V, E, P, s);
   LevelView L = view_of(lvl, S.dims);
   S.cs.err = c->dev_err;
   mark(c, 4, 0);
-  connectivity(L, E, V, part, conn, S.cs, s);
+  check_map_kernel<<<grid_for(V, 256, 4096), 256, 0, s>>>(part, V, nullptr, map, nullptr,
+                                                        c->dev_err);
+  connectivity(L, E, V, map, conn, S.cs, s);
   mark(c, 4, 1);
   return launch_status(c);
 }

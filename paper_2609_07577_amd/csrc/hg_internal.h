@@ -22,6 +22,7 @@ enum : int32_t {
   kErrHashFull = 8,     // S7 fingerprint table probe bound
   kErrWorkCount = 16,   // a work-list count above its capacity
   kErrListLength = 32,  // S7 list longer than its source hyperedge
+  kErrMapRange = 64,    // a caller's vmap / part value (or n_coarse) out of range
 };
 
 // Level sizes kept in device memory so that a chain of kernels can run

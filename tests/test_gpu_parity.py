@@ -258,3 +258,51 @@ def test_tuning_never_changes_results(ctx):
     oc, ocs = oracle.candidates(OL, lim, query=q)
     np.testing.assert_array_equal(ref[0][q], oc)
     np.testing.assert_array_equal(ref[1][q], ocs)
+
+
+def test_out_of_range_maps_are_rejected(ctx):
+    """A vmap / part value outside its range, or an n_coarse outside [1, V],
+    is caught by the device-side check of hg_contract / hg_connectivity:
+    hg_sync fails with HG_ERR_INVALID_ARG, nothing outside the outputs is
+    written, and the context works normally afterwards."""
+    import torch as T
+    from paper_2609_07577_amd import hg
+    n = 20000
+    rng = np.random.default_rng(17)
+    axons = [(0, list(range(1, n)), 2)]  # one hyperedge above 16384 pins
+    for s in range(1, 300):
+        tg = sorted(set(rng.choice(np.arange(n), 12, replace=False).tolist()) - {s})
+        axons.append((s, tg, 1))
+    g = synth.from_axons(n, axons)
+    L = ctx.upload(g)
+    OL = oracle.level0(g)
+    k = 500
+    vmap = (np.arange(n) % k).astype(np.int32)
+    good = T.from_numpy(vmap).cuda()
+    nc = T.tensor([k], dtype=T.int32, device="cuda")
+    expect_conn = oracle.connectivity(OL.eoff, OL.pins, OL.w, vmap)
+    expect_level = oracle.contract(OL, vmap, k)
+
+    def bad_vmap(value):
+        v = vmap.copy()
+        v[[3, n // 2, n - 1]] = value
+        return T.from_numpy(v).cuda()
+
+    cases = [("vmap value == n_coarse", bad_vmap(k), nc),
+             ("negative vmap value", bad_vmap(-5), nc),
+             ("n_coarse above V", good, T.tensor([n + 100], dtype=T.int32, device="cuda")),
+             ("n_coarse zero", good, T.tensor([0], dtype=T.int32, device="cuda")),
+             ("n_coarse negative", good, T.tensor([-1], dtype=T.int32, device="cuda"))]
+    for what, vm, ncv in cases:
+        print(f"  contract: {what}", flush=True)
+        with pytest.raises(hg.HgError) as ei:
+            ctx.contract(L, vm, ncv)
+        assert ei.value.code == 1, (what, ei.value)
+        assert_level_equal(ctx.contract(L, good, nc), expect_level, f"after {what}")
+    for what, value in (("part value == V", n), ("negative part value", -1)):
+        print(f"  connectivity: {what}", flush=True)
+        ctx.connectivity(L, bad_vmap(value))
+        with pytest.raises(hg.HgError) as ei:
+            ctx.sync()
+        assert ei.value.code == 1, (what, ei.value)
+        assert int(ctx.connectivity(L, good).item()) == expect_conn, f"after {what}"
