@@ -68,6 +68,14 @@ __device__ inline uint32_t table_add(uint64_t* table, uint32_t mask, int shift, 
 
 __device__ inline int log2_pow2(uint32_t c) { return 31 - __clz(c); }
 
+// A value that is the same in every lane (e.g. read from LDS at a
+// wave-uniform address), moved to a scalar register so that the control flow
+// depending on it stays scalar.
+__device__ inline int32_t rfl_i32(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline uint32_t rfl_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)x);
+}
+
 struct VertexCtx {
   int32_t n;
   int64_t beg, deg;
@@ -612,6 +620,310 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
   }
 }
 
+// Multipass over windows of neighbour ids for vertices whose incident
+// hyperedges fit in LDS (no distinct-axon overlap needed).  In a large
+// neighbourhood most neighbours share a single hyperedge with n: the score
+// of such a neighbour is that hyperedge's weight, known from the visit
+// itself, and needs no table.  Per window [lo, lo + width) of ids, width at
+// most kWinIds:
+//   sweep 1 walks each incident hyperedge from its cursor to the window end,
+//     setting one LDS bit per visited id; a visit that finds its bit already
+//     set enters the id, as repeated, in a small LDS hash table (key only);
+//   the bitmap is then rebuilt to hold just the repeated ids;
+//   sweep 2 visits the same pins again, flattened over the known slices: a
+//     repeated id adds the hyperedge weight to its table entry, any other id
+//     has its complete score and is compared with the lane's best;
+//   the table is folded into the best (validity tested only for entries that
+//     beat it) and emptied.
+// A window whose repeated ids would overfill the table is abandoned and
+// retried at half the width.
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int bucket,
+                                                              int64_t maxV) {
+  constexpr int NW = THREADS / kWave;
+  constexpr int kBatch = 8;
+  constexpr uint32_t kWinIds = 1u << 19;
+  constexpr int kWords = (int)(kWinIds / 32);
+  constexpr int HSLOTS = 8192;
+  constexpr int HMAX = HSLOTS / 2;
+  constexpr int kPublish = 32;
+  constexpr uint32_t kSent = 0x7FFFFFFFu;
+  static_assert(HMAX + NW * (kPublish + kWave) < HSLOTS, "table must never fill up");
+  __shared__ uint32_t seen[kWords];
+  __shared__ uint64_t rtab[HSLOTS];
+  __shared__ uint32_t m_start[kMetaDeg];  // pin offsets are below 2^31
+  __shared__ int32_t m_len[kMetaDeg];
+  __shared__ int32_t m_w[kMetaDeg];
+  __shared__ int32_t m_cur[kMetaDeg];   // committed cursors
+  __shared__ int32_t m_tent[kMetaDeg];  // cursors reached in the current window
+  __shared__ uint64_t red[2 * NW];
+  __shared__ int32_t s_item;
+  __shared__ int32_t s_fill;
+  __shared__ int32_t s_wover[NW];
+
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  int32_t count = a.b.count[bucket];
+  if (count > maxV) {
+    if (tid == 0) atomicOr(a.err, kErrWorkCount);
+    count = (int32_t)maxV;
+  }
+  const int32_t* list = a.b.list + (int64_t)bucket * maxV;
+  for (int i = tid; i < kWords; i += THREADS) seen[i] = 0;
+  for (int i = tid; i < HSLOTS; i += THREADS) rtab[i] = kEmpty;
+  const int hshift = 32 - log2_pow2(HSLOTS);
+
+  while (true) {
+    __syncthreads();
+    if (tid == 0) s_item = atomicAdd(&a.work[bucket], 1);
+    __syncthreads();
+    const int32_t item = s_item;
+    if (item >= count) break;
+
+    VertexCtx v;
+    v.n = list[item];
+    v.beg = a.voff[v.n];
+    v.deg = a.voff[v.n + 1] - v.beg;
+    v.size_n = a.L.size[v.n];
+    v.syn_n = a.L.syn[v.n];
+    v.ax_n = a.L.ax[v.n];
+    v.G = a.gc[a.L.gid ? a.L.gid[v.n] : 0];
+    v.all_valid = (int64_t)v.size_n + v.G.max_size <= v.G.omega &&
+                  (int64_t)v.syn_n + v.G.max_syn <= v.G.phi &&
+                  (int64_t)v.ax_n + v.G.max_ax <= v.G.delta;
+    const uint32_t n = (uint32_t)v.n;
+    const int32_t deg = (int32_t)v.deg;  // <= kMetaDeg by the bucket rule
+    uint64_t best = 0;
+
+    int64_t mn = INT64_MAX, mx = -1;
+    for (int j = tid; j < deg; j += THREADS) {
+      const uint32_t e = a.vinc[v.beg + j] & kIdMask;
+      const int64_t s0 = a.L.eoff[e], e0 = a.L.eoff[e + 1];
+      m_start[j] = (uint32_t)s0;
+      m_len[j] = (int32_t)(e0 - s0);
+      m_w[j] = a.L.w[e];
+      m_cur[j] = 0;
+      const int64_t f = a.L.pins[s0] & kIdMask, l = a.L.pins[e0 - 1] & kIdMask;
+      mn = f < mn ? f : mn;
+      mx = l > mx ? l : mx;
+    }
+    block_min_max_i64<THREADS>(mn, mx, (int64_t*)red);  // also orders the staging
+    const int64_t hi_all = mx + 1;
+    int64_t lo = mn;
+    int64_t width = hi_all - lo < (int64_t)kWinIds ? hi_all - lo : (int64_t)kWinIds;
+    int passes = 0;
+    while (lo < hi_all) {
+      const int64_t hi = lo + width < hi_all ? lo + width : hi_all;
+      const uint32_t lo32 = (uint32_t)lo, hi32 = (uint32_t)hi;  // ids are below 2^31
+      __syncthreads();  // previous window drained / cleared, flags read, cursors committed
+      if (++passes > kMaxPasses) {
+        if (tid == 0) atomicOr(a.err, kErrPassLimit);
+        break;
+      }
+      if (tid == 0) s_fill = 0;
+      __syncthreads();
+
+      // ---- sweep 1: seen bits, repeated ids into the table, slice ends ----
+      // Per-hyperedge values read from LDS are the same for the whole wave;
+      // reading them into scalar registers keeps the loop control scalar.
+      bool over = false;
+      int32_t pending = 0;  // repeated ids entered by this wave, not yet published
+      for (int32_t j0 = wid; j0 < deg && !over; j0 += kBatch * NW) {
+        uint32_t pin[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const int32_t j = j0 + b * NW;
+          const int32_t js = j < deg ? j : j0;
+          const uint32_t st = rfl_u32(m_start[js]);
+          const int32_t len = rfl_i32(m_len[js]);
+          const int32_t p = rfl_i32(m_cur[js]) + lane;
+          const bool ok = j < deg && p < len;
+          pin[b] = a.L.pins[st + (uint32_t)(p < len ? p : len - 1)];  // never empty
+          pin[b] = ok ? pin[b] : kSent;
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const int32_t j = j0 + b * NW;
+          if (j >= deg || over) break;  // wave-uniform
+          const uint32_t* seg = a.L.pins + rfl_u32(m_start[j]);
+          const int32_t len = rfl_i32(m_len[j]);
+          int32_t c = rfl_i32(m_cur[j]);
+          uint32_t cur = pin[b];
+          while (true) {
+            // the slice goes on past this chunk iff its last lane holds a pin
+            // below the window end (pins ascend; lanes past the hyperedge
+            // hold the sentinel)
+            const uint32_t last = __builtin_amdgcn_readlane(cur, kWave - 1);
+            const bool cont = (last & kIdMask) < hi32 && c + kWave < len;
+            const int32_t pn = c + kWave + lane;
+            uint32_t nxt = kSent;
+            if (cont) nxt = seg[pn < len ? pn : len - 1];  // wave-uniform
+            const uint32_t id = cur & kIdMask;
+            const bool in = id < hi32;  // and >= lo: the cursor starts at the window
+            const bool act = in & (id != n);
+            // branch-free: an idle lane ors 0 into a word of its own
+            const uint32_t rel = id - lo32;
+            const uint32_t word = act ? rel >> 5 : (uint32_t)lane;
+            const uint32_t bit = act ? 1u << (rel & 31) : 0u;
+            const bool rep = (atomicOr(&seen[word], bit) & bit) != 0;
+            if (__ballot(rep) != 0) {  // wave-uniform; rare in sparse neighbourhoods
+              bool fresh = false;
+              if (rep) {
+                uint32_t h = slot_hash(id, hshift);
+                const uint64_t mine = (uint64_t)id << 32;
+                uint64_t old;
+                uint32_t probe = 0;
+                while (true) {
+                  old = atomicCAS((unsigned long long*)&rtab[h], (unsigned long long)kEmpty,
+                                  (unsigned long long)mine);
+                  ++probe;
+                  const bool stop = (old == kEmpty) | ((uint32_t)(old >> 32) == id) |
+                                    (probe >= (uint32_t)HSLOTS);
+                  if (stop) break;
+                  h = (h + 1) & (HSLOTS - 1);
+                }
+                fresh = old == kEmpty;
+                // the probe bound is never reached while the fill bound holds
+                if (!fresh && (uint32_t)(old >> 32) != id) atomicOr(a.err, kErrTableFull);
+              }
+              pending = rfl_i32(pending + __popcll(__ballot(fresh)));
+              if (pending >= kPublish) {  // wave-uniform
+                // one lane publishes (a lane-varying operand would make the
+                // compiler scan over all lanes)
+                int32_t old = 0;
+                if (lane == 0) old = atomicAdd(&s_fill, pending);
+                over = __builtin_amdgcn_readlane(old, 0) + pending > HMAX;
+                pending = 0;
+              }
+            }
+            c += __popcll(__ballot(in));
+            if (!cont || over) break;
+            cur = pn < len ? nxt : kSent;
+          }
+          m_tent[j] = c;  // every lane stores the same value
+        }
+      }
+      if (pending > 0) {  // wave-uniform
+        int32_t old = 0;
+        if (lane == 0) old = atomicAdd(&s_fill, pending);
+        over = over || __builtin_amdgcn_readlane(old, 0) + pending > HMAX;
+      }
+      s_wover[wid] = over ? 1 : 0;  // every lane stores the same value
+      __syncthreads();
+      bool any_over = false;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) any_over |= s_wover[w] != 0;
+      const int32_t fill = s_fill;
+      for (int i = tid; i < kWords; i += THREADS) seen[i] = 0;
+      if (any_over) {
+        for (int i = tid; i < HSLOTS; i += THREADS) rtab[i] = kEmpty;
+        width = width / 2 > 0 ? width / 2 : 1;
+        continue;  // the loop head synchronises before the next window
+      }
+      __syncthreads();  // bitmap cleared
+      if (fill > 0) {
+        for (int i = tid; i < HSLOTS; i += THREADS) {
+          const uint64_t s = rtab[i];
+          if (s != kEmpty) {
+            const uint32_t rel = (uint32_t)(s >> 32) - lo32;
+            atomicOr(&seen[rel >> 5], 1u << (rel & 31));
+          }
+        }
+        __syncthreads();  // bitmap holds the repeated ids
+      }
+
+      // ---- sweep 2: the slices [m_cur, m_tent) again ----
+      for (int32_t j0 = wid; j0 < deg; j0 += kBatch * NW) {
+        uint32_t pin[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const int32_t j = j0 + b * NW;
+          const int32_t js = j < deg ? j : j0;
+          const int32_t c0 = rfl_i32(m_cur[js]);
+          const int32_t sl = rfl_i32(m_tent[js]) - c0;
+          // a lane past the slice re-reads the slice's last pin, and an
+          // empty slice (possibly at the hyperedge's end) its first pin; such
+          // lanes are masked below
+          const int32_t p = sl > 0 ? c0 + (lane < sl ? lane : sl - 1) : 0;
+          pin[b] = a.L.pins[rfl_u32(m_start[js]) + (uint32_t)p];
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const int32_t j = j0 + b * NW;
+          if (j >= deg) break;  // wave-uniform
+          const int32_t c0 = rfl_i32(m_cur[j]);
+          const int32_t sl = rfl_i32(m_tent[j]) - c0;
+          const uint32_t* seg = a.L.pins + rfl_u32(m_start[j]) + (uint32_t)c0;
+          const uint32_t wt = rfl_u32(m_w[j]);
+          uint32_t cur = pin[b];
+          for (int32_t c = 0; c < sl; c += kWave) {  // wave-uniform
+            const int32_t pn = c + kWave + lane;
+            uint32_t nxt = 0;
+            if (c + kWave < sl) nxt = seg[pn < sl ? pn : sl - 1];  // wave-uniform
+            const uint32_t id = cur & kIdMask;
+            const bool act = (c + lane < sl) & (id != n);
+            const uint32_t rel = id - lo32;  // in the window for every lane
+            const bool isrep = fill > 0 && ((seen[rel >> 5] >> (rel & 31)) & 1u);
+            const uint64_t key = ((uint64_t)wt << 32) | (uint64_t)(kSent - id);
+            if (act & !isrep & (key > best)) {
+              if (v.all_valid || merge_valid(a, v, id, 0)) best = key;
+            }
+            const bool add = act & isrep;
+            if (__ballot(add) != 0) {  // wave-uniform
+              if (add) {
+                uint32_t h = slot_hash(id, hshift);
+                uint64_t s;
+                uint32_t probe = 0;
+                while (true) {
+                  s = rtab[h];
+                  ++probe;
+                  const bool stop = ((uint32_t)(s >> 32) == id) | (s == kEmpty) |
+                                    (probe >= (uint32_t)HSLOTS);
+                  if (stop) break;
+                  h = (h + 1) & (HSLOTS - 1);
+                }
+                if ((uint32_t)(s >> 32) == id)
+                  atomicAdd((unsigned long long*)&rtab[h], (unsigned long long)wt);
+                else  // every repeated id was entered in sweep 1
+                  atomicOr(a.err, kErrTableFull);
+              }
+            }
+            cur = nxt;
+          }
+        }
+      }
+      __syncthreads();  // sweep 2 done: table complete
+      if (fill > 0) {
+        for (int i = tid; i < HSLOTS; i += THREADS) {
+          const uint64_t s = rtab[i];
+          if (s != kEmpty) {
+            const uint32_t id = (uint32_t)(s >> 32);
+            const uint64_t key = ((s & 0xFFFFFFFFull) << 32) | (uint64_t)(kSent - id);
+            if (key > best && (v.all_valid || merge_valid(a, v, id, 0))) best = key;
+            rtab[i] = kEmpty;
+            seen[(id - lo32) >> 5] = 0;
+          }
+        }
+      }
+      for (int jj = tid; jj < deg; jj += THREADS) m_cur[jj] = m_tent[jj];
+      lo = hi;
+      if (fill < HMAX / 4 && width < (int64_t)kWinIds) {
+        width *= 2;
+        if (width > (int64_t)kWinIds) width = kWinIds;
+      }
+    }
+    best = block_max_u64<THREADS>(best, red);
+    if (tid == 0) {
+      if (best == 0) {
+        a.cand[v.n] = -1;
+        a.cscore[v.n] = 0;
+      } else {
+        a.cand[v.n] = (int32_t)(kSent - (uint32_t)(best & 0xFFFFFFFFull));
+        a.cscore[v.n] = (int32_t)(best >> 32);
+      }
+    }
+  }
+}
+
 __global__ void no_candidate_kernel(const Dims* __restrict__ d, int32_t* __restrict__ cand,
                                     int32_t* __restrict__ cscore, int32_t* __restrict__ work) {
   int64_t V = d->V;
@@ -641,7 +953,7 @@ void score_candidates(const ScoreArgs& a, int64_t maxV, int64_t maxP, hipStream_
   static int g[kNumBuckets] = {0};
   auto k0 = score_block_kernel<256, kSmallSlots, false, false>;
   auto k1 = score_block_kernel<512, kBigSlots, false, false>;
-  auto k2 = score_stream_kernel<1024, kBigSlots, false>;
+  auto k2 = score_window_kernel<1024>;
   auto k3 = score_block_kernel<512, kBigSlots, true, false>;
   auto k4 = score_block_kernel<256, kSmallSlots, false, true>;
   auto k5 = score_block_kernel<512, kBigSlotsOv, false, true>;
