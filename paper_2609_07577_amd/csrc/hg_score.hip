@@ -620,46 +620,102 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
   }
 }
 
+// Exclusive scan over the block of one pair (x, y) per thread: prefix sums
+// (px, py) and block totals (tx, ty).  ws holds 2 * THREADS / 64 ints.
+template <int THREADS>
+__device__ inline void block_scan_pair(int32_t x, int32_t y, int32_t& px, int32_t& py,
+                                       int32_t& tx, int32_t& ty, int32_t* ws) {
+  constexpr int NW = THREADS / kWave;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  int32_t ix = x, iy = y;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int32_t ox = __shfl_up(ix, d, kWave), oy = __shfl_up(iy, d, kWave);
+    ix += lane >= d ? ox : 0;
+    iy += lane >= d ? oy : 0;
+  }
+  if (lane == kWave - 1) {
+    ws[wid] = ix;
+    ws[NW + wid] = iy;
+  }
+  __syncthreads();
+  int32_t bx = 0, by = 0;
+  tx = 0;
+  ty = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int32_t a = ws[w], b = ws[NW + w];
+    bx += w < wid ? a : 0;
+    by += w < wid ? b : 0;
+    tx += a;
+    ty += b;
+  }
+  px = bx + ix - x;
+  py = by + iy - y;
+  __syncthreads();  // ws may be reused
+}
+
 // Multipass over windows of neighbour ids for vertices whose incident
 // hyperedges fit in LDS (no distinct-axon overlap needed).  In a large
 // neighbourhood most neighbours share a single hyperedge with n: the score
 // of such a neighbour is that hyperedge's weight, known from the visit
 // itself, and needs no table.  Per window [lo, lo + width) of ids, width at
 // most kWinIds:
-//   sweep 1 walks each incident hyperedge from its cursor to the window end,
-//     setting one LDS bit per visited id; a visit that finds its bit already
-//     set enters the id, as repeated, in a small LDS hash table (key only);
+//   sweep 1 visits the pins of every incident hyperedge from its cursor up
+//     to the window end, setting one LDS bit per id; a visit that finds its
+//     bit already set enters the id, as repeated, in a small LDS hash table
+//     (key only), and the pins below the window end are counted;
 //   the bitmap is then rebuilt to hold just the repeated ids;
-//   sweep 2 visits the same pins again, flattened over the known slices: a
-//     repeated id adds the hyperedge weight to its table entry, any other id
-//     has its complete score and is compared with the lane's best;
+//   sweep 2 visits the same pins again: a repeated id adds the hyperedge
+//     weight to its table entry, any other id has its complete score and is
+//     compared with the lane's best;
 //   the table is folded into the best (validity tested only for entries that
-//     beat it) and emptied.
+//     beat it) and emptied, and the cursors move past the counted pins.
 // A window whose repeated ids would overfill the table is abandoned and
 // retried at half the width.
+//
+// Work balance: hyperedge sizes follow a heavy-tailed law, so each sweep cuts
+// the vertex's slices into batches of B chunks (64 pins each), numbers the
+// batches of all hyperedges in a row, and deals them to the waves round
+// robin; a wave finds the hyperedge of its next batch with one LDS read per
+// lane and a ballot over a compact list of the hyperedges that have batches.
+// A wave issues the B loads of its next batch before it processes the
+// current one, so up to 2B loads are in flight.  In sweep 1 the slice end is
+// not known in advance: the batches cover an estimate of it (from the pins'
+// id density, plus two standard deviations and a chunk), every pin is tested
+// against the window end, and when a slice runs on past its batches the wave
+// holding the last of them continues with further batches until the end.
+// The count of pins below the window end is exact whatever the estimate; a
+// poor one only costs loads.
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int bucket,
                                                               int64_t maxV) {
   constexpr int NW = THREADS / kWave;
-  constexpr int kBatch = 8;
+  constexpr int B = 4;  // chunks per batch
   constexpr uint32_t kWinIds = 1u << 19;
   constexpr int kWords = (int)(kWinIds / 32);
-  constexpr int HSLOTS = 8192;
-  constexpr int HMAX = HSLOTS / 2;
-  constexpr int kPublish = 32;
+  constexpr int HSLOTS = 4096;
+  constexpr int HMAX = 2560;
+  constexpr int kPublish = 16;
   constexpr uint32_t kSent = 0x7FFFFFFFu;
   static_assert(HMAX + NW * (kPublish + kWave) < HSLOTS, "table must never fill up");
+  static_assert(kMetaDeg <= 2 * THREADS, "a thread lists at most two hyperedges");
   __shared__ uint32_t seen[kWords];
   __shared__ uint64_t rtab[HSLOTS];
   __shared__ uint32_t m_start[kMetaDeg];  // pin offsets are below 2^31
   __shared__ int32_t m_len[kMetaDeg];
   __shared__ int32_t m_w[kMetaDeg];
-  __shared__ int32_t m_cur[kMetaDeg];   // committed cursors
-  __shared__ int32_t m_tent[kMetaDeg];  // cursors reached in the current window
+  __shared__ uint32_t m_last[kMetaDeg];   // largest id of the hyperedge
+  __shared__ int32_t m_cur[kMetaDeg];     // cursor: pins below the window
+  __shared__ int32_t m_nb[kMetaDeg];      // sweep 1: chunks covered by batches
+  __shared__ int32_t m_cnt[kMetaDeg];     // pins of the slice (below the window end)
+  __shared__ int32_t c_list[kMetaDeg];    // hyperedges with batches (bit 31: may run on)
+  __shared__ int32_t c_pre[kMetaDeg + 1]; // batches before each listed hyperedge
+  __shared__ int32_t ws[2 * NW];
   __shared__ uint64_t red[2 * NW];
   __shared__ int32_t s_item;
   __shared__ int32_t s_fill;
-  __shared__ int32_t s_wover[NW];
+  __shared__ int32_t s_over;  // the window overflowed the table
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   int32_t count = a.b.count[bucket];
@@ -691,7 +747,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
                   (int64_t)v.syn_n + v.G.max_syn <= v.G.phi &&
                   (int64_t)v.ax_n + v.G.max_ax <= v.G.delta;
     const uint32_t n = (uint32_t)v.n;
-    const int32_t deg = (int32_t)v.deg;  // <= kMetaDeg by the bucket rule
+    const int32_t deg = (int32_t)v.deg;  // 1 .. kMetaDeg by the bucket rule
     uint64_t best = 0;
 
     int64_t mn = INT64_MAX, mx = -1;
@@ -702,15 +758,115 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       m_len[j] = (int32_t)(e0 - s0);
       m_w[j] = a.L.w[e];
       m_cur[j] = 0;
-      const int64_t f = a.L.pins[s0] & kIdMask, l = a.L.pins[e0 - 1] & kIdMask;
-      mn = f < mn ? f : mn;
-      mx = l > mx ? l : mx;
+      const uint32_t f = a.L.pins[s0] & kIdMask, l = a.L.pins[e0 - 1] & kIdMask;
+      m_last[j] = l;
+      mn = (int64_t)f < mn ? (int64_t)f : mn;
+      mx = (int64_t)l > mx ? (int64_t)l : mx;
     }
     block_min_max_i64<THREADS>(mn, mx, (int64_t*)red);  // also orders the staging
     const int64_t hi_all = mx + 1;
     int64_t lo = mn;
     int64_t width = hi_all - lo < (int64_t)kWinIds ? hi_all - lo : (int64_t)kWinIds;
     int passes = 0;
+
+    // Lists the hyperedges with batches: thread t looks at hyperedges 2t and
+    // 2t + 1, whose chunk counts (and run-on flags) it passes in.  Returns
+    // the number of listed hyperedges and of batches (block-uniform).
+    auto list_batches = [&](int32_t nb0, int32_t nb1, bool ro0, bool ro1, int32_t& nc,
+                            int32_t& tb) {
+      const int32_t b0 = (nb0 + B - 1) / B, b1 = (nb1 + B - 1) / B;
+      int32_t pc, pb;
+      block_scan_pair<THREADS>((b0 > 0) + (b1 > 0), b0 + b1, pc, pb, nc, tb, ws);
+      const int32_t j0 = 2 * tid;
+      if (b0 > 0) {
+        c_list[pc] = j0 | (ro0 ? (int32_t)0x80000000 : 0);
+        c_pre[pc] = pb;
+        ++pc;
+        pb += b0;
+      }
+      if (b1 > 0) {
+        c_list[pc] = (j0 + 1) | (ro1 ? (int32_t)0x80000000 : 0);
+        c_pre[pc] = pb;
+      }
+      if (tid == 0) c_pre[nc] = tb;
+    };
+
+    // A batch: hyperedge j (deg: no more work), chunks k .. kend - 1 of its
+    // slice, which starts at seg and has r pins left (sweep 1) or exactly r
+    // pins (sweep 2).
+    struct Batch {
+      int32_t j, k, kend, r;
+      bool runs_on;  // sweep 1: the slice may go on past chunk kend - 1, the last
+                     // chunk listed for the hyperedge
+      uint32_t wt;
+      const uint32_t* seg;
+    };
+    const uint32_t* dummy = a.L.pins + rfl_u32(m_start[0]);
+    int32_t nc = 0, tb = 0;  // listed hyperedges, batches of the current sweep
+    int32_t bnext = 0, ci = 0;
+    bool has_cont = false;
+    int32_t cont_j = 0, cont_k = 0;
+    // The wave's next batch; its loads are issued at once (for no batch, at
+    // an address inside the pins, so that every path issues B loads).
+    auto fetch = [&](Batch& t, uint32_t (&pin)[B], bool sweep1) {
+      const int32_t ov =
+          rfl_i32(__hip_atomic_load(&s_over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+      t.j = deg;
+      t.k = 0;
+      t.runs_on = false;
+      bool cont = false;
+      if (sweep1 && has_cont) {  // wave-uniform
+        t.j = cont_j;
+        t.k = cont_k;
+        has_cont = false;
+        cont = true;
+      } else if (bnext < tb) {  // wave-uniform
+        // the last listed hyperedge (from ci on) whose first batch is at most
+        // bnext: the entries are strictly increasing, so the lanes that pass
+        // form a prefix, and it lies within 16 entries of ci
+        const int32_t idx = ci + lane < nc ? ci + lane : nc;
+        const uint64_t m = __ballot(c_pre[idx] <= bnext);
+        const int32_t i = ci + (int32_t)__popcll(m) - 1;
+        ci = i;
+        const int32_t e = rfl_i32(c_list[i]);
+        t.j = e & 0x7FFFFFFF;
+        t.runs_on = e < 0;
+        t.k = (bnext - rfl_i32(c_pre[i])) * B;
+        bnext += NW;
+      }
+      if (ov != 0 && sweep1) t.j = deg;
+      if (t.j < deg) {  // wave-uniform
+        const int32_t c0 = rfl_i32(m_cur[t.j]);
+        t.seg = a.L.pins + rfl_u32(m_start[t.j]) + (uint32_t)c0;
+        t.wt = rfl_u32(m_w[t.j]);
+        if (sweep1) {
+          t.r = rfl_i32(m_len[t.j]) - c0;
+          const int32_t full = (t.r + kWave - 1) / kWave;
+          const int32_t nb = cont ? full : rfl_i32(m_nb[t.j]);
+          t.kend = t.k + B < nb ? t.k + B : nb;
+          // only the batch holding the hyperedge's last listed chunk (or a
+          // continuation) may find that the slice runs on
+          t.runs_on = (t.runs_on && t.kend == nb) || cont;
+        } else {
+          t.r = rfl_i32(m_cnt[t.j]);
+          const int32_t nb = (t.r + kWave - 1) / kWave;
+          t.kend = t.k + B < nb ? t.k + B : nb;
+        }
+      } else {
+        t.r = 1;
+        t.seg = dummy;
+        t.k = 0;
+        t.kend = 0;
+        t.wt = 0;
+        t.runs_on = false;
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int32_t p = (t.k + u) * kWave + lane;
+        pin[u] = t.seg[p < t.r ? p : t.r - 1];
+      }
+    };
+
     while (lo < hi_all) {
       const int64_t hi = lo + width < hi_all ? lo + width : hi_all;
       const uint32_t lo32 = (uint32_t)lo, hi32 = (uint32_t)hi;  // ids are below 2^31
@@ -719,99 +875,144 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         if (tid == 0) atomicOr(a.err, kErrPassLimit);
         break;
       }
-      if (tid == 0) s_fill = 0;
-      __syncthreads();
-
-      // ---- sweep 1: seen bits, repeated ids into the table, slice ends ----
-      // Per-hyperedge values read from LDS are the same for the whole wave;
-      // reading them into scalar registers keeps the loop control scalar.
-      bool over = false;
-      int32_t pending = 0;  // repeated ids entered by this wave, not yet published
-      for (int32_t j0 = wid; j0 < deg && !over; j0 += kBatch * NW) {
-        uint32_t pin[kBatch];
+      // ---- sweep 1 batches: all remaining chunks when the hyperedge ends in
+      // the window (or has at most two left), else a generous estimate of the
+      // slice, flagged as possibly running on
+      {
+        int32_t nbq[2] = {0, 0};
+        bool roq[2] = {false, false};
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-          const int32_t j = j0 + b * NW;
-          const int32_t js = j < deg ? j : j0;
-          const uint32_t st = rfl_u32(m_start[js]);
-          const int32_t len = rfl_i32(m_len[js]);
-          const int32_t p = rfl_i32(m_cur[js]) + lane;
-          const bool ok = j < deg && p < len;
-          pin[b] = a.L.pins[st + (uint32_t)(p < len ? p : len - 1)];  // never empty
-          pin[b] = ok ? pin[b] : kSent;
-        }
-#pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-          const int32_t j = j0 + b * NW;
-          if (j >= deg || over) break;  // wave-uniform
-          const uint32_t* seg = a.L.pins + rfl_u32(m_start[j]);
-          const int32_t len = rfl_i32(m_len[j]);
-          int32_t c = rfl_i32(m_cur[j]);
-          uint32_t cur = pin[b];
-          while (true) {
-            // the slice goes on past this chunk iff its last lane holds a pin
-            // below the window end (pins ascend; lanes past the hyperedge
-            // hold the sentinel)
-            const uint32_t last = __builtin_amdgcn_readlane(cur, kWave - 1);
-            const bool cont = (last & kIdMask) < hi32 && c + kWave < len;
-            const int32_t pn = c + kWave + lane;
-            uint32_t nxt = kSent;
-            if (cont) nxt = seg[pn < len ? pn : len - 1];  // wave-uniform
-            const uint32_t id = cur & kIdMask;
-            const bool in = id < hi32;  // and >= lo: the cursor starts at the window
-            const bool act = in & (id != n);
-            // branch-free: an idle lane ors 0 into a word of its own
-            const uint32_t rel = id - lo32;
-            const uint32_t word = act ? rel >> 5 : (uint32_t)lane;
-            const uint32_t bit = act ? 1u << (rel & 31) : 0u;
-            const bool rep = (atomicOr(&seen[word], bit) & bit) != 0;
-            if (__ballot(rep) != 0) {  // wave-uniform; rare in sparse neighbourhoods
-              bool fresh = false;
-              if (rep) {
-                uint32_t h = slot_hash(id, hshift);
-                const uint64_t mine = (uint64_t)id << 32;
-                uint64_t old;
-                uint32_t probe = 0;
-                while (true) {
-                  old = atomicCAS((unsigned long long*)&rtab[h], (unsigned long long)kEmpty,
-                                  (unsigned long long)mine);
-                  ++probe;
-                  const bool stop = (old == kEmpty) | ((uint32_t)(old >> 32) == id) |
-                                    (probe >= (uint32_t)HSLOTS);
-                  if (stop) break;
-                  h = (h + 1) & (HSLOTS - 1);
-                }
-                fresh = old == kEmpty;
-                // the probe bound is never reached while the fill bound holds
-                if (!fresh && (uint32_t)(old >> 32) != id) atomicOr(a.err, kErrTableFull);
-              }
-              pending = rfl_i32(pending + __popcll(__ballot(fresh)));
-              if (pending >= kPublish) {  // wave-uniform
-                // one lane publishes (a lane-varying operand would make the
-                // compiler scan over all lanes)
-                int32_t old = 0;
-                if (lane == 0) old = atomicAdd(&s_fill, pending);
-                over = __builtin_amdgcn_readlane(old, 0) + pending > HMAX;
-                pending = 0;
-              }
+        for (int q = 0; q < 2; ++q) {
+          const int32_t j = 2 * tid + q;
+          if (j < deg) {
+            const int32_t r = m_len[j] - m_cur[j];
+            const int32_t full = (r + kWave - 1) / kWave;
+            int32_t nb = full;
+            if (m_last[j] >= hi32 && full > 2) {
+              const uint32_t l = m_last[j];
+              const float est = (float)r * (float)(hi - lo) / (float)((int64_t)l - lo + 1);
+              const float body = est + 2.0f * sqrtf(est) + (float)kWave;
+              nb = (int32_t)(body / (float)kWave) + 1;
+              nb = nb < full ? nb : full;
             }
-            c += __popcll(__ballot(in));
-            if (!cont || over) break;
-            cur = pn < len ? nxt : kSent;
+            nbq[q] = nb;
+            roq[q] = nb < full;
           }
-          m_tent[j] = c;  // every lane stores the same value
+        }
+        list_batches(nbq[0], nbq[1], roq[0], roq[1], nc, tb);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int32_t j = 2 * tid + q;
+          if (j < deg) {
+            m_nb[j] = nbq[q];
+            m_cnt[j] = 0;
+          }
+        }
+      }
+      if (tid == 0) {
+        s_fill = 0;
+        s_over = 0;
+      }
+      __syncthreads();
+      bnext = wid;
+      ci = 0;
+      has_cont = false;
+
+      // ---- sweep 1 ----
+      int32_t pending = 0;  // repeated ids entered by this wave, not yet published
+      bool over = false;
+      // one chunk: bits, repeated ids, returns the pins below the window end
+      auto visit1 = [&](uint32_t pin, bool valid) -> int32_t {
+        const uint32_t id = pin & kIdMask;
+        const bool in = valid & (id < hi32);  // ids >= lo: cursor order
+        const bool act = in & (id != n);
+        // branch-free: an idle lane ors 0 into a word of its own
+        const uint32_t rel = id - lo32;
+        const uint32_t word = act ? rel >> 5 : (uint32_t)lane;
+        const uint32_t bit = act ? 1u << (rel & 31) : 0u;
+        const bool rep = (atomicOr(&seen[word], bit) & bit) != 0;
+        if (__ballot(rep) != 0) {  // wave-uniform; rare in sparse neighbourhoods
+          bool fresh = false;
+          if (rep) {
+            uint32_t h = slot_hash(id, hshift);
+            const uint64_t mine = (uint64_t)id << 32;
+            uint64_t old;
+            uint32_t probe = 0;
+            while (true) {
+              old = atomicCAS((unsigned long long*)&rtab[h], (unsigned long long)kEmpty,
+                              (unsigned long long)mine);
+              ++probe;
+              const bool stop = (old == kEmpty) | ((uint32_t)(old >> 32) == id) |
+                                (probe >= (uint32_t)HSLOTS);
+              if (stop) break;
+              h = (h + 1) & (HSLOTS - 1);
+            }
+            fresh = old == kEmpty;
+            // the probe bound is never reached while the fill bound holds
+            if (!fresh && (uint32_t)(old >> 32) != id) atomicOr(a.err, kErrTableFull);
+          }
+          pending = rfl_i32(pending + __popcll(__ballot(fresh)));
+          if (pending >= kPublish) {  // wave-uniform
+            // one lane publishes (a lane-varying operand would make the
+            // compiler scan over all lanes)
+            int32_t old = 0;
+            if (lane == 0) old = atomicAdd(&s_fill, pending);
+            if (__builtin_amdgcn_readlane(old, 0) + pending > HMAX) {
+              over = true;
+              s_over = 1;  // every lane stores the same value
+            }
+            pending = 0;
+          }
+        }
+        return __popcll(__ballot(in));
+      };
+      auto process1 = [&](const Batch& t, const uint32_t (&pin)[B]) {
+        int32_t cnt = 0;
+        uint32_t lastpin = kSent;
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          if (t.k + u < t.kend && !over) {  // wave-uniform
+            cnt += visit1(pin[u], (t.k + u) * kWave + lane < t.r);
+            if (t.k + u == t.kend - 1) lastpin = __builtin_amdgcn_readlane(pin[u], kWave - 1);
+          }
+        }
+        // the slice runs on past this batch iff the batch ends the
+        // hyperedge's listed chunks (or is a continuation), its last chunk is
+        // full (kend * 64 < r) and that chunk's last pin lies below the
+        // window end
+        if (t.runs_on && t.kend * kWave < t.r && (lastpin & kIdMask) < hi32 &&
+            !over) {  // wave-uniform
+          has_cont = true;
+          cont_j = t.j;
+          cont_k = t.kend;
+        }
+        if (lane == 0 && cnt) atomicAdd(&m_cnt[t.j], cnt);  // cnt = 0 when there is no batch
+        // every batch's loads are complete here, on every path (no batch
+        // never reads its registers otherwise), which keeps the compiler's
+        // count of loads in flight exact across the loop
+        asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
+      };
+      static_assert(B == 4, "the register uses name B registers");
+      {
+        Batch ta, tb2;
+        uint32_t pa[B], pb[B];
+        fetch(ta, pa, true);
+        while (true) {
+          if ((ta.j >= deg && !has_cont) || over) break;
+          fetch(tb2, pb, true);
+          process1(ta, pa);
+          if ((tb2.j >= deg && !has_cont) || over) break;
+          fetch(ta, pa, true);
+          process1(tb2, pb);
         }
       }
       if (pending > 0) {  // wave-uniform
         int32_t old = 0;
         if (lane == 0) old = atomicAdd(&s_fill, pending);
-        over = over || __builtin_amdgcn_readlane(old, 0) + pending > HMAX;
+        if (__builtin_amdgcn_readlane(old, 0) + pending > HMAX) s_over = 1;
       }
-      s_wover[wid] = over ? 1 : 0;  // every lane stores the same value
       __syncthreads();
-      bool any_over = false;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) any_over |= s_wover[w] != 0;
+      const bool any_over = s_over != 0;
       const int32_t fill = s_fill;
       for (int i = tid; i < kWords; i += THREADS) seen[i] = 0;
       if (any_over) {
@@ -819,7 +1020,18 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         width = width / 2 > 0 ? width / 2 : 1;
         continue;  // the loop head synchronises before the next window
       }
-      __syncthreads();  // bitmap cleared
+      // ---- sweep 2 batches: the exact slices ----
+      {
+        int32_t nbq[2] = {0, 0};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int32_t j = 2 * tid + q;
+          if (j < deg) nbq[q] = (m_cnt[j] + kWave - 1) / kWave;
+        }
+        list_batches(nbq[0], nbq[1], false, false, nc, tb);  // synchronises
+      }
+      bnext = wid;
+      ci = 0;
       if (fill > 0) {
         for (int i = tid; i < HSLOTS; i += THREADS) {
           const uint64_t s = rtab[i];
@@ -828,45 +1040,25 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
             atomicOr(&seen[rel >> 5], 1u << (rel & 31));
           }
         }
-        __syncthreads();  // bitmap holds the repeated ids
       }
+      __syncthreads();  // list written, bitmap holds the repeated ids
 
-      // ---- sweep 2: the slices [m_cur, m_tent) again ----
-      for (int32_t j0 = wid; j0 < deg; j0 += kBatch * NW) {
-        uint32_t pin[kBatch];
+      // ---- sweep 2 ----
+      auto process2 = [&](const Batch& t, const uint32_t (&pin)[B]) {
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-          const int32_t j = j0 + b * NW;
-          const int32_t js = j < deg ? j : j0;
-          const int32_t c0 = rfl_i32(m_cur[js]);
-          const int32_t sl = rfl_i32(m_tent[js]) - c0;
-          // a lane past the slice re-reads the slice's last pin, and an
-          // empty slice (possibly at the hyperedge's end) its first pin; such
-          // lanes are masked below
-          const int32_t p = sl > 0 ? c0 + (lane < sl ? lane : sl - 1) : 0;
-          pin[b] = a.L.pins[rfl_u32(m_start[js]) + (uint32_t)p];
-        }
-#pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-          const int32_t j = j0 + b * NW;
-          if (j >= deg) break;  // wave-uniform
-          const int32_t c0 = rfl_i32(m_cur[j]);
-          const int32_t sl = rfl_i32(m_tent[j]) - c0;
-          const uint32_t* seg = a.L.pins + rfl_u32(m_start[j]) + (uint32_t)c0;
-          const uint32_t wt = rfl_u32(m_w[j]);
-          uint32_t cur = pin[b];
-          for (int32_t c = 0; c < sl; c += kWave) {  // wave-uniform
-            const int32_t pn = c + kWave + lane;
-            uint32_t nxt = 0;
-            if (c + kWave < sl) nxt = seg[pn < sl ? pn : sl - 1];  // wave-uniform
-            const uint32_t id = cur & kIdMask;
-            const bool act = (c + lane < sl) & (id != n);
-            const uint32_t rel = id - lo32;  // in the window for every lane
+        for (int u = 0; u < B; ++u) {
+          if (t.k + u < t.kend) {  // wave-uniform
+            // lanes past the slice hold its last pin (inside the window)
+            const uint32_t id = pin[u] & kIdMask;
+            const bool act = ((t.k + u) * kWave + lane < t.r) & (id != n);
+            const uint32_t rel = id - lo32;
             const bool isrep = fill > 0 && ((seen[rel >> 5] >> (rel & 31)) & 1u);
-            const uint64_t key = ((uint64_t)wt << 32) | (uint64_t)(kSent - id);
-            if (act & !isrep & (key > best)) {
-              if (v.all_valid || merge_valid(a, v, id, 0)) best = key;
+            const uint64_t key = ((uint64_t)t.wt << 32) | (uint64_t)(kSent - id);
+            bool better = act & !isrep & (key > best);
+            if (!v.all_valid && __ballot(better) != 0) {  // wave-uniform
+              if (better) better = merge_valid(a, v, id, 0);
             }
+            best = better ? key : best;
             const bool add = act & isrep;
             if (__ballot(add) != 0) {  // wave-uniform
               if (add) {
@@ -882,13 +1074,27 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
                   h = (h + 1) & (HSLOTS - 1);
                 }
                 if ((uint32_t)(s >> 32) == id)
-                  atomicAdd((unsigned long long*)&rtab[h], (unsigned long long)wt);
+                  atomicAdd((unsigned long long*)&rtab[h], (unsigned long long)t.wt);
                 else  // every repeated id was entered in sweep 1
                   atomicOr(a.err, kErrTableFull);
               }
             }
-            cur = nxt;
           }
+        }
+        // as in sweep 1: every batch's loads are complete here
+        asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
+      };
+      {
+        Batch ta, tb2;
+        uint32_t pa[B], pb[B];
+        fetch(ta, pa, false);
+        while (true) {
+          if (ta.j >= deg) break;
+          fetch(tb2, pb, false);
+          process2(ta, pa);
+          if (tb2.j >= deg) break;
+          fetch(ta, pa, false);
+          process2(tb2, pb);
         }
       }
       __syncthreads();  // sweep 2 done: table complete
@@ -904,7 +1110,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
           }
         }
       }
-      for (int jj = tid; jj < deg; jj += THREADS) m_cur[jj] = m_tent[jj];
+      for (int jj = tid; jj < deg; jj += THREADS) m_cur[jj] += m_cnt[jj];
       lo = hi;
       if (fill < HMAX / 4 && width < (int64_t)kWinIds) {
         width *= 2;
