@@ -663,16 +663,19 @@ __device__ inline void block_scan_pair(int32_t x, int32_t y, int32_t& px, int32_
 // most kWinIds:
 //   sweep 1 visits the pins of every incident hyperedge from its cursor up
 //     to the window end, setting one LDS bit per id; a visit that finds its
-//     bit already set enters the id, as repeated, in a small LDS hash table
-//     (key only), and the pins below the window end are counted;
-//   the bitmap is then rebuilt to hold just the repeated ids;
+//     bit already set appends the id to a list of repeat visits, and the
+//     pins below the window end are counted;
+//   the bitmap is then rebuilt to hold just the repeated ids, and a prefix
+//     count per bitmap word gives every repeated id a dense rank (the number
+//     of repeated ids below it in the window);
 //   sweep 2 visits the same pins again: a repeated id adds the hyperedge
-//     weight to its table entry, any other id has its complete score and is
-//     compared with the lane's best;
-//   the table is folded into the best (validity tested only for entries that
-//     beat it) and emptied, and the cursors move past the counted pins.
-// A window whose repeated ids would overfill the table is abandoned and
-// retried at half the width.
+//     weight to the score at its rank, any other id has its complete score
+//     and is compared with the lane's best;
+//   the repeated ids' scores are folded into the best (validity tested only
+//     for those that beat it), and the cursors move past the counted pins.
+// No step probes a table: each visit is one LDS bit operation, and a
+// repeated one one more LDS add.  A window whose repeat visits overflow the
+// list is abandoned and retried at half the width.
 //
 // Work balance: hyperedge sizes follow a heavy-tailed law, so each sweep cuts
 // the vertex's slices into batches of B chunks (64 pins each), numbers the
@@ -694,14 +697,16 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
   constexpr int B = 4;  // chunks per batch
   constexpr uint32_t kWinIds = 1u << 19;
   constexpr int kWords = (int)(kWinIds / 32);
-  constexpr int HSLOTS = 4096;
-  constexpr int HMAX = 2560;
-  constexpr int kPublish = 16;
+  constexpr int kList = 4096;  // repeat visits of a window (sweep 1)
+  constexpr int kWordsPerThread = kWords / THREADS;
   constexpr uint32_t kSent = 0x7FFFFFFFu;
-  static_assert(HMAX + NW * (kPublish + kWave) < HSLOTS, "table must never fill up");
+  static_assert(kWords % THREADS == 0, "every thread owns the same number of words");
   static_assert(kMetaDeg <= 2 * THREADS, "a thread lists at most two hyperedges");
   __shared__ uint32_t seen[kWords];
-  __shared__ uint64_t rtab[HSLOTS];
+  // sweep 1: the ids of repeat visits; sweep 2 and after: the score of the
+  // repeated id of each rank (there are at most as many as repeat visits)
+  __shared__ uint32_t lst[kList];
+  __shared__ uint16_t wpre[kWords];  // repeated ids in the words before each word
   __shared__ uint32_t m_start[kMetaDeg];  // pin offsets are below 2^31
   __shared__ int32_t m_len[kMetaDeg];
   __shared__ int32_t m_w[kMetaDeg];
@@ -714,10 +719,11 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
   __shared__ int32_t ws[2 * NW];
   __shared__ uint64_t red[2 * NW];
   __shared__ int32_t s_item;
-  __shared__ int32_t s_fill;
-  __shared__ int32_t s_over;  // the window overflowed the table
+  __shared__ int32_t s_nrep;  // repeat visits appended in sweep 1
+  __shared__ int32_t s_over;  // the window overflowed the list
 
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int wid = rfl_i32(tid / kWave);  // the same in every lane: keep it scalar
   int32_t count = a.b.count[bucket];
   if (count > maxV) {
     if (tid == 0) atomicOr(a.err, kErrWorkCount);
@@ -725,8 +731,6 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
   }
   const int32_t* list = a.b.list + (int64_t)bucket * maxV;
   for (int i = tid; i < kWords; i += THREADS) seen[i] = 0;
-  for (int i = tid; i < HSLOTS; i += THREADS) rtab[i] = kEmpty;
-  const int hshift = 32 - log2_pow2(HSLOTS);
 
   while (true) {
     __syncthreads();
@@ -792,20 +796,27 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     };
 
     // A batch: hyperedge j (deg: no more work), chunks k .. kend - 1 of its
-    // slice, which starts at seg and has r pins left (sweep 1) or exactly r
-    // pins (sweep 2).
+    // slice, which starts at pin `base` and has r pins left (sweep 1) or
+    // exactly r pins (sweep 2).
     struct Batch {
       int32_t j, k, kend, r;
       bool runs_on;  // sweep 1: the slice may go on past chunk kend - 1, the last
                      // chunk listed for the hyperedge
       uint32_t wt;
-      const uint32_t* seg;
+      uint32_t base;  // pin offsets are below 2^31
     };
-    const uint32_t* dummy = a.L.pins + rfl_u32(m_start[0]);
+    const uint32_t dummy = rfl_u32(m_start[0]);
     int32_t nc = 0, tb = 0;  // listed hyperedges, batches of the current sweep
     int32_t bnext = 0, ci = 0;
     bool has_cont = false;
     int32_t cont_j = 0, cont_k = 0;
+    // Keeps a batch buffer's registers live until the point where they are
+    // refilled, so that the register allocator does not reuse them as
+    // temporaries in between (a temporary in a register whose load the
+    // compiler cannot prove complete costs a wait for every load in flight).
+    auto hold = [](uint32_t (&pin)[B]) {
+      asm volatile("" : "+v"(pin[0]), "+v"(pin[1]), "+v"(pin[2]), "+v"(pin[3]));
+    };
     // The wave's next batch; its loads are issued at once (for no batch, at
     // an address inside the pins, so that every path issues B loads).
     auto fetch = [&](Batch& t, uint32_t (&pin)[B], bool sweep1) {
@@ -837,7 +848,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       if (ov != 0 && sweep1) t.j = deg;
       if (t.j < deg) {  // wave-uniform
         const int32_t c0 = rfl_i32(m_cur[t.j]);
-        t.seg = a.L.pins + rfl_u32(m_start[t.j]) + (uint32_t)c0;
+        t.base = rfl_u32(m_start[t.j]) + (uint32_t)c0;
         t.wt = rfl_u32(m_w[t.j]);
         if (sweep1) {
           t.r = rfl_i32(m_len[t.j]) - c0;
@@ -854,16 +865,25 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         }
       } else {
         t.r = 1;
-        t.seg = dummy;
+        t.base = dummy;
         t.k = 0;
         t.kend = 0;
         t.wt = 0;
         t.runs_on = false;
       }
+      // the fields are wave-uniform; say so, so that the tests on them in the
+      // chunk loops stay scalar
+      t.j = rfl_i32(t.j);
+      t.k = rfl_i32(t.k);
+      t.kend = rfl_i32(t.kend);
+      t.r = rfl_i32(t.r);
+      t.wt = rfl_u32(t.wt);
+      t.runs_on = rfl_i32(t.runs_on ? 1 : 0) != 0;
+      t.base = rfl_u32(t.base);
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         const int32_t p = (t.k + u) * kWave + lane;
-        pin[u] = t.seg[p < t.r ? p : t.r - 1];
+        pin[u] = a.L.pins[t.base + (uint32_t)(p < t.r ? p : t.r - 1)];
       }
     };
 
@@ -910,7 +930,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         }
       }
       if (tid == 0) {
-        s_fill = 0;
+        s_nrep = 0;
         s_over = 0;
       }
       __syncthreads();
@@ -919,62 +939,58 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       has_cont = false;
 
       // ---- sweep 1 ----
-      int32_t pending = 0;  // repeated ids entered by this wave, not yet published
       bool over = false;
-      // one chunk: bits, repeated ids, returns the pins below the window end
-      auto visit1 = [&](uint32_t pin, bool valid) -> int32_t {
-        const uint32_t id = pin & kIdMask;
-        const bool in = valid & (id < hi32);  // ids >= lo: cursor order
-        const bool act = in & (id != n);
-        // branch-free: an idle lane ors 0 into a word of its own
-        const uint32_t rel = id - lo32;
-        const uint32_t word = act ? rel >> 5 : (uint32_t)lane;
-        const uint32_t bit = act ? 1u << (rel & 31) : 0u;
-        const bool rep = (atomicOr(&seen[word], bit) & bit) != 0;
-        if (__ballot(rep) != 0) {  // wave-uniform; rare in sparse neighbourhoods
-          bool fresh = false;
-          if (rep) {
-            uint32_t h = slot_hash(id, hshift);
-            const uint64_t mine = (uint64_t)id << 32;
-            uint64_t old;
-            uint32_t probe = 0;
-            while (true) {
-              old = atomicCAS((unsigned long long*)&rtab[h], (unsigned long long)kEmpty,
-                              (unsigned long long)mine);
-              ++probe;
-              const bool stop = (old == kEmpty) | ((uint32_t)(old >> 32) == id) |
-                                (probe >= (uint32_t)HSLOTS);
-              if (stop) break;
-              h = (h + 1) & (HSLOTS - 1);
+      // A batch of sweep 1: the B chunks' bitmap updates are issued back to
+      // back (one wait for all of them); chunks past kend, lanes past the
+      // slice and pins at or above the window end or equal to n update a
+      // word of their own with 0.  The repeat visits of the batch are
+      // appended to the list with one single-lane atomic.
+      auto process1 = [&](const Batch& t, const uint32_t (&pin)[B]) {
+        uint32_t id[B], bit[B], old[B];
+        bool in[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          id[u] = pin[u] & kIdMask;
+          const bool live = (t.k + u < t.kend) & ((t.k + u) * kWave + lane < t.r);
+          in[u] = live & (id[u] < hi32);  // ids >= lo: cursor order
+          const bool act = in[u] & (id[u] != n);
+          const uint32_t rel = id[u] - lo32;
+          const uint32_t word = act ? rel >> 5 : (uint32_t)lane;
+          bit[u] = act ? 1u << (rel & 31) : 0u;
+          old[u] = atomicOr(&seen[word], bit[u]);
+        }
+        bool rep[B];
+        uint64_t rb[B];
+        int32_t nr = 0;
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          rep[u] = (old[u] & bit[u]) != 0;
+          rb[u] = __ballot(rep[u]);
+          nr += (int32_t)__popcll(rb[u]);
+        }
+        if (nr > 0 && !over) {  // wave-uniform
+          int32_t base = 0;
+          if (lane == 0) base = atomicAdd(&s_nrep, nr);
+          base = __builtin_amdgcn_readlane(base, 0);
+          if (base + nr > kList) {
+            over = true;
+            s_over = 1;  // every lane stores the same value
+          } else {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+              const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                  (uint32_t)(rb[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)rb[u], 0u));
+              if (rep[u]) lst[base + (int32_t)below] = id[u];
+              base += (int32_t)__popcll(rb[u]);
             }
-            fresh = old == kEmpty;
-            // the probe bound is never reached while the fill bound holds
-            if (!fresh && (uint32_t)(old >> 32) != id) atomicOr(a.err, kErrTableFull);
-          }
-          pending = rfl_i32(pending + __popcll(__ballot(fresh)));
-          if (pending >= kPublish) {  // wave-uniform
-            // one lane publishes (a lane-varying operand would make the
-            // compiler scan over all lanes)
-            int32_t old = 0;
-            if (lane == 0) old = atomicAdd(&s_fill, pending);
-            if (__builtin_amdgcn_readlane(old, 0) + pending > HMAX) {
-              over = true;
-              s_over = 1;  // every lane stores the same value
-            }
-            pending = 0;
           }
         }
-        return __popcll(__ballot(in));
-      };
-      auto process1 = [&](const Batch& t, const uint32_t (&pin)[B]) {
         int32_t cnt = 0;
         uint32_t lastpin = kSent;
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-          if (t.k + u < t.kend && !over) {  // wave-uniform
-            cnt += visit1(pin[u], (t.k + u) * kWave + lane < t.r);
-            if (t.k + u == t.kend - 1) lastpin = __builtin_amdgcn_readlane(pin[u], kWave - 1);
-          }
+          cnt += __popcll(__ballot(in[u]));
+          if (t.k + u == t.kend - 1) lastpin = __builtin_amdgcn_readlane(pin[u], kWave - 1);
         }
         // the slice runs on past this batch iff the batch ends the
         // hyperedge's listed chunks (or is a continuation), its last chunk is
@@ -999,24 +1015,20 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         fetch(ta, pa, true);
         while (true) {
           if ((ta.j >= deg && !has_cont) || over) break;
+          hold(pb);
           fetch(tb2, pb, true);
           process1(ta, pa);
           if ((tb2.j >= deg && !has_cont) || over) break;
+          hold(pa);
           fetch(ta, pa, true);
           process1(tb2, pb);
         }
       }
-      if (pending > 0) {  // wave-uniform
-        int32_t old = 0;
-        if (lane == 0) old = atomicAdd(&s_fill, pending);
-        if (__builtin_amdgcn_readlane(old, 0) + pending > HMAX) s_over = 1;
-      }
       __syncthreads();
-      const bool any_over = s_over != 0;
-      const int32_t fill = s_fill;
+      const bool any_over = s_over != 0 || s_nrep > kList;
+      const int32_t nrep = s_nrep < kList ? s_nrep : kList;
       for (int i = tid; i < kWords; i += THREADS) seen[i] = 0;
       if (any_over) {
-        for (int i = tid; i < HSLOTS; i += THREADS) rtab[i] = kEmpty;
         width = width / 2 > 0 ? width / 2 : 1;
         continue;  // the loop head synchronises before the next window
       }
@@ -1032,52 +1044,64 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       }
       bnext = wid;
       ci = 0;
-      if (fill > 0) {
-        for (int i = tid; i < HSLOTS; i += THREADS) {
-          const uint64_t s = rtab[i];
-          if (s != kEmpty) {
-            const uint32_t rel = (uint32_t)(s >> 32) - lo32;
-            atomicOr(&seen[rel >> 5], 1u << (rel & 31));
-          }
-        }
+      // the bitmap of repeated ids (it was cleared before the list was
+      // built) and the rank prefix of every word; the scores start at 0
+      for (int i = tid; i < nrep; i += THREADS) {
+        const uint32_t rel = lst[i] - lo32;
+        atomicOr(&seen[rel >> 5], 1u << (rel & 31));
       }
-      __syncthreads();  // list written, bitmap holds the repeated ids
+      int32_t nrank = 0;  // repeated ids of the window
+      if (nrep > 0) {     // block-uniform
+        __syncthreads();
+        const int w0 = tid * kWordsPerThread;
+        int32_t mine = 0;
+#pragma unroll
+        for (int i = 0; i < kWordsPerThread; ++i) mine += __popc(seen[w0 + i]);
+        int32_t pre, unused0, unused1;
+        block_scan_pair<THREADS>(mine, 0, pre, unused0, nrank, unused1, ws);
+#pragma unroll
+        for (int i = 0; i < kWordsPerThread; ++i) {
+          wpre[w0 + i] = (uint16_t)pre;
+          pre += __popc(seen[w0 + i]);
+        }
+        for (int i = tid; i < nrank; i += THREADS) lst[i] = 0;
+      }
+      __syncthreads();  // list of batches, bitmap, ranks and scores ready
 
       // ---- sweep 2 ----
       auto process2 = [&](const Batch& t, const uint32_t (&pin)[B]) {
+        // the B chunks' bitmap reads are issued back to back
+        uint32_t id[B], w[B];
+        bool act[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-          if (t.k + u < t.kend) {  // wave-uniform
-            // lanes past the slice hold its last pin (inside the window)
-            const uint32_t id = pin[u] & kIdMask;
-            const bool act = ((t.k + u) * kWave + lane < t.r) & (id != n);
-            const uint32_t rel = id - lo32;
-            const bool isrep = fill > 0 && ((seen[rel >> 5] >> (rel & 31)) & 1u);
-            const uint64_t key = ((uint64_t)t.wt << 32) | (uint64_t)(kSent - id);
-            bool better = act & !isrep & (key > best);
-            if (!v.all_valid && __ballot(better) != 0) {  // wave-uniform
-              if (better) better = merge_valid(a, v, id, 0);
-            }
-            best = better ? key : best;
-            const bool add = act & isrep;
-            if (__ballot(add) != 0) {  // wave-uniform
-              if (add) {
-                uint32_t h = slot_hash(id, hshift);
-                uint64_t s;
-                uint32_t probe = 0;
-                while (true) {
-                  s = rtab[h];
-                  ++probe;
-                  const bool stop = ((uint32_t)(s >> 32) == id) | (s == kEmpty) |
-                                    (probe >= (uint32_t)HSLOTS);
-                  if (stop) break;
-                  h = (h + 1) & (HSLOTS - 1);
-                }
-                if ((uint32_t)(s >> 32) == id)
-                  atomicAdd((unsigned long long*)&rtab[h], (unsigned long long)t.wt);
-                else  // every repeated id was entered in sweep 1
-                  atomicOr(a.err, kErrTableFull);
-              }
+          // lanes past the slice hold its last pin (inside the window)
+          id[u] = pin[u] & kIdMask;
+          act[u] = (t.k + u < t.kend) & ((t.k + u) * kWave + lane < t.r) & (id[u] != n);
+          w[u] = seen[(id[u] - lo32) >> 5];
+        }
+        bool anyadd = false;
+        bool add[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const bool isrep = ((w[u] >> ((id[u] - lo32) & 31)) & 1u) != 0;
+          const uint64_t key = ((uint64_t)t.wt << 32) | (uint64_t)(kSent - id[u]);
+          bool better = act[u] & !isrep & (key > best);
+          if (!v.all_valid && __ballot(better) != 0) {  // wave-uniform
+            if (better) better = merge_valid(a, v, id[u], 0);
+          }
+          best = better ? key : best;
+          add[u] = act[u] & isrep;
+          anyadd |= add[u];
+        }
+        if (__ballot(anyadd) != 0) {  // wave-uniform
+#pragma unroll
+          for (int u = 0; u < B; ++u) {
+            if (add[u]) {
+              const uint32_t rel = id[u] - lo32;
+              const uint32_t rank =
+                  (uint32_t)wpre[rel >> 5] + (uint32_t)__popc(w[u] & ((1u << (rel & 31)) - 1u));
+              atomicAdd(&lst[rank], t.wt);
             }
           }
         }
@@ -1090,29 +1114,34 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         fetch(ta, pa, false);
         while (true) {
           if (ta.j >= deg) break;
+          hold(pb);
           fetch(tb2, pb, false);
           process2(ta, pa);
           if (tb2.j >= deg) break;
+          hold(pa);
           fetch(ta, pa, false);
           process2(tb2, pb);
         }
       }
-      __syncthreads();  // sweep 2 done: table complete
-      if (fill > 0) {
-        for (int i = tid; i < HSLOTS; i += THREADS) {
-          const uint64_t s = rtab[i];
-          if (s != kEmpty) {
-            const uint32_t id = (uint32_t)(s >> 32);
-            const uint64_t key = ((s & 0xFFFFFFFFull) << 32) | (uint64_t)(kSent - id);
+      __syncthreads();  // sweep 2 done: scores complete
+      if (nrank > 0) {    // block-uniform
+        const int w0 = tid * kWordsPerThread;
+        for (int i = 0; i < kWordsPerThread; ++i) {
+          uint32_t bits = seen[w0 + i];
+          uint32_t r = wpre[w0 + i];
+          while (bits) {
+            const uint32_t b = (uint32_t)__ffs(bits) - 1;
+            bits &= bits - 1;
+            const uint32_t id = lo32 + (uint32_t)(w0 + i) * 32u + b;
+            const uint64_t key = ((uint64_t)lst[r++] << 32) | (uint64_t)(kSent - id);
             if (key > best && (v.all_valid || merge_valid(a, v, id, 0))) best = key;
-            rtab[i] = kEmpty;
-            seen[(id - lo32) >> 5] = 0;
           }
+          seen[w0 + i] = 0;
         }
       }
       for (int jj = tid; jj < deg; jj += THREADS) m_cur[jj] += m_cnt[jj];
       lo = hi;
-      if (fill < HMAX / 4 && width < (int64_t)kWinIds) {
+      if (nrep < kList / 4 && width < (int64_t)kWinIds) {
         width *= 2;
         if (width > (int64_t)kWinIds) width = kWinIds;
       }
