@@ -534,7 +534,7 @@ def main():
                    "coarse_hyperedges": C.E, "coarse_pins": C.P},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "score_stream_kernel<1024,16384,false> (Eq. 12 scores and candidates)",
+                     "kernel": "score_window_kernel<1024> (Eq. 12 scores and candidates)",
                      "algorithmic_bytes": b_s2, "ms_per_launch": phases["score"]},
         "level_hbm_frac": b_level / (ms_step / 1000.0) / 1e9 / HBM_PEAK_GBS,
         "phases_ms": phases,
