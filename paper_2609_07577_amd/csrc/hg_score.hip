@@ -698,9 +698,10 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
   constexpr uint32_t kWinIds = 1u << 19;
   constexpr int kWords = (int)(kWinIds / 32);
   constexpr int kList = 4096;  // repeat visits of a window (sweep 1)
-  constexpr int kWordsPerThread = kWords / THREADS;
+  constexpr int kWordsPerWave = kWords / NW;  // words a wave ranks and drains
+  constexpr int kRows = kWordsPerWave / kWave;
   constexpr uint32_t kSent = 0x7FFFFFFFu;
-  static_assert(kWords % THREADS == 0, "every thread owns the same number of words");
+  static_assert(kWords % (NW * kWave) == 0, "every wave owns whole rows of words");
   static_assert(kMetaDeg <= 2 * THREADS, "a thread lists at most two hyperedges");
   __shared__ uint32_t seen[kWords];
   // sweep 1: the ids of repeat visits; sweep 2 and after: the score of the
@@ -1050,19 +1051,34 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         const uint32_t rel = lst[i] - lo32;
         atomicOr(&seen[rel >> 5], 1u << (rel & 31));
       }
+      // Wave w ranks the words [w * kWordsPerWave, (w + 1) * kWordsPerWave)
+      // in rows of 64 consecutive words, one per lane (no bank conflicts);
+      // the waves' totals are scanned across the block.
       int32_t nrank = 0;  // repeated ids of the window
       if (nrep > 0) {     // block-uniform
         __syncthreads();
-        const int w0 = tid * kWordsPerThread;
-        int32_t mine = 0;
+        int32_t wave_total = 0;
+#pragma unroll 4
+        for (int r = 0; r < kRows; ++r) wave_total += __popc(seen[wid * kWordsPerWave + r * kWave + lane]);
 #pragma unroll
-        for (int i = 0; i < kWordsPerThread; ++i) mine += __popc(seen[w0 + i]);
-        int32_t pre, unused0, unused1;
-        block_scan_pair<THREADS>(mine, 0, pre, unused0, nrank, unused1, ws);
+        for (int d = kWave / 2; d > 0; d >>= 1) wave_total += __shfl_xor(wave_total, d, kWave);
+        int32_t before, unused0, unused1;
+        // one pair per thread: lane 0 of each wave carries the wave's total
+        block_scan_pair<THREADS>(lane == 0 ? wave_total : 0, 0, before, unused0, nrank, unused1,
+                                 ws);
+        int32_t run = __builtin_amdgcn_readlane(before, 0);
+#pragma unroll 4
+        for (int r = 0; r < kRows; ++r) {
+          const int wi = wid * kWordsPerWave + r * kWave + lane;
+          const int32_t c = __popc(seen[wi]);
+          int32_t inc = c;
 #pragma unroll
-        for (int i = 0; i < kWordsPerThread; ++i) {
-          wpre[w0 + i] = (uint16_t)pre;
-          pre += __popc(seen[w0 + i]);
+          for (int d = 1; d < kWave; d <<= 1) {
+            const int32_t o = __shfl_up(inc, d, kWave);
+            inc += lane >= d ? o : 0;
+          }
+          wpre[wi] = (uint16_t)(run + inc - c);
+          run += __builtin_amdgcn_readlane(inc, kWave - 1);
         }
         for (int i = tid; i < nrank; i += THREADS) lst[i] = 0;
       }
@@ -1070,6 +1086,11 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
 
       // ---- sweep 2 ----
       auto process2 = [&](const Batch& t, const uint32_t (&pin)[B]) {
+        if (t.j >= deg) {  // wave-uniform: no batch (its pins may lie outside
+                           // the window; they are not looked at)
+          asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
+          return;
+        }
         // the B chunks' bitmap reads are issued back to back
         uint32_t id[B], w[B];
         bool act[B];
@@ -1124,19 +1145,21 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         }
       }
       __syncthreads();  // sweep 2 done: scores complete
-      if (nrank > 0) {    // block-uniform
-        const int w0 = tid * kWordsPerThread;
-        for (int i = 0; i < kWordsPerThread; ++i) {
-          uint32_t bits = seen[w0 + i];
-          uint32_t r = wpre[w0 + i];
-          while (bits) {
-            const uint32_t b = (uint32_t)__ffs(bits) - 1;
-            bits &= bits - 1;
-            const uint32_t id = lo32 + (uint32_t)(w0 + i) * 32u + b;
-            const uint64_t key = ((uint64_t)lst[r++] << 32) | (uint64_t)(kSent - id);
-            if (key > best && (v.all_valid || merge_valid(a, v, id, 0))) best = key;
+      if (nrank > 0) {    // block-uniform; words in the ranking's order
+        for (int r = 0; r < kRows; ++r) {
+          const int wi = wid * kWordsPerWave + r * kWave + lane;
+          uint32_t bits = seen[wi];
+          if (bits) {
+            uint32_t rk = wpre[wi];
+            while (bits) {
+              const uint32_t b = (uint32_t)__ffs(bits) - 1;
+              bits &= bits - 1;
+              const uint32_t id = lo32 + (uint32_t)wi * 32u + b;
+              const uint64_t key = ((uint64_t)lst[rk++] << 32) | (uint64_t)(kSent - id);
+              if (key > best && (v.all_valid || merge_valid(a, v, id, 0))) best = key;
+            }
+            seen[wi] = 0;
           }
-          seen[w0 + i] = 0;
         }
       }
       for (int jj = tid; jj < deg; jj += THREADS) m_cur[jj] += m_cnt[jj];

@@ -306,3 +306,44 @@ def test_out_of_range_maps_are_rejected(ctx):
             ctx.sync()
         assert ei.value.code == 1, (what, ei.value)
         assert int(ctx.connectivity(L, good).item()) == expect_conn, f"after {what}"
+
+
+def _window_bucket_vertices(g, load16=8, big_slots=16384):
+    """Vertices the score step gives to the multipass window kernel: the
+    distinct-neighbour bound min(X_n, V - 1) above the single-pass capacity
+    (load16/16 of the big table) with at most 1280 incident hyperedges
+    (the overlap bound cannot bind for these level-0 limits)."""
+    L0 = oracle.level0(g)
+    lens = np.diff(L0.eoff).astype(np.int64)
+    edge_of_pin = np.repeat(np.arange(L0.E), lens)
+    ids = (L0.pins & 0x7FFFFFFF).astype(np.int64)
+    xn = np.bincount(ids, weights=lens[edge_of_pin], minlength=g.n_vertices)
+    deg = np.bincount(ids, minlength=g.n_vertices)
+    dist = np.minimum(xn, g.n_vertices - 1)
+    return np.flatnonzero((dist > big_slots * load16 // 16) & (deg <= 1280))
+
+
+def test_window_list_overflow_halves_the_window(ctx):
+    """Every neighbour of the 9000 targets is shared by four hyperedges, so a
+    window of the multipass score step holds three repeat visits per id and
+    overflows its list of repeat visits until the window is narrowed to a
+    couple of thousand ids; the result must be the oracle's."""
+    nt = 9000
+    axons = [(nt + i, list(range(nt)), w) for i, w in enumerate((3, 5, 2, 7))]
+    g = synth.from_axons(nt + 4, axons)
+    assert len(_window_bucket_vertices(g)) >= nt
+    run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
+
+
+def test_window_slice_runs_past_its_estimate(ctx):
+    """Three hyperedges whose pins are 4000 consecutive low ids plus one id
+    near the top of a 600,000-vertex level: the id-density estimate of a
+    window's slice falls far short, so the kernel must continue the slice
+    past its estimated batches (and, with every target repeated, also
+    narrow the window); the level must equal the oracle's."""
+    n = 600_000
+    axons = [(n - 10 + i, list(range(4000)), w) for i, w in enumerate((4, 9, 1))]
+    axons.append((n - 1, sorted(set(range(0, n - 20, 997)) - {n - 1}), 2))
+    g = synth.from_axons(n, axons)
+    assert len(_window_bucket_vertices(g)) >= 4000
+    run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
