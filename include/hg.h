@@ -196,13 +196,16 @@ int hg_contract(hg_ctx* ctx, const hg_level* in, const int32_t* vmap,
 int hg_connectivity(hg_ctx* ctx, const hg_level* lvl, const int32_t* part, int64_t* conn);
 
 /*
- * Score-step tuning of a context.  The score step (Eq. 12) accumulates a
- * vertex's neighbours in an on-chip table.  Vertices whose expansion (sum of
- * the sizes of their incident hyperedges) is at most single_pass_load16/16 of
- * a table's slots are scored in one pass; larger ones in passes over ranges
- * of neighbour ids, each range aimed at pass_fill16/16 of the table.  Results
- * never depend on these values, only the speed does.  Defaults 8 and 5;
- * accepted ranges 1..12 and 1..10 (HG_ERR_INVALID_ARG otherwise).
+ * Score-step tuning of a context.  The score step (Eq. 12) scores a vertex in
+ * one pass over an on-chip table when its distinct-neighbour bound (its
+ * expansion, the sum of the sizes of its incident hyperedges, capped by the
+ * vertex count) is at most single_pass_load16/16 of the table's slots.
+ * Larger neighbourhoods are scored in windows of neighbour ids with an
+ * on-chip bitmap.  Where the distinct-axon overlap of Section 3 can bind,
+ * they are scored in passes over a table, each range aimed at
+ * pass_fill16/16 of it.  Results never depend on these values, only the
+ * speed does.  Defaults 8 and 5; accepted ranges 1..12 and 1..10
+ * (HG_ERR_INVALID_ARG otherwise).
  */
 typedef struct {
   int32_t single_pass_load16;

@@ -1,10 +1,11 @@
 """Autotuner of the score-step settings (``hg_tuning``).
 
 The score step (Eq. 12) scores a vertex in one pass over an on-chip table
-when its expansion is at most ``single_pass_load16``/16 of the table, and in
-passes over ranges of neighbour ids otherwise, each range aimed at
-``pass_fill16``/16 of the table.  Results never depend on these settings;
-the best ones depend on the degree and hyperedge-size mix of the workload.
+when its distinct-neighbour bound is at most ``single_pass_load16``/16 of
+the table, and in windows of neighbour ids otherwise (in passes over a table
+aimed at ``pass_fill16``/16 of it where the distinct-axon overlap can bind).
+Results never depend on these settings; the best ones depend on the degree
+and hyperedge-size mix of the workload.
 ``autotune`` times one coarsening level of sample levels under each
 candidate setting and keeps the fastest.
 """
