@@ -124,13 +124,14 @@ void level0_state(const Dims* d, const int64_t* eoff, const uint32_t* pins, int6
 // bucket lists for the scoring kernels.
 // Buckets 0-3 without, 4-7 with the shared-inbound count: single pass in the
 // small table, single pass in the big table, multipass with the incident
-// hyperedges staged in LDS (degree <= kMetaDeg), multipass with them read
+// hyperedges staged in LDS (degree <= kWinDeg), multipass with them read
 // from global memory.
 constexpr int kNumBuckets = 8;
 constexpr int kSmallSlots = 4096;
 constexpr int kBigSlots = 16384;
 constexpr int kBigSlotsOv = 8192;
 constexpr int kMetaDeg = 1280;
+constexpr int kWinDeg = 1024;  // incident hyperedges of a window-kernel vertex
 struct Buckets {
   int32_t* count;  // [kNumBuckets] device counters
   int32_t* list;   // [kNumBuckets * maxV]

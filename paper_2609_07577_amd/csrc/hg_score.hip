@@ -622,18 +622,26 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
 
 // Exclusive scan over the block of one pair (x, y) per thread: prefix sums
 // (px, py) and block totals (tx, ty).  ws holds 2 * THREADS / 64 ints.
+// Inclusive prefix sum over the 64 lanes of a wave with the DPP unit: four
+// shifts within rows of 16 lanes, then the row totals carried into the later
+// rows with the row broadcasts (lanes shifted in from outside a row, and
+// rows a step leaves out, add 0).
+__device__ inline int32_t wave_incl_scan(int32_t x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 to rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 to rows 2, 3
+  return x;
+}
+
 template <int THREADS>
 __device__ inline void block_scan_pair(int32_t x, int32_t y, int32_t& px, int32_t& py,
                                        int32_t& tx, int32_t& ty, int32_t* ws) {
   constexpr int NW = THREADS / kWave;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  int32_t ix = x, iy = y;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int32_t ox = __shfl_up(ix, d, kWave), oy = __shfl_up(iy, d, kWave);
-    ix += lane >= d ? ox : 0;
-    iy += lane >= d ? oy : 0;
-  }
+  const int32_t ix = wave_incl_scan(x), iy = wave_incl_scan(y);
   if (lane == kWave - 1) {
     ws[wid] = ix;
     ws[NW + wid] = iy;
@@ -663,8 +671,8 @@ __device__ inline void block_scan_pair(int32_t x, int32_t y, int32_t& px, int32_
 // most kWinIds:
 //   sweep 1 visits the pins of every incident hyperedge from its cursor up
 //     to the window end, setting one LDS bit per id; a visit that finds its
-//     bit already set appends the id to a list of repeat visits, and the
-//     pins below the window end are counted;
+//     bit already set appends the id to the wave's part of a list of repeat
+//     visits, and the pins below the window end are counted;
 //   the bitmap is then rebuilt to hold just the repeated ids, and a prefix
 //     count per bitmap word gives every repeated id a dense rank (the number
 //     of repeated ids below it in the window);
@@ -674,54 +682,74 @@ __device__ inline void block_scan_pair(int32_t x, int32_t y, int32_t& px, int32_
 //   the repeated ids' scores are folded into the best (validity tested only
 //     for those that beat it), and the cursors move past the counted pins.
 // No step probes a table: each visit is one LDS bit operation, and a
-// repeated one one more LDS add.  A window whose repeat visits overflow the
-// list is abandoned and retried at half the width.
+// repeated one one more LDS add.  A window whose repeat visits overflow a
+// wave's part of the list is abandoned and retried at half the width.
 //
 // Work balance: hyperedge sizes follow a heavy-tailed law, so each sweep cuts
 // the vertex's slices into batches of B chunks (64 pins each), numbers the
 // batches of all hyperedges in a row, and deals them to the waves round
-// robin; a wave finds the hyperedge of its next batch with one LDS read per
-// lane and a ballot over a compact list of the hyperedges that have batches.
-// A wave issues the B loads of its next batch before it processes the
-// current one, so up to 2B loads are in flight.  In sweep 1 the slice end is
-// not known in advance: the batches cover an estimate of it (from the pins'
-// id density, plus two standard deviations and a chunk), every pin is tested
-// against the window end, and when a slice runs on past its batches the wave
-// holding the last of them continues with further batches until the end.
-// The count of pins below the window end is exact whatever the estimate; a
-// poor one only costs loads.
+// robin.  The listed hyperedges carry everything a wave needs to load and
+// process a batch (slice start, pin count, chunk count, weight), so a wave
+// finds its next batch with one LDS read per lane, a ballot and a few
+// readlanes.  A wave issues the B loads of its next batch before it
+// processes the current one.  In sweep 1 the slice end is not known in
+// advance: the batches cover an estimate of it (from the pins' id density,
+// plus two standard deviations and a chunk), every pin is tested against
+// the window end, and when a slice runs on past its batches the wave holding
+// the last of them continues with further batches until the end.  The count
+// of pins below the window end is exact whatever the estimate; a poor one
+// only costs loads.
+//
+// The sweeps are bound by instruction issue (a batch holds 150-250 useful
+// pins), so the per-batch bookkeeping is kept scalar and short: batch
+// fields are a pin offset and a pin count, lanes are tested against the
+// count with one compare per chunk, and loads take a scalar base and a
+// lane offset clamped to the batch's last live pin.
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int bucket,
                                                               int64_t maxV) {
   constexpr int NW = THREADS / kWave;
   constexpr int B = 4;  // chunks per batch
+  constexpr int kBatchPins = B * kWave;
   constexpr uint32_t kWinIds = 1u << 19;
   constexpr int kWords = (int)(kWinIds / 32);
-  constexpr int kList = 4096;  // repeat visits of a window (sweep 1)
-  constexpr int kWordsPerWave = kWords / NW;  // words a wave ranks and drains
-  constexpr int kRows = kWordsPerWave / kWave;
+  constexpr int kList = 4096;        // repeat visits of a window (sweep 1)
+  constexpr int kSeg = kList / NW;   // a wave's part of the list
   constexpr uint32_t kSent = 0x7FFFFFFFu;
-  static_assert(kWords % (NW * kWave) == 0, "every wave owns whole rows of words");
-  static_assert(kMetaDeg <= 2 * THREADS, "a thread lists at most two hyperedges");
-  __shared__ uint32_t seen[kWords];
-  // sweep 1: the ids of repeat visits; sweep 2 and after: the score of the
-  // repeated id of each rank (there are at most as many as repeat visits)
-  __shared__ uint32_t lst[kList];
-  __shared__ uint16_t wpre[kWords];  // repeated ids in the words before each word
-  __shared__ uint32_t m_start[kMetaDeg];  // pin offsets are below 2^31
-  __shared__ int32_t m_len[kMetaDeg];
-  __shared__ int32_t m_w[kMetaDeg];
-  __shared__ uint32_t m_last[kMetaDeg];   // largest id of the hyperedge
-  __shared__ int32_t m_cur[kMetaDeg];     // cursor: pins below the window
-  __shared__ int32_t m_nb[kMetaDeg];      // sweep 1: chunks covered by batches
-  __shared__ int32_t m_cnt[kMetaDeg];     // pins of the slice (below the window end)
-  __shared__ int32_t c_list[kMetaDeg];    // hyperedges with batches (bit 31: may run on)
-  __shared__ int32_t c_pre[kMetaDeg + 1]; // batches before each listed hyperedge
-  __shared__ int32_t ws[2 * NW];
-  __shared__ uint64_t red[2 * NW];
-  __shared__ int32_t s_item;
-  __shared__ int32_t s_nrep;  // repeat visits appended in sweep 1
-  __shared__ int32_t s_over;  // the window overflowed the list
+  // thread t ranks and drains the bitmap words [16 t, 16 t + 16)
+  static_assert(kWords == 16 * THREADS, "a thread owns 16 consecutive bitmap words");
+  static_assert(kWinDeg <= 2 * THREADS, "a thread lists at most two hyperedges");
+  static_assert(B == 4, "the register uses name B registers");
+  // One LDS block laid out by hand: the descriptors of the listed
+  // hyperedges and the bitmap come first, so that their offsets fit the
+  // immediate field of the LDS instructions of the sweeps.
+  struct Lds {
+    // The hyperedges that have batches in the current sweep (one extra
+    // entry: c_pre there holds the number of batches).
+    int32_t c_pre[kWinDeg + 1];    // batches before the hyperedge
+    int32_t c_list[kWinDeg + 1];   // the hyperedge (bit 31: its slice may run on)
+    uint32_t c_base[kWinDeg + 1];  // first pin of its slice
+    int32_t c_r[kWinDeg + 1];      // pins left (sweep 1) / of the slice (sweep 2)
+    int32_t c_nb[kWinDeg + 1];     // chunks covered by its batches
+    uint32_t c_w[kWinDeg + 1];     // its weight
+    alignas(16) uint32_t seen[kWords];
+    // sweep 1: the ids of repeat visits, wave w appending to its part
+    // [w * kSeg, (w + 1) * kSeg); sweep 2 and after: the score of the
+    // repeated id of each rank (there are at most as many as repeat visits)
+    uint32_t lst[kList + kWave];   // (plus a slot per lane that takes no visit)
+    alignas(16) uint16_t wpre[kWords];  // repeated ids in the words before each word
+    // the incident hyperedges
+    uint32_t m_base[kWinDeg];      // first pin not yet below a window (offsets < 2^31)
+    int32_t m_rem[kWinDeg];        // pins from there to the hyperedge's end
+    int32_t m_w[kWinDeg];
+    uint32_t m_last[kWinDeg];      // largest id of the hyperedge
+    int32_t m_cnt[kWinDeg];        // pins of the slice (below the window end)
+    int32_t s_wcnt[NW];            // repeat visits of each wave (-1: its part overflowed)
+    int32_t ws[2 * NW];
+    uint64_t red[2 * NW];
+    int32_t s_item;
+  };
+  __shared__ Lds S;
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   const int wid = rfl_i32(tid / kWave);  // the same in every lane: keep it scalar
@@ -731,19 +759,27 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     count = (int32_t)maxV;
   }
   const int32_t* list = a.b.list + (int64_t)bucket * maxV;
-  for (int i = tid; i < kWords; i += THREADS) seen[i] = 0;
+  for (int i = tid; i < kWords; i += THREADS) S.seen[i] = 0;
+  // byte offset of the lane's pin in each chunk of a batch
+  uint32_t lofs[B];
+#pragma unroll
+  for (int u = 0; u < B; ++u) lofs[u] = (uint32_t)(u * kWave + lane) * 4u;
 
   while (true) {
     __syncthreads();
-    if (tid == 0) s_item = atomicAdd(&a.work[bucket], 1);
+    if (tid == 0) S.s_item = atomicAdd(&a.work[bucket], 1);
     __syncthreads();
-    const int32_t item = s_item;
+    const int32_t item = S.s_item;
     if (item >= count) break;
 
     VertexCtx v;
     v.n = list[item];
     v.beg = a.voff[v.n];
     v.deg = a.voff[v.n + 1] - v.beg;
+    if (v.deg > kWinDeg) {  // block-uniform; the bucket rule excludes it
+      if (tid == 0) atomicOr(a.err, kErrWorkCount);
+      continue;
+    }
     v.size_n = a.L.size[v.n];
     v.syn_n = a.L.syn[v.n];
     v.ax_n = a.L.ax[v.n];
@@ -752,139 +788,122 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
                   (int64_t)v.syn_n + v.G.max_syn <= v.G.phi &&
                   (int64_t)v.ax_n + v.G.max_ax <= v.G.delta;
     const uint32_t n = (uint32_t)v.n;
-    const int32_t deg = (int32_t)v.deg;  // 1 .. kMetaDeg by the bucket rule
+    const int32_t deg = (int32_t)v.deg;  // 1 .. kWinDeg
     uint64_t best = 0;
 
     int64_t mn = INT64_MAX, mx = -1;
     for (int j = tid; j < deg; j += THREADS) {
       const uint32_t e = a.vinc[v.beg + j] & kIdMask;
       const int64_t s0 = a.L.eoff[e], e0 = a.L.eoff[e + 1];
-      m_start[j] = (uint32_t)s0;
-      m_len[j] = (int32_t)(e0 - s0);
-      m_w[j] = a.L.w[e];
-      m_cur[j] = 0;
+      S.m_base[j] = (uint32_t)s0;
+      S.m_rem[j] = (int32_t)(e0 - s0);
+      S.m_w[j] = a.L.w[e];
       const uint32_t f = a.L.pins[s0] & kIdMask, l = a.L.pins[e0 - 1] & kIdMask;
-      m_last[j] = l;
+      S.m_last[j] = l;
       mn = (int64_t)f < mn ? (int64_t)f : mn;
       mx = (int64_t)l > mx ? (int64_t)l : mx;
     }
-    block_min_max_i64<THREADS>(mn, mx, (int64_t*)red);  // also orders the staging
+    block_min_max_i64<THREADS>(mn, mx, (int64_t*)S.red);  // also orders the staging
     const int64_t hi_all = mx + 1;
     int64_t lo = mn;
     int64_t width = hi_all - lo < (int64_t)kWinIds ? hi_all - lo : (int64_t)kWinIds;
     int passes = 0;
 
     // Lists the hyperedges with batches: thread t looks at hyperedges 2t and
-    // 2t + 1, whose chunk counts (and run-on flags) it passes in.  Returns
-    // the number of listed hyperedges and of batches (block-uniform).
-    auto list_batches = [&](int32_t nb0, int32_t nb1, bool ro0, bool ro1, int32_t& nc,
-                            int32_t& tb) {
-      const int32_t b0 = (nb0 + B - 1) / B, b1 = (nb1 + B - 1) / B;
+    // 2t + 1 and passes in, for each, its chunk count, run-on flag, slice
+    // start and pin count.  Returns the number of listed hyperedges and of
+    // batches (block-uniform).
+    auto list_batches = [&](const int32_t (&nbq)[2], const bool (&roq)[2],
+                            const uint32_t (&baseq)[2], const int32_t (&rq)[2],
+                            int32_t& nc, int32_t& tb) {
+      const int32_t b0 = (nbq[0] + B - 1) / B, b1 = (nbq[1] + B - 1) / B;
       int32_t pc, pb;
-      block_scan_pair<THREADS>((b0 > 0) + (b1 > 0), b0 + b1, pc, pb, nc, tb, ws);
-      const int32_t j0 = 2 * tid;
-      if (b0 > 0) {
-        c_list[pc] = j0 | (ro0 ? (int32_t)0x80000000 : 0);
-        c_pre[pc] = pb;
-        ++pc;
-        pb += b0;
+      block_scan_pair<THREADS>((b0 > 0) + (b1 > 0), b0 + b1, pc, pb, nc, tb, S.ws);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int32_t bq = q == 0 ? b0 : b1;
+        if (bq > 0) {
+          const int32_t j = 2 * tid + q;
+          S.c_list[pc] = j | (roq[q] ? (int32_t)0x80000000 : 0);
+          S.c_pre[pc] = pb;
+          S.c_base[pc] = baseq[q];
+          S.c_r[pc] = rq[q];
+          S.c_nb[pc] = nbq[q];
+          S.c_w[pc] = (uint32_t)S.m_w[j];
+          ++pc;
+          pb += bq;
+        }
       }
-      if (b1 > 0) {
-        c_list[pc] = (j0 + 1) | (ro1 ? (int32_t)0x80000000 : 0);
-        c_pre[pc] = pb;
-      }
-      if (tid == 0) c_pre[nc] = tb;
+      if (tid == 0) S.c_pre[nc] = tb;
     };
 
-    // A batch: hyperedge j (deg: no more work), chunks k .. kend - 1 of its
-    // slice, which starts at pin `base` and has r pins left (sweep 1) or
-    // exactly r pins (sweep 2).
+    // A batch: pins [base, base + lim) of hyperedge j's slice (lim = 0: no
+    // batch), weight wt (sweep 2); rem (sweep 1) > 0 when the slice may run
+    // on past the batch, with rem pins left in the hyperedge after it.
     struct Batch {
-      int32_t j, k, kend, r;
-      bool runs_on;  // sweep 1: the slice may go on past chunk kend - 1, the last
-                     // chunk listed for the hyperedge
+      uint32_t base;
+      int32_t lim, j, rem;
       uint32_t wt;
-      uint32_t base;  // pin offsets are below 2^31
     };
-    const uint32_t dummy = rfl_u32(m_start[0]);
     int32_t nc = 0, tb = 0;  // listed hyperedges, batches of the current sweep
     int32_t bnext = 0, ci = 0;
     bool has_cont = false;
-    int32_t cont_j = 0, cont_k = 0;
-    // Keeps a batch buffer's registers live until the point where they are
-    // refilled, so that the register allocator does not reuse them as
-    // temporaries in between (a temporary in a register whose load the
-    // compiler cannot prove complete costs a wait for every load in flight).
-    auto hold = [](uint32_t (&pin)[B]) {
-      asm volatile("" : "+v"(pin[0]), "+v"(pin[1]), "+v"(pin[2]), "+v"(pin[3]));
-    };
+    int32_t cont_j = 0, cont_rem = 0;  // a continuation: hyperedge, pins left
+    uint32_t cont_base = 0;            // and its first pin
     // The wave's next batch; its loads are issued at once (for no batch, at
-    // an address inside the pins, so that every path issues B loads).
+    // pin 0, so that every path issues B loads).
     auto fetch = [&](Batch& t, uint32_t (&pin)[B], bool sweep1) {
-      const int32_t ov =
-          rfl_i32(__hip_atomic_load(&s_over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-      t.j = deg;
-      t.k = 0;
-      t.runs_on = false;
-      bool cont = false;
+      uint32_t base = 0, wt = 0;
+      int32_t lim = 0, j = deg, rem = 0;
       if (sweep1 && has_cont) {  // wave-uniform
-        t.j = cont_j;
-        t.k = cont_k;
         has_cont = false;
-        cont = true;
+        j = cont_j;
+        base = cont_base;
+        lim = cont_rem < kBatchPins ? cont_rem : kBatchPins;
+        rem = cont_rem - lim;
       } else if (bnext < tb) {  // wave-uniform
-        // the last listed hyperedge (from ci on) whose first batch is at most
+        // The last listed hyperedge (from ci on) whose first batch is at most
         // bnext: the entries are strictly increasing, so the lanes that pass
-        // form a prefix, and it lies within 16 entries of ci
+        // form a prefix, and it lies within NW entries of ci.  Every lane
+        // reads its entry, and the chosen one is taken with readlane.
         const int32_t idx = ci + lane < nc ? ci + lane : nc;
-        const uint64_t m = __ballot(c_pre[idx] <= bnext);
-        const int32_t i = ci + (int32_t)__popcll(m) - 1;
-        ci = i;
-        const int32_t e = rfl_i32(c_list[i]);
-        t.j = e & 0x7FFFFFFF;
-        t.runs_on = e < 0;
-        t.k = (bnext - rfl_i32(c_pre[i])) * B;
+        const int32_t pre_l = S.c_pre[idx], e_l = S.c_list[idx], r_l = S.c_r[idx],
+                      nb_l = S.c_nb[idx];
+        const uint32_t base_l = S.c_base[idx];
+        const uint32_t w_l = sweep1 ? 0u : S.c_w[idx];
+        const uint64_t m = __ballot(pre_l <= bnext);
+        const int32_t sel = (int32_t)__popcll(m) - 1;
+        ci += sel;
+        const int32_t e = __builtin_amdgcn_readlane(e_l, sel);
+        const int32_t r = __builtin_amdgcn_readlane(r_l, sel);
+        const int32_t nb = __builtin_amdgcn_readlane(nb_l, sel);
+        const int32_t k = (bnext - __builtin_amdgcn_readlane(pre_l, sel)) * B;
+        const int32_t kend = k + B < nb ? k + B : nb;
+        j = e & 0x7FFFFFFF;
+        base = (uint32_t)__builtin_amdgcn_readlane((int32_t)base_l, sel) + (uint32_t)(k * kWave);
+        lim = r - k * kWave < (kend - k) * kWave ? r - k * kWave : (kend - k) * kWave;
+        // only the batch holding the hyperedge's last listed chunk may find
+        // that the slice runs on (its chunks are then full)
+        if (sweep1 && e < 0 && kend == nb) rem = r - kend * kWave;
+        if (!sweep1) wt = (uint32_t)__builtin_amdgcn_readlane((int32_t)w_l, sel);
         bnext += NW;
       }
-      if (ov != 0 && sweep1) t.j = deg;
-      if (t.j < deg) {  // wave-uniform
-        const int32_t c0 = rfl_i32(m_cur[t.j]);
-        t.base = rfl_u32(m_start[t.j]) + (uint32_t)c0;
-        t.wt = rfl_u32(m_w[t.j]);
-        if (sweep1) {
-          t.r = rfl_i32(m_len[t.j]) - c0;
-          const int32_t full = (t.r + kWave - 1) / kWave;
-          const int32_t nb = cont ? full : rfl_i32(m_nb[t.j]);
-          t.kend = t.k + B < nb ? t.k + B : nb;
-          // only the batch holding the hyperedge's last listed chunk (or a
-          // continuation) may find that the slice runs on
-          t.runs_on = (t.runs_on && t.kend == nb) || cont;
-        } else {
-          t.r = rfl_i32(m_cnt[t.j]);
-          const int32_t nb = (t.r + kWave - 1) / kWave;
-          t.kend = t.k + B < nb ? t.k + B : nb;
-        }
-      } else {
-        t.r = 1;
-        t.base = dummy;
-        t.k = 0;
-        t.kend = 0;
-        t.wt = 0;
-        t.runs_on = false;
-      }
-      // the fields are wave-uniform; say so, so that the tests on them in the
-      // chunk loops stay scalar
-      t.j = rfl_i32(t.j);
-      t.k = rfl_i32(t.k);
-      t.kend = rfl_i32(t.kend);
-      t.r = rfl_i32(t.r);
-      t.wt = rfl_u32(t.wt);
-      t.runs_on = rfl_i32(t.runs_on ? 1 : 0) != 0;
-      t.base = rfl_u32(t.base);
+      // the fields are wave-uniform; say so, so that the tests on them stay
+      // scalar
+      t.base = rfl_u32(base);
+      t.lim = rfl_i32(lim);
+      t.j = rfl_i32(j);
+      t.rem = rfl_i32(rem);
+      t.wt = rfl_u32(wt);
+      // lanes past the batch load its last live pin (a scalar bound: the
+      // readfirstlane keeps the compiler from turning it into a per-lane
+      // select after the clamp)
+      const uint32_t last4 = rfl_u32(t.lim > 0 ? (uint32_t)(t.lim - 1) * 4u : 0u);
+      const char* p = reinterpret_cast<const char*>(a.L.pins + t.base);
 #pragma unroll
       for (int u = 0; u < B; ++u) {
-        const int32_t p = (t.k + u) * kWave + lane;
-        pin[u] = a.L.pins[t.base + (uint32_t)(p < t.r ? p : t.r - 1)];
+        const uint32_t off = lofs[u] < last4 ? lofs[u] : last4;
+        pin[u] = *reinterpret_cast<const uint32_t*>(p + off);
       }
     };
 
@@ -900,17 +919,18 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       // the window (or has at most two left), else a generous estimate of the
       // slice, flagged as possibly running on
       {
-        int32_t nbq[2] = {0, 0};
+        int32_t nbq[2] = {0, 0}, rq[2] = {0, 0};
         bool roq[2] = {false, false};
+        uint32_t baseq[2] = {0, 0};
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int32_t j = 2 * tid + q;
           if (j < deg) {
-            const int32_t r = m_len[j] - m_cur[j];
+            const int32_t r = S.m_rem[j];
             const int32_t full = (r + kWave - 1) / kWave;
             int32_t nb = full;
-            if (m_last[j] >= hi32 && full > 2) {
-              const uint32_t l = m_last[j];
+            if (S.m_last[j] >= hi32 && full > 2) {
+              const uint32_t l = S.m_last[j];
               const float est = (float)r * (float)(hi - lo) / (float)((int64_t)l - lo + 1);
               const float body = est + 2.0f * sqrtf(est) + (float)kWave;
               nb = (int32_t)(body / (float)kWave) + 1;
@@ -918,21 +938,12 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
             }
             nbq[q] = nb;
             roq[q] = nb < full;
+            rq[q] = r;
+            baseq[q] = S.m_base[j];
+            S.m_cnt[j] = 0;
           }
         }
-        list_batches(nbq[0], nbq[1], roq[0], roq[1], nc, tb);
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int32_t j = 2 * tid + q;
-          if (j < deg) {
-            m_nb[j] = nbq[q];
-            m_cnt[j] = 0;
-          }
-        }
-      }
-      if (tid == 0) {
-        s_nrep = 0;
-        s_over = 0;
+        list_batches(nbq, roq, baseq, rq, nc, tb);
       }
       __syncthreads();
       bnext = wid;
@@ -941,25 +952,29 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
 
       // ---- sweep 1 ----
       bool over = false;
+      int32_t wcnt = 0;  // repeat visits in the wave's part of the list
       // A batch of sweep 1: the B chunks' bitmap updates are issued back to
-      // back (one wait for all of them); chunks past kend, lanes past the
-      // slice and pins at or above the window end or equal to n update a
-      // word of their own with 0.  The repeat visits of the batch are
-      // appended to the list with one single-lane atomic.
+      // back (one wait for all of them); lanes past the batch and pins at or
+      // above the window end or equal to n update a word of their own with 0.
       auto process1 = [&](const Batch& t, const uint32_t (&pin)[B]) {
+        const uint32_t lim4 = (uint32_t)t.lim * 4u;
         uint32_t id[B], bit[B], old[B];
-        bool in[B];
+        int32_t cnt = 0;
 #pragma unroll
         for (int u = 0; u < B; ++u) {
           id[u] = pin[u] & kIdMask;
-          const bool live = (t.k + u < t.kend) & ((t.k + u) * kWave + lane < t.r);
-          in[u] = live & (id[u] < hi32);  // ids >= lo: cursor order
-          const bool act = in[u] & (id[u] != n);
+          const bool in = (lofs[u] < lim4) & (id[u] < hi32);  // ids >= lo: cursor order
+          cnt += (int32_t)__popcll(__ballot(in));
+          const bool act = in & (id[u] != n);
           const uint32_t rel = id[u] - lo32;
           const uint32_t word = act ? rel >> 5 : (uint32_t)lane;
           bit[u] = act ? 1u << (rel & 31) : 0u;
-          old[u] = atomicOr(&seen[word], bit[u]);
+          old[u] = atomicOr(&S.seen[word], bit[u]);
         }
+        // count here, in a scalar register: left to itself the compiler sinks
+        // the count below the list appends and keeps the B lane masks alive
+        // across them as 0/1 vectors
+        asm volatile("" : "+s"(cnt));
         bool rep[B];
         uint64_t rb[B];
         int32_t nr = 0;
@@ -969,160 +984,188 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
           rb[u] = __ballot(rep[u]);
           nr += (int32_t)__popcll(rb[u]);
         }
-        if (nr > 0 && !over) {  // wave-uniform
-          int32_t base = 0;
-          if (lane == 0) base = atomicAdd(&s_nrep, nr);
-          base = __builtin_amdgcn_readlane(base, 0);
-          if (base + nr > kList) {
+        if (nr > 0 && !over) {  // wave-uniform (most batches hold a few)
+          if (wcnt + nr > kSeg) {
             over = true;
-            s_over = 1;  // every lane stores the same value
           } else {
+            // every lane writes: a repeat visit to its place in the wave's
+            // part of the list, any other lane to a slot of its own
+            uint32_t at = (uint32_t)(wid * kSeg + wcnt);
+            wcnt += nr;
 #pragma unroll
             for (int u = 0; u < B; ++u) {
               const uint32_t below = __builtin_amdgcn_mbcnt_hi(
                   (uint32_t)(rb[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)rb[u], 0u));
-              if (rep[u]) lst[base + (int32_t)below] = id[u];
-              base += (int32_t)__popcll(rb[u]);
+              S.lst[rep[u] ? at + below : (uint32_t)(kList + lane)] = id[u];
+              at += (uint32_t)__popcll(rb[u]);
             }
           }
         }
-        int32_t cnt = 0;
-        uint32_t lastpin = kSent;
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-          cnt += __popcll(__ballot(in[u]));
-          if (t.k + u == t.kend - 1) lastpin = __builtin_amdgcn_readlane(pin[u], kWave - 1);
-        }
+        if (cnt > 0 && lane == 0) atomicAdd(&S.m_cnt[t.j], cnt);
         // the slice runs on past this batch iff the batch ends the
-        // hyperedge's listed chunks (or is a continuation), its last chunk is
-        // full (kend * 64 < r) and that chunk's last pin lies below the
-        // window end
-        if (t.runs_on && t.kend * kWave < t.r && (lastpin & kIdMask) < hi32 &&
-            !over) {  // wave-uniform
-          has_cont = true;
-          cont_j = t.j;
-          cont_k = t.kend;
+        // hyperedge's listed chunks (or is a continuation), pins are left
+        // after it, and its last pin (lane 63 of its last chunk, which is
+        // full) lies below the window end
+        if (t.rem > 0 && !over) {  // wave-uniform
+          const int32_t c = (t.lim >> 6) - 1;
+          const uint32_t lp = c == 0 ? pin[0] : c == 1 ? pin[1] : c == 2 ? pin[2] : pin[3];
+          const uint32_t last = (uint32_t)__builtin_amdgcn_readlane((int32_t)lp, kWave - 1);
+          if ((last & kIdMask) < hi32) {
+            has_cont = true;
+            cont_j = t.j;
+            cont_base = t.base + (uint32_t)t.lim;
+            cont_rem = t.rem;
+          }
         }
-        if (lane == 0 && cnt) atomicAdd(&m_cnt[t.j], cnt);  // cnt = 0 when there is no batch
-        // every batch's loads are complete here, on every path (no batch
-        // never reads its registers otherwise), which keeps the compiler's
-        // count of loads in flight exact across the loop
+        // every batch's loads are complete here, on every path, which keeps
+        // the compiler's count of loads in flight exact across the loop
         asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
       };
-      static_assert(B == 4, "the register uses name B registers");
+      // One exit, at the top: an exit between the two halves would give the
+      // loop a second path into its head, along which the other buffer's
+      // loads are still in flight, and the compiler would then wait for them
+      // at the head.
       {
         Batch ta, tb2;
         uint32_t pa[B], pb[B];
         fetch(ta, pa, true);
-        while (true) {
-          if ((ta.j >= deg && !has_cont) || over) break;
-          hold(pb);
+        while ((ta.lim > 0 || has_cont) && !over) {
           fetch(tb2, pb, true);
           process1(ta, pa);
-          if ((tb2.j >= deg && !has_cont) || over) break;
-          hold(pa);
           fetch(ta, pa, true);
           process1(tb2, pb);
         }
       }
+      S.s_wcnt[wid] = over ? -1 : wcnt;  // every lane stores the same value
       __syncthreads();
-      const bool any_over = s_over != 0 || s_nrep > kList;
-      const int32_t nrep = s_nrep < kList ? s_nrep : kList;
-      for (int i = tid; i < kWords; i += THREADS) seen[i] = 0;
+      bool any_over = false;
+      int32_t nrep = 0;  // repeat visits of the window
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const int32_t c = S.s_wcnt[w];
+        any_over |= c < 0;
+        nrep += c > 0 ? c : 0;
+      }
+      for (int i = tid; i < kWords; i += THREADS) S.seen[i] = 0;
       if (any_over) {
         width = width / 2 > 0 ? width / 2 : 1;
         continue;  // the loop head synchronises before the next window
       }
       // ---- sweep 2 batches: the exact slices ----
       {
-        int32_t nbq[2] = {0, 0};
+        int32_t nbq[2] = {0, 0}, rq[2] = {0, 0};
+        const bool roq[2] = {false, false};
+        uint32_t baseq[2] = {0, 0};
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int32_t j = 2 * tid + q;
-          if (j < deg) nbq[q] = (m_cnt[j] + kWave - 1) / kWave;
+          if (j < deg) {
+            rq[q] = S.m_cnt[j];
+            nbq[q] = (rq[q] + kWave - 1) / kWave;
+            baseq[q] = S.m_base[j];
+          }
         }
-        list_batches(nbq[0], nbq[1], false, false, nc, tb);  // synchronises
+        list_batches(nbq, roq, baseq, rq, nc, tb);  // synchronises
       }
       bnext = wid;
       ci = 0;
       // the bitmap of repeated ids (it was cleared before the list was
-      // built) and the rank prefix of every word; the scores start at 0
-      for (int i = tid; i < nrep; i += THREADS) {
-        const uint32_t rel = lst[i] - lo32;
-        atomicOr(&seen[rel >> 5], 1u << (rel & 31));
+      // built; each wave sets the ids of its own part) and the rank prefix
+      // of every word; the scores start at 0
+      for (int o = lane; o < wcnt; o += kWave) {
+        const uint32_t rel = S.lst[wid * kSeg + o] - lo32;
+        atomicOr(&S.seen[rel >> 5], 1u << (rel & 31));
       }
-      // Wave w ranks the words [w * kWordsPerWave, (w + 1) * kWordsPerWave)
-      // in rows of 64 consecutive words, one per lane (no bank conflicts);
-      // the waves' totals are scanned across the block.
+      // Thread t ranks its 16 words: their repeated ids are counted, the
+      // counts scanned across the block, and the running rank stored per
+      // word, two to a 32-bit store.
+      uint4* const seen4 = reinterpret_cast<uint4*>(S.seen);
+      uint4* const wpre4 = reinterpret_cast<uint4*>(S.wpre);
       int32_t nrank = 0;  // repeated ids of the window
       if (nrep > 0) {     // block-uniform
         __syncthreads();
-        int32_t wave_total = 0;
-#pragma unroll 4
-        for (int r = 0; r < kRows; ++r) wave_total += __popc(seen[wid * kWordsPerWave + r * kWave + lane]);
+        uint4 q[4];
+        int32_t c = 0;
 #pragma unroll
-        for (int d = kWave / 2; d > 0; d >>= 1) wave_total += __shfl_xor(wave_total, d, kWave);
-        int32_t before, unused0, unused1;
-        // one pair per thread: lane 0 of each wave carries the wave's total
-        block_scan_pair<THREADS>(lane == 0 ? wave_total : 0, 0, before, unused0, nrank, unused1,
-                                 ws);
-        int32_t run = __builtin_amdgcn_readlane(before, 0);
-#pragma unroll 4
-        for (int r = 0; r < kRows; ++r) {
-          const int wi = wid * kWordsPerWave + r * kWave + lane;
-          const int32_t c = __popc(seen[wi]);
-          int32_t inc = c;
-#pragma unroll
-          for (int d = 1; d < kWave; d <<= 1) {
-            const int32_t o = __shfl_up(inc, d, kWave);
-            inc += lane >= d ? o : 0;
-          }
-          wpre[wi] = (uint16_t)(run + inc - c);
-          run += __builtin_amdgcn_readlane(inc, kWave - 1);
+        for (int i = 0; i < 4; ++i) {
+          q[i] = seen4[4 * tid + i];
+          c += __popc(q[i].x) + __popc(q[i].y) + __popc(q[i].z) + __popc(q[i].w);
         }
-        for (int i = tid; i < nrank; i += THREADS) lst[i] = 0;
+        int32_t before, unused0, unused1;
+        block_scan_pair<THREADS>(c, 0, before, unused0, nrank, unused1, S.ws);
+        uint32_t run = (uint32_t)before, pk[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t r0 = run;
+          run += __popc(q[i].x);
+          const uint32_t r1 = run;
+          run += __popc(q[i].y);
+          const uint32_t r2 = run;
+          run += __popc(q[i].z);
+          const uint32_t r3 = run;
+          run += __popc(q[i].w);
+          pk[2 * i] = r0 | (r1 << 16);
+          pk[2 * i + 1] = r2 | (r3 << 16);
+        }
+        wpre4[2 * tid] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+        wpre4[2 * tid + 1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+        for (int i = tid; i < nrank; i += THREADS) S.lst[i] = 0;
       }
       __syncthreads();  // list of batches, bitmap, ranks and scores ready
 
       // ---- sweep 2 ----
       auto process2 = [&](const Batch& t, const uint32_t (&pin)[B]) {
-        if (t.j >= deg) {  // wave-uniform: no batch (its pins may lie outside
+        if (t.lim == 0) {  // wave-uniform: no batch (its pins may lie outside
                            // the window; they are not looked at)
           asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
           return;
         }
-        // the B chunks' bitmap reads are issued back to back
+        // the B chunks' bitmap reads are issued back to back; lanes past the
+        // batch hold its last live pin (inside the window)
+        const uint32_t lim4 = (uint32_t)t.lim * 4u;
         uint32_t id[B], w[B];
-        bool act[B];
+        bool act[B], rep[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-          // lanes past the slice hold its last pin (inside the window)
           id[u] = pin[u] & kIdMask;
-          act[u] = (t.k + u < t.kend) & ((t.k + u) * kWave + lane < t.r) & (id[u] != n);
-          w[u] = seen[(id[u] - lo32) >> 5];
+          act[u] = (lofs[u] < lim4) & (id[u] != n);
+          w[u] = S.seen[(id[u] - lo32) >> 5];
         }
         bool anyadd = false;
-        bool add[B];
+        if (v.all_valid) {  // block-uniform
+          // every single scores the batch's weight: the best of them is the
+          // smallest id
+          uint32_t mid = kSent;
 #pragma unroll
-        for (int u = 0; u < B; ++u) {
-          const bool isrep = ((w[u] >> ((id[u] - lo32) & 31)) & 1u) != 0;
-          const uint64_t key = ((uint64_t)t.wt << 32) | (uint64_t)(kSent - id[u]);
-          bool better = act[u] & !isrep & (key > best);
-          if (!v.all_valid && __ballot(better) != 0) {  // wave-uniform
-            if (better) better = merge_valid(a, v, id[u], 0);
+          for (int u = 0; u < B; ++u) {
+            rep[u] = ((w[u] >> ((id[u] - lo32) & 31)) & 1u) != 0;
+            const bool single = act[u] & !rep[u];
+            mid = single && id[u] < mid ? id[u] : mid;
+            anyadd |= act[u] & rep[u];
           }
-          best = better ? key : best;
-          add[u] = act[u] & isrep;
-          anyadd |= add[u];
+          const uint64_t key = ((uint64_t)t.wt << 32) | (uint64_t)(kSent - mid);
+          best = mid != kSent && key > best ? key : best;
+        } else {
+#pragma unroll
+          for (int u = 0; u < B; ++u) {
+            rep[u] = ((w[u] >> ((id[u] - lo32) & 31)) & 1u) != 0;
+            const uint64_t key = ((uint64_t)t.wt << 32) | (uint64_t)(kSent - id[u]);
+            bool better = act[u] & !rep[u] & (key > best);
+            if (__ballot(better) != 0) {  // wave-uniform
+              if (better) better = merge_valid(a, v, id[u], 0);
+            }
+            best = better ? key : best;
+            anyadd |= act[u] & rep[u];
+          }
         }
         if (__ballot(anyadd) != 0) {  // wave-uniform
 #pragma unroll
           for (int u = 0; u < B; ++u) {
-            if (add[u]) {
+            if (act[u] & rep[u]) {
               const uint32_t rel = id[u] - lo32;
-              const uint32_t rank =
-                  (uint32_t)wpre[rel >> 5] + (uint32_t)__popc(w[u] & ((1u << (rel & 31)) - 1u));
-              atomicAdd(&lst[rank], t.wt);
+              const uint32_t rank = (uint32_t)S.wpre[rel >> 5] +
+                                    (uint32_t)__popc(w[u] & ((1u << (rel & 31)) - 1u));
+              atomicAdd(&S.lst[rank], t.wt);
             }
           }
         }
@@ -1133,43 +1176,47 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         Batch ta, tb2;
         uint32_t pa[B], pb[B];
         fetch(ta, pa, false);
-        while (true) {
-          if (ta.j >= deg) break;
-          hold(pb);
+        while (ta.lim > 0) {
           fetch(tb2, pb, false);
           process2(ta, pa);
-          if (tb2.j >= deg) break;
-          hold(pa);
           fetch(ta, pa, false);
           process2(tb2, pb);
         }
       }
       __syncthreads();  // sweep 2 done: scores complete
-      if (nrank > 0) {    // block-uniform; words in the ranking's order
-        for (int r = 0; r < kRows; ++r) {
-          const int wi = wid * kWordsPerWave + r * kWave + lane;
-          uint32_t bits = seen[wi];
-          if (bits) {
-            uint32_t rk = wpre[wi];
+      if (nrank > 0) {  // block-uniform; the thread's words in the ranking's order
+        uint32_t rk = S.wpre[16 * tid];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint4 q = seen4[4 * tid + i];
+          const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            uint32_t bits = wv[x];
+            const uint32_t id0 = lo32 + (uint32_t)(16 * tid + 4 * i + x) * 32u;
             while (bits) {
               const uint32_t b = (uint32_t)__ffs(bits) - 1;
               bits &= bits - 1;
-              const uint32_t id = lo32 + (uint32_t)wi * 32u + b;
-              const uint64_t key = ((uint64_t)lst[rk++] << 32) | (uint64_t)(kSent - id);
+              const uint32_t id = id0 + b;
+              const uint64_t key = ((uint64_t)S.lst[rk++] << 32) | (uint64_t)(kSent - id);
               if (key > best && (v.all_valid || merge_valid(a, v, id, 0))) best = key;
             }
-            seen[wi] = 0;
           }
+          if ((q.x | q.y | q.z | q.w) != 0) seen4[4 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
         }
       }
-      for (int jj = tid; jj < deg; jj += THREADS) m_cur[jj] += m_cnt[jj];
+      for (int jj = tid; jj < deg; jj += THREADS) {
+        const int32_t c = S.m_cnt[jj];
+        S.m_base[jj] += (uint32_t)c;
+        S.m_rem[jj] -= c;
+      }
       lo = hi;
       if (nrep < kList / 4 && width < (int64_t)kWinIds) {
         width *= 2;
         if (width > (int64_t)kWinIds) width = kWinIds;
       }
     }
-    best = block_max_u64<THREADS>(best, red);
+    best = block_max_u64<THREADS>(best, S.red);
     if (tid == 0) {
       if (best == 0) {
         a.cand[v.n] = -1;

@@ -154,7 +154,7 @@ __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
         const int64_t dist = x < (int64_t)G.nverts - 1 ? x : (int64_t)G.nverts - 1;
         if (dist <= (int64_t)kSmallSlots * load16 / 16) bk = 0;
         else if (dist <= (int64_t)(ov ? kBigSlotsOv : kBigSlots) * load16 / 16) bk = 1;
-        else bk = (voff[v + 1] - voff[v] <= kMetaDeg) ? 2 : 3;
+        else bk = (voff[v + 1] - voff[v] <= kWinDeg) ? 2 : 3;
         if (ov) bk += 4;
       }
     }
