@@ -713,12 +713,15 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
   constexpr int kBatchPins = B * kWave;
   constexpr uint32_t kWinIds = 1u << 19;
   constexpr int kWords = (int)(kWinIds / 32);
-  constexpr int kList = 4096;        // repeat visits of a window (sweep 1)
-  constexpr int kSeg = kList / NW;   // a wave's part of the list
+  constexpr int kList = 4096;         // repeat visits of a window
+  constexpr int kSeg = kList / NW;    // a wave's part of them
+  constexpr int kScores = 2048;       // repeated ids of a window
+  constexpr int kNbMax = (1 << 21) - 1;  // chunk count a list entry holds
   constexpr uint32_t kSent = 0x7FFFFFFFu;
   // thread t ranks and drains the bitmap words [16 t, 16 t + 16)
   static_assert(kWords == 16 * THREADS, "a thread owns 16 consecutive bitmap words");
   static_assert(kWinDeg <= 2 * THREADS, "a thread lists at most two hyperedges");
+  static_assert(kWinDeg <= 1024, "a list entry holds the hyperedge in 10 bits");
   static_assert(B == 4, "the register uses name B registers");
   // One LDS block laid out by hand: the descriptors of the listed
   // hyperedges and the bitmap come first, so that their offsets fit the
@@ -727,16 +730,17 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     // The hyperedges that have batches in the current sweep (one extra
     // entry: c_pre there holds the number of batches).
     int32_t c_pre[kWinDeg + 1];    // batches before the hyperedge
-    int32_t c_list[kWinDeg + 1];   // the hyperedge (bit 31: its slice may run on)
+    // the hyperedge j (bits 0-9), in sweep 1 the chunks its batches cover
+    // (bits 10-30; they end at most at kNbMax) and whether its slice may run
+    // on past them (bit 31)
+    int32_t c_list[kWinDeg + 1];
     uint32_t c_base[kWinDeg + 1];  // first pin of its slice
     int32_t c_r[kWinDeg + 1];      // pins left (sweep 1) / of the slice (sweep 2)
-    int32_t c_nb[kWinDeg + 1];     // chunks covered by its batches
-    uint32_t c_w[kWinDeg + 1];     // its weight
     alignas(16) uint32_t seen[kWords];
-    // sweep 1: the ids of repeat visits, wave w appending to its part
-    // [w * kSeg, (w + 1) * kSeg); sweep 2 and after: the score of the
-    // repeated id of each rank (there are at most as many as repeat visits)
-    uint32_t lst[kList + kWave];   // (plus a slot per lane that takes no visit)
+    // the ids of sweep 1's repeat visits, wave w's from w * kSeg on (plus a
+    // slot per lane that takes no visit); they stay for the final fold
+    uint32_t lst[kList + kWave];
+    uint32_t sc[kScores];          // sweep 2 on: the score of each rank
     alignas(16) uint16_t wpre[kWords];  // repeated ids in the words before each word
     // the incident hyperedges
     uint32_t m_base[kWinDeg];      // first pin not yet below a window (offsets < 2^31)
@@ -759,7 +763,8 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     count = (int32_t)maxV;
   }
   const int32_t* list = a.b.list + (int64_t)bucket * maxV;
-  for (int i = tid; i < kWords; i += THREADS) S.seen[i] = 0;
+  uint4* const seen4 = reinterpret_cast<uint4*>(S.seen);
+  uint4* const wpre4 = reinterpret_cast<uint4*>(S.wpre);
   // byte offset of the lane's pin in each chunk of a batch
   uint32_t lofs[B];
 #pragma unroll
@@ -811,8 +816,9 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
 
     // Lists the hyperedges with batches: thread t looks at hyperedges 2t and
     // 2t + 1 and passes in, for each, its chunk count, run-on flag, slice
-    // start and pin count.  Returns the number of listed hyperedges and of
-    // batches (block-uniform).
+    // start and pin count (sweep 2 takes the chunk count from the pin
+    // count).  Returns the number of listed hyperedges and of batches
+    // (block-uniform).
     auto list_batches = [&](const int32_t (&nbq)[2], const bool (&roq)[2],
                             const uint32_t (&baseq)[2], const int32_t (&rq)[2],
                             int32_t& nc, int32_t& tb) {
@@ -824,12 +830,13 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         const int32_t bq = q == 0 ? b0 : b1;
         if (bq > 0) {
           const int32_t j = 2 * tid + q;
-          S.c_list[pc] = j | (roq[q] ? (int32_t)0x80000000 : 0);
+          // chunks past kNbMax are reached as a continuation
+          const bool ro = roq[q] || nbq[q] > kNbMax;
+          const int32_t nb = nbq[q] < kNbMax ? nbq[q] : kNbMax;
+          S.c_list[pc] = j | (nb << 10) | (ro ? (int32_t)0x80000000 : 0);
           S.c_pre[pc] = pb;
           S.c_base[pc] = baseq[q];
           S.c_r[pc] = rq[q];
-          S.c_nb[pc] = nbq[q];
-          S.c_w[pc] = (uint32_t)S.m_w[j];
           ++pc;
           pb += bq;
         }
@@ -867,25 +874,23 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         // form a prefix, and it lies within NW entries of ci.  Every lane
         // reads its entry, and the chosen one is taken with readlane.
         const int32_t idx = ci + lane < nc ? ci + lane : nc;
-        const int32_t pre_l = S.c_pre[idx], e_l = S.c_list[idx], r_l = S.c_r[idx],
-                      nb_l = S.c_nb[idx];
+        const int32_t pre_l = S.c_pre[idx], e_l = S.c_list[idx], r_l = S.c_r[idx];
         const uint32_t base_l = S.c_base[idx];
-        const uint32_t w_l = sweep1 ? 0u : S.c_w[idx];
         const uint64_t m = __ballot(pre_l <= bnext);
         const int32_t sel = (int32_t)__popcll(m) - 1;
         ci += sel;
         const int32_t e = __builtin_amdgcn_readlane(e_l, sel);
         const int32_t r = __builtin_amdgcn_readlane(r_l, sel);
-        const int32_t nb = __builtin_amdgcn_readlane(nb_l, sel);
+        const int32_t nb = sweep1 ? (e >> 10) & kNbMax : (r + kWave - 1) / kWave;
         const int32_t k = (bnext - __builtin_amdgcn_readlane(pre_l, sel)) * B;
         const int32_t kend = k + B < nb ? k + B : nb;
-        j = e & 0x7FFFFFFF;
+        j = e & 0x3FF;
         base = (uint32_t)__builtin_amdgcn_readlane((int32_t)base_l, sel) + (uint32_t)(k * kWave);
         lim = r - k * kWave < (kend - k) * kWave ? r - k * kWave : (kend - k) * kWave;
         // only the batch holding the hyperedge's last listed chunk may find
         // that the slice runs on (its chunks are then full)
         if (sweep1 && e < 0 && kend == nb) rem = r - kend * kWave;
-        if (!sweep1) wt = (uint32_t)__builtin_amdgcn_readlane((int32_t)w_l, sel);
+        if (!sweep1) wt = (uint32_t)S.m_w[j];
         bnext += NW;
       }
       // the fields are wave-uniform; say so, so that the tests on them stay
@@ -945,6 +950,9 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         }
         list_batches(nbq, roq, baseq, rq, nc, tb);
       }
+      // the bitmap starts empty (the last window's fold left its repeated ids)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) seen4[4 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
       __syncthreads();
       bnext = wid;
       ci = 0;
@@ -955,7 +963,9 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       int32_t wcnt = 0;  // repeat visits in the wave's part of the list
       // A batch of sweep 1: the B chunks' bitmap updates are issued back to
       // back (one wait for all of them); lanes past the batch and pins at or
-      // above the window end or equal to n update a word of their own with 0.
+      // above the window end update a word of their own with 0.  n itself is
+      // visited like any id (once per incident hyperedge): it ends up
+      // repeated, and is left out when the scores are folded.
       auto process1 = [&](const Batch& t, const uint32_t (&pin)[B]) {
         const uint32_t lim4 = (uint32_t)t.lim * 4u;
         uint32_t id[B], bit[B], old[B];
@@ -965,10 +975,9 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
           id[u] = pin[u] & kIdMask;
           const bool in = (lofs[u] < lim4) & (id[u] < hi32);  // ids >= lo: cursor order
           cnt += (int32_t)__popcll(__ballot(in));
-          const bool act = in & (id[u] != n);
           const uint32_t rel = id[u] - lo32;
-          const uint32_t word = act ? rel >> 5 : (uint32_t)lane;
-          bit[u] = act ? 1u << (rel & 31) : 0u;
+          const uint32_t word = in ? rel >> 5 : (uint32_t)lane;
+          bit[u] = in ? 1u << (rel & 31) : 0u;
           old[u] = atomicOr(&S.seen[word], bit[u]);
         }
         // count here, in a scalar register: left to itself the compiler sinks
@@ -1046,7 +1055,10 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         any_over |= c < 0;
         nrep += c > 0 ? c : 0;
       }
-      for (int i = tid; i < kWords; i += THREADS) S.seen[i] = 0;
+      // more repeated ids than scores (at most nrep, and n)
+      any_over |= nrep >= kScores;  // more repeated ids than scores (at most nrep)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) seen4[4 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
       if (any_over) {
         width = width / 2 > 0 ? width / 2 : 1;
         continue;  // the loop head synchronises before the next window
@@ -1070,19 +1082,20 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       bnext = wid;
       ci = 0;
       // the bitmap of repeated ids (it was cleared before the list was
-      // built; each wave sets the ids of its own part) and the rank prefix
-      // of every word; the scores start at 0
+      // built; each wave sets the ids of its own part, and n counts as
+      // repeated, so that sweep 2 never takes it for a single) and the rank
+      // prefix of every word; the scores start at 0
       for (int o = lane; o < wcnt; o += kWave) {
         const uint32_t rel = S.lst[wid * kSeg + o] - lo32;
         atomicOr(&S.seen[rel >> 5], 1u << (rel & 31));
       }
+      const bool n_in = n >= lo32 && n < hi32;  // block-uniform
+      if (tid == 0 && n_in) atomicOr(&S.seen[(n - lo32) >> 5], 1u << ((n - lo32) & 31));
       // Thread t ranks its 16 words: their repeated ids are counted, the
       // counts scanned across the block, and the running rank stored per
       // word, two to a 32-bit store.
-      uint4* const seen4 = reinterpret_cast<uint4*>(S.seen);
-      uint4* const wpre4 = reinterpret_cast<uint4*>(S.wpre);
       int32_t nrank = 0;  // repeated ids of the window
-      if (nrep > 0) {     // block-uniform
+      if (nrep > 0 || n_in) {  // block-uniform
         __syncthreads();
         uint4 q[4];
         int32_t c = 0;
@@ -1109,7 +1122,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         }
         wpre4[2 * tid] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
         wpre4[2 * tid + 1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
-        for (int i = tid; i < nrank; i += THREADS) S.lst[i] = 0;
+        for (int i = tid; i < nrank; i += THREADS) S.sc[i] = 0;
       }
       __syncthreads();  // list of batches, bitmap, ranks and scores ready
 
@@ -1128,7 +1141,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
 #pragma unroll
         for (int u = 0; u < B; ++u) {
           id[u] = pin[u] & kIdMask;
-          act[u] = (lofs[u] < lim4) & (id[u] != n);
+          act[u] = lofs[u] < lim4;  // n is marked repeated: never a single
           w[u] = S.seen[(id[u] - lo32) >> 5];
         }
         bool anyadd = false;
@@ -1165,7 +1178,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
               const uint32_t rel = id[u] - lo32;
               const uint32_t rank = (uint32_t)S.wpre[rel >> 5] +
                                     (uint32_t)__popc(w[u] & ((1u << (rel & 31)) - 1u));
-              atomicAdd(&S.lst[rank], t.wt);
+              atomicAdd(&S.sc[rank], t.wt);
             }
           }
         }
@@ -1184,26 +1197,18 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         }
       }
       __syncthreads();  // sweep 2 done: scores complete
-      if (nrank > 0) {  // block-uniform; the thread's words in the ranking's order
-        uint32_t rk = S.wpre[16 * tid];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint4 q = seen4[4 * tid + i];
-          const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-          for (int x = 0; x < 4; ++x) {
-            uint32_t bits = wv[x];
-            const uint32_t id0 = lo32 + (uint32_t)(16 * tid + 4 * i + x) * 32u;
-            while (bits) {
-              const uint32_t b = (uint32_t)__ffs(bits) - 1;
-              bits &= bits - 1;
-              const uint32_t id = id0 + b;
-              const uint64_t key = ((uint64_t)S.lst[rk++] << 32) | (uint64_t)(kSent - id);
-              if (key > best && (v.all_valid || merge_valid(a, v, id, 0))) best = key;
-            }
-          }
-          if ((q.x | q.y | q.z | q.w) != 0) seen4[4 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
-        }
+      // The fold: every repeat visit of the wave's part names a repeated id
+      // (an id visited k times has k - 1 of them); its score is at its rank.
+      // Ids named twice are compared twice, to the same effect; n is no
+      // candidate of its own.
+      for (int o = lane; o < wcnt; o += kWave) {
+        const uint32_t id = S.lst[wid * kSeg + o];
+        const uint32_t rel = id - lo32;
+        const uint32_t w = S.seen[rel >> 5];
+        const uint32_t rank =
+            (uint32_t)S.wpre[rel >> 5] + (uint32_t)__popc(w & ((1u << (rel & 31)) - 1u));
+        const uint64_t key = ((uint64_t)S.sc[rank] << 32) | (uint64_t)(kSent - id);
+        if (id != n && key > best && (v.all_valid || merge_valid(a, v, id, 0))) best = key;
       }
       for (int jj = tid; jj < deg; jj += THREADS) {
         const int32_t c = S.m_cnt[jj];
@@ -1211,7 +1216,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         S.m_rem[jj] -= c;
       }
       lo = hi;
-      if (nrep < kList / 4 && width < (int64_t)kWinIds) {
+      if (nrep < kScores / 2 && width < (int64_t)kWinIds) {
         width *= 2;
         if (width > (int64_t)kWinIds) width = kWinIds;
       }
