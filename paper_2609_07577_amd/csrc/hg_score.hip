@@ -71,6 +71,9 @@ __device__ inline int log2_pow2(uint32_t c) { return 31 - __clz(c); }
 // A value that is the same in every lane (e.g. read from LDS at a
 // wave-uniform address), moved to a scalar register so that the control flow
 // depending on it stays scalar.
+// The lane mask of a predicate (HIP's __ballot takes an int, which costs a
+// select and a compare per call to turn the predicate back into a mask).
+__device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 __device__ inline int32_t rfl_i32(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ inline uint32_t rfl_u32(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)x);
@@ -620,8 +623,6 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
   }
 }
 
-// Exclusive scan over the block of one pair (x, y) per thread: prefix sums
-// (px, py) and block totals (tx, ty).  ws holds 2 * THREADS / 64 ints.
 // Inclusive prefix sum over the 64 lanes of a wave with the DPP unit: four
 // shifts within rows of 16 lanes, then the row totals carried into the later
 // rows with the row broadcasts (lanes shifted in from outside a row, and
@@ -636,31 +637,33 @@ __device__ inline int32_t wave_incl_scan(int32_t x) {
   return x;
 }
 
+// Exclusive block-wide prefix sums of three per-thread values (in thread
+// order) and their totals.  One barrier: the caller synchronises again
+// before ws (3 * NW entries) is written by another scan.
 template <int THREADS>
-__device__ inline void block_scan_pair(int32_t x, int32_t y, int32_t& px, int32_t& py,
-                                       int32_t& tx, int32_t& ty, int32_t* ws) {
+__device__ inline void block_scan3(const int32_t (&x)[3], int32_t (&px)[3], int32_t (&tx)[3],
+                                   int32_t* ws) {
   constexpr int NW = THREADS / kWave;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int32_t ix = wave_incl_scan(x), iy = wave_incl_scan(y);
-  if (lane == kWave - 1) {
-    ws[wid] = ix;
-    ws[NW + wid] = iy;
+  int32_t ix[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    ix[c] = wave_incl_scan(x[c]);
+    if (lane == kWave - 1) ws[c * NW + wid] = ix[c];
   }
   __syncthreads();
-  int32_t bx = 0, by = 0;
-  tx = 0;
-  ty = 0;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    const int32_t a = ws[w], b = ws[NW + w];
-    bx += w < wid ? a : 0;
-    by += w < wid ? b : 0;
-    tx += a;
-    ty += b;
+  for (int c = 0; c < 3; ++c) {
+    int32_t b = 0, t = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const int32_t a = ws[c * NW + w];
+      b += w < wid ? a : 0;
+      t += a;
+    }
+    px[c] = b + ix[c] - x[c];
+    tx[c] = t;
   }
-  px = bx + ix - x;
-  py = by + iy - y;
-  __syncthreads();  // ws may be reused
 }
 
 // Multipass over windows of neighbour ids for vertices whose incident
@@ -749,7 +752,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     uint32_t m_last[kWinDeg];      // largest id of the hyperedge
     int32_t m_cnt[kWinDeg];        // pins of the slice (below the window end)
     int32_t s_wcnt[NW];            // repeat visits of each wave (-1: its part overflowed)
-    int32_t ws[2 * NW];
+    int32_t ws[3 * NW];
     uint64_t red[2 * NW];
     int32_t s_item;
   };
@@ -817,14 +820,17 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     // Lists the hyperedges with batches: thread t looks at hyperedges 2t and
     // 2t + 1 and passes in, for each, its chunk count, run-on flag, slice
     // start and pin count (sweep 2 takes the chunk count from the pin
-    // count).  Returns the number of listed hyperedges and of batches
-    // (block-uniform).
-    auto list_batches = [&](const int32_t (&nbq)[2], const bool (&roq)[2],
-                            const uint32_t (&baseq)[2], const int32_t (&rq)[2],
-                            int32_t& nc, int32_t& tb) {
+    // count), and the place of its first entry and first batch (from a
+    // block scan of the entry and batch counts list_counts gives).
+    auto list_counts = [&](const int32_t (&nbq)[2], int32_t& ce, int32_t& cb) {
       const int32_t b0 = (nbq[0] + B - 1) / B, b1 = (nbq[1] + B - 1) / B;
-      int32_t pc, pb;
-      block_scan_pair<THREADS>((b0 > 0) + (b1 > 0), b0 + b1, pc, pb, nc, tb, S.ws);
+      ce = (b0 > 0) + (b1 > 0);
+      cb = b0 + b1;
+    };
+    auto list_write = [&](const int32_t (&nbq)[2], const bool (&roq)[2],
+                          const uint32_t (&baseq)[2], const int32_t (&rq)[2], int32_t pc,
+                          int32_t pb) {
+      const int32_t b0 = (nbq[0] + B - 1) / B, b1 = (nbq[1] + B - 1) / B;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int32_t bq = q == 0 ? b0 : b1;
@@ -841,7 +847,6 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
           pb += bq;
         }
       }
-      if (tid == 0) S.c_pre[nc] = tb;
     };
 
     // A batch: pins [base, base + lim) of hyperedge j's slice (lim = 0: no
@@ -876,7 +881,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         const int32_t idx = ci + lane < nc ? ci + lane : nc;
         const int32_t pre_l = S.c_pre[idx], e_l = S.c_list[idx], r_l = S.c_r[idx];
         const uint32_t base_l = S.c_base[idx];
-        const uint64_t m = __ballot(pre_l <= bnext);
+        const uint64_t m = ballot(pre_l <= bnext);
         const int32_t sel = (int32_t)__popcll(m) - 1;
         ci += sel;
         const int32_t e = __builtin_amdgcn_readlane(e_l, sel);
@@ -935,10 +940,13 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
             const int32_t full = (r + kWave - 1) / kWave;
             int32_t nb = full;
             if (S.m_last[j] >= hi32 && full > 2) {
-              const uint32_t l = S.m_last[j];
-              const float est = (float)r * (float)(hi - lo) / (float)((int64_t)l - lo + 1);
-              const float body = est + 2.0f * sqrtf(est) + (float)kWave;
-              nb = (int32_t)(body / (float)kWave) + 1;
+              // (the hardware reciprocal and square root: an estimate only,
+              // and the same on every run)
+              const uint32_t span = S.m_last[j] - lo32 + 1u;
+              const float est = (float)r * (float)(hi32 - lo32) *
+                                __builtin_amdgcn_rcpf((float)span);
+              const float body = est + 2.0f * __builtin_amdgcn_sqrtf(est) + (float)kWave;
+              nb = (int32_t)(body * (1.0f / (float)kWave)) + 1;
               nb = nb < full ? nb : full;
             }
             nbq[q] = nb;
@@ -948,7 +956,13 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
             S.m_cnt[j] = 0;
           }
         }
-        list_batches(nbq, roq, baseq, rq, nc, tb);
+        int32_t x3[3] = {0, 0, 0}, p3[3], t3[3];
+        list_counts(nbq, x3[0], x3[1]);
+        block_scan3<THREADS>(x3, p3, t3, S.ws);
+        nc = t3[0];
+        tb = t3[1];
+        list_write(nbq, roq, baseq, rq, p3[0], p3[1]);
+        if (tid == 0) S.c_pre[nc] = tb;
       }
       // the bitmap starts empty (the last window's fold left its repeated ids)
 #pragma unroll
@@ -974,7 +988,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         for (int u = 0; u < B; ++u) {
           id[u] = pin[u] & kIdMask;
           const bool in = (lofs[u] < lim4) & (id[u] < hi32);  // ids >= lo: cursor order
-          cnt += (int32_t)__popcll(__ballot(in));
+          cnt += (int32_t)__popcll(ballot(in));
           const uint32_t rel = id[u] - lo32;
           const uint32_t word = in ? rel >> 5 : (uint32_t)lane;
           bit[u] = in ? 1u << (rel & 31) : 0u;
@@ -990,7 +1004,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
 #pragma unroll
         for (int u = 0; u < B; ++u) {
           rep[u] = (old[u] & bit[u]) != 0;
-          rb[u] = __ballot(rep[u]);
+          rb[u] = ballot(rep[u]);
           nr += (int32_t)__popcll(rb[u]);
         }
         if (nr > 0 && !over) {  // wave-uniform (most batches hold a few)
@@ -1063,50 +1077,50 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         width = width / 2 > 0 ? width / 2 : 1;
         continue;  // the loop head synchronises before the next window
       }
-      // ---- sweep 2 batches: the exact slices ----
-      {
-        int32_t nbq[2] = {0, 0}, rq[2] = {0, 0};
-        const bool roq[2] = {false, false};
-        uint32_t baseq[2] = {0, 0};
+      // ---- sweep 2 batches (the exact slices), the bitmap of repeated ids
+      // and their ranks.  The bitmap was cleared above; each wave sets the
+      // ids of its own part of the list, and n counts as repeated, so that
+      // sweep 2 never takes it for a single.  Thread t then ranks its 16
+      // words: one block scan gives the list places and the ranks, stored
+      // per word two to a 32-bit store; the scores start at 0.
+      int32_t nbq[2] = {0, 0}, rq[2] = {0, 0};
+      const bool roq[2] = {false, false};
+      uint32_t baseq[2] = {0, 0};
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int32_t j = 2 * tid + q;
-          if (j < deg) {
-            rq[q] = S.m_cnt[j];
-            nbq[q] = (rq[q] + kWave - 1) / kWave;
-            baseq[q] = S.m_base[j];
-          }
+      for (int q = 0; q < 2; ++q) {
+        const int32_t j = 2 * tid + q;
+        if (j < deg) {
+          rq[q] = S.m_cnt[j];
+          nbq[q] = (rq[q] + kWave - 1) / kWave;
+          baseq[q] = S.m_base[j];
         }
-        list_batches(nbq, roq, baseq, rq, nc, tb);  // synchronises
       }
-      bnext = wid;
-      ci = 0;
-      // the bitmap of repeated ids (it was cleared before the list was
-      // built; each wave sets the ids of its own part, and n counts as
-      // repeated, so that sweep 2 never takes it for a single) and the rank
-      // prefix of every word; the scores start at 0
+      __syncthreads();  // bitmap cleared
       for (int o = lane; o < wcnt; o += kWave) {
         const uint32_t rel = S.lst[wid * kSeg + o] - lo32;
         atomicOr(&S.seen[rel >> 5], 1u << (rel & 31));
       }
       const bool n_in = n >= lo32 && n < hi32;  // block-uniform
       if (tid == 0 && n_in) atomicOr(&S.seen[(n - lo32) >> 5], 1u << ((n - lo32) & 31));
-      // Thread t ranks its 16 words: their repeated ids are counted, the
-      // counts scanned across the block, and the running rank stored per
-      // word, two to a 32-bit store.
+      __syncthreads();  // repeated ids marked
       int32_t nrank = 0;  // repeated ids of the window
-      if (nrep > 0 || n_in) {  // block-uniform
-        __syncthreads();
+      {
         uint4 q[4];
-        int32_t c = 0;
+        int32_t x3[3], p3[3], t3[3];
+        list_counts(nbq, x3[0], x3[1]);
+        x3[2] = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           q[i] = seen4[4 * tid + i];
-          c += __popc(q[i].x) + __popc(q[i].y) + __popc(q[i].z) + __popc(q[i].w);
+          x3[2] += __popc(q[i].x) + __popc(q[i].y) + __popc(q[i].z) + __popc(q[i].w);
         }
-        int32_t before, unused0, unused1;
-        block_scan_pair<THREADS>(c, 0, before, unused0, nrank, unused1, S.ws);
-        uint32_t run = (uint32_t)before, pk[8];
+        block_scan3<THREADS>(x3, p3, t3, S.ws);
+        nc = t3[0];
+        tb = t3[1];
+        nrank = t3[2];
+        list_write(nbq, roq, baseq, rq, p3[0], p3[1]);
+        if (tid == 0) S.c_pre[nc] = tb;
+        uint32_t run = (uint32_t)p3[2], pk[8];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const uint32_t r0 = run;
@@ -1120,10 +1134,14 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
           pk[2 * i] = r0 | (r1 << 16);
           pk[2 * i + 1] = r2 | (r3 << 16);
         }
-        wpre4[2 * tid] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
-        wpre4[2 * tid + 1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
-        for (int i = tid; i < nrank; i += THREADS) S.sc[i] = 0;
+        if (nrank > 0) {  // block-uniform
+          wpre4[2 * tid] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+          wpre4[2 * tid + 1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+          for (int i = tid; i < nrank; i += THREADS) S.sc[i] = 0;
+        }
       }
+      bnext = wid;
+      ci = 0;
       __syncthreads();  // list of batches, bitmap, ranks and scores ready
 
       // ---- sweep 2 ----
@@ -1164,14 +1182,14 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
             rep[u] = ((w[u] >> ((id[u] - lo32) & 31)) & 1u) != 0;
             const uint64_t key = ((uint64_t)t.wt << 32) | (uint64_t)(kSent - id[u]);
             bool better = act[u] & !rep[u] & (key > best);
-            if (__ballot(better) != 0) {  // wave-uniform
+            if (ballot(better) != 0) {  // wave-uniform
               if (better) better = merge_valid(a, v, id[u], 0);
             }
             best = better ? key : best;
             anyadd |= act[u] & rep[u];
           }
         }
-        if (__ballot(anyadd) != 0) {  // wave-uniform
+        if (ballot(anyadd) != 0) {  // wave-uniform
 #pragma unroll
           for (int u = 0; u < B; ++u) {
             if (act[u] & rep[u]) {
