@@ -719,7 +719,6 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
   constexpr int kList = 4096;         // repeat visits of a window
   constexpr int kSeg = kList / NW;    // a wave's part of them
   constexpr int kScores = 2048;       // repeated ids of a window
-  constexpr int kNbMax = (1 << 21) - 1;  // chunk count a list entry holds
   constexpr uint32_t kSent = 0x7FFFFFFFu;
   // thread t ranks and drains the bitmap words [16 t, 16 t + 16)
   static_assert(kWords == 16 * THREADS, "a thread owns 16 consecutive bitmap words");
@@ -733,12 +732,13 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     // The hyperedges that have batches in the current sweep (one extra
     // entry: c_pre there holds the number of batches).
     int32_t c_pre[kWinDeg + 1];    // batches before the hyperedge
-    // the hyperedge j (bits 0-9), in sweep 1 the chunks its batches cover
-    // (bits 10-30; they end at most at kNbMax) and whether its slice may run
-    // on past them (bit 31)
+    // the hyperedge j (bits 0-9) and, in sweep 1, whether its slice may run
+    // on past its batches (bit 31)
     int32_t c_list[kWinDeg + 1];
-    uint32_t c_base[kWinDeg + 1];  // first pin of its slice
-    int32_t c_r[kWinDeg + 1];      // pins left (sweep 1) / of the slice (sweep 2)
+    // the first pin of its slice less c_pre * kBatchPins (modulo 2^32), so
+    // that batch b starts at pin c_base + b * kBatchPins
+    uint32_t c_base[kWinDeg + 1];
+    uint32_t c_end[kWinDeg + 1];   // the pin after the last its batches cover
     alignas(16) uint32_t seen[kWords];
     // the ids of sweep 1's repeat visits, wave w's from w * kSeg on (plus a
     // slot per lane that takes no visit); they stay for the final fold
@@ -836,13 +836,11 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         const int32_t bq = q == 0 ? b0 : b1;
         if (bq > 0) {
           const int32_t j = 2 * tid + q;
-          // chunks past kNbMax are reached as a continuation
-          const bool ro = roq[q] || nbq[q] > kNbMax;
-          const int32_t nb = nbq[q] < kNbMax ? nbq[q] : kNbMax;
-          S.c_list[pc] = j | (nb << 10) | (ro ? (int32_t)0x80000000 : 0);
+          const int64_t cover = (int64_t)nbq[q] * kWave;
+          S.c_list[pc] = j | (roq[q] ? (int32_t)0x80000000 : 0);
           S.c_pre[pc] = pb;
-          S.c_base[pc] = baseq[q];
-          S.c_r[pc] = rq[q];
+          S.c_base[pc] = baseq[q] - (uint32_t)pb * (uint32_t)kBatchPins;
+          S.c_end[pc] = baseq[q] + (uint32_t)(rq[q] < cover ? rq[q] : cover);
           ++pc;
           pb += bq;
         }
@@ -879,22 +877,23 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         // form a prefix, and it lies within NW entries of ci.  Every lane
         // reads its entry, and the chosen one is taken with readlane.
         const int32_t idx = ci + lane < nc ? ci + lane : nc;
-        const int32_t pre_l = S.c_pre[idx], e_l = S.c_list[idx], r_l = S.c_r[idx];
-        const uint32_t base_l = S.c_base[idx];
+        const int32_t pre_l = S.c_pre[idx], e_l = S.c_list[idx];
+        const uint32_t base_l = S.c_base[idx], end_l = S.c_end[idx];
         const uint64_t m = ballot(pre_l <= bnext);
         const int32_t sel = (int32_t)__popcll(m) - 1;
         ci += sel;
         const int32_t e = __builtin_amdgcn_readlane(e_l, sel);
-        const int32_t r = __builtin_amdgcn_readlane(r_l, sel);
-        const int32_t nb = sweep1 ? (e >> 10) & kNbMax : (r + kWave - 1) / kWave;
-        const int32_t k = (bnext - __builtin_amdgcn_readlane(pre_l, sel)) * B;
-        const int32_t kend = k + B < nb ? k + B : nb;
+        const uint32_t end = (uint32_t)__builtin_amdgcn_readlane((int32_t)end_l, sel);
         j = e & 0x3FF;
-        base = (uint32_t)__builtin_amdgcn_readlane((int32_t)base_l, sel) + (uint32_t)(k * kWave);
-        lim = r - k * kWave < (kend - k) * kWave ? r - k * kWave : (kend - k) * kWave;
-        // only the batch holding the hyperedge's last listed chunk may find
-        // that the slice runs on (its chunks are then full)
-        if (sweep1 && e < 0 && kend == nb) rem = r - kend * kWave;
+        base = (uint32_t)__builtin_amdgcn_readlane((int32_t)base_l, sel) +
+               (uint32_t)bnext * (uint32_t)kBatchPins;
+        const uint32_t left = end - base;  // at least 1
+        lim = (int32_t)(left < (uint32_t)kBatchPins ? left : (uint32_t)kBatchPins);
+        // only the batch that reaches the end of the hyperedge's listed pins
+        // may find that the slice runs on (its chunks are then full); the
+        // pins left are those up to the hyperedge's end
+        if (sweep1 && e < 0 && left <= (uint32_t)kBatchPins)
+          rem = (int32_t)(S.m_base[j] + (uint32_t)S.m_rem[j] - end);
         if (!sweep1) wt = (uint32_t)S.m_w[j];
         bnext += NW;
       }
@@ -1017,8 +1016,11 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
             wcnt += nr;
 #pragma unroll
             for (int u = 0; u < B; ++u) {
-              const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+              uint32_t below = __builtin_amdgcn_mbcnt_hi(
                   (uint32_t)(rb[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)rb[u], 0u));
+              // in every lane (left to itself the compiler computes it under
+              // an exec mask of the repeat lanes, at more scalar cost)
+              asm volatile("" : "+v"(below));
               S.lst[rep[u] ? at + below : (uint32_t)(kList + lane)] = id[u];
               at += (uint32_t)__popcll(rb[u]);
             }
