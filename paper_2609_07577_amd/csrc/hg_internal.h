@@ -131,7 +131,7 @@ constexpr int kSmallSlots = 4096;
 constexpr int kBigSlots = 16384;
 constexpr int kBigSlotsOv = 8192;
 constexpr int kMetaDeg = 1280;
-constexpr int kWinDeg = 1024;  // incident hyperedges of a window-kernel vertex
+constexpr int kWinDeg = 768;  // incident hyperedges of a window-kernel vertex
 struct Buckets {
   int32_t* count;  // [kNumBuckets] device counters
   int32_t* list;   // [kNumBuckets * maxV]

@@ -718,7 +718,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
   constexpr int kWords = (int)(kWinIds / 32);
   constexpr int kList = 4096;         // repeat visits of a window
   constexpr int kSeg = kList / NW;    // a wave's part of them
-  constexpr int kScores = 2048;       // repeated ids of a window
+  constexpr int kScores = 4096;       // repeated ids of a window
   constexpr uint32_t kSent = 0x7FFFFFFFu;
   // thread t ranks and drains the bitmap words [16 t, 16 t + 16)
   static_assert(kWords == 16 * THREADS, "a thread owns 16 consecutive bitmap words");
@@ -1236,7 +1236,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         S.m_rem[jj] -= c;
       }
       lo = hi;
-      if (nrep < kScores / 2 && width < (int64_t)kWinIds) {
+      if (nrep < kList / 4 && width < (int64_t)kWinIds) {
         width *= 2;
         if (width > (int64_t)kWinIds) width = kWinIds;
       }

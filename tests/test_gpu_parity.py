@@ -311,7 +311,7 @@ def test_out_of_range_maps_are_rejected(ctx):
 def _window_bucket_vertices(g, load16=8, big_slots=16384):
     """Vertices the score step gives to the multipass window kernel: the
     distinct-neighbour bound min(X_n, V - 1) above the single-pass capacity
-    (load16/16 of the big table) with at most 1024 incident hyperedges
+    (load16/16 of the big table) with at most 768 incident hyperedges
     (the overlap bound cannot bind for these level-0 limits)."""
     L0 = oracle.level0(g)
     lens = np.diff(L0.eoff).astype(np.int64)
@@ -320,7 +320,7 @@ def _window_bucket_vertices(g, load16=8, big_slots=16384):
     xn = np.bincount(ids, weights=lens[edge_of_pin], minlength=g.n_vertices)
     deg = np.bincount(ids, minlength=g.n_vertices)
     dist = np.minimum(xn, g.n_vertices - 1)
-    return np.flatnonzero((dist > big_slots * load16 // 16) & (deg <= 1024))
+    return np.flatnonzero((dist > big_slots * load16 // 16) & (deg <= 768))
 
 
 def test_window_list_overflow_halves_the_window(ctx):
