@@ -722,7 +722,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
   constexpr uint32_t kSent = 0x7FFFFFFFu;
   // thread t ranks and drains the bitmap words [16 t, 16 t + 16)
   static_assert(kWords == 16 * THREADS, "a thread owns 16 consecutive bitmap words");
-  static_assert(kWinDeg <= 2 * THREADS, "a thread lists at most two hyperedges");
+  static_assert(kWinDeg <= THREADS, "thread j lists hyperedge j");
   static_assert(kWinDeg <= 1024, "a list entry holds the hyperedge in 10 bits");
   static_assert(B == 4, "the register uses name B registers");
   // One LDS block laid out by hand: the descriptors of the listed
@@ -817,33 +817,18 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     int64_t width = hi_all - lo < (int64_t)kWinIds ? hi_all - lo : (int64_t)kWinIds;
     int passes = 0;
 
-    // Lists the hyperedges with batches: thread t looks at hyperedges 2t and
-    // 2t + 1 and passes in, for each, its chunk count, run-on flag, slice
-    // start and pin count (sweep 2 takes the chunk count from the pin
-    // count), and the place of its first entry and first batch (from a
-    // block scan of the entry and batch counts list_counts gives).
-    auto list_counts = [&](const int32_t (&nbq)[2], int32_t& ce, int32_t& cb) {
-      const int32_t b0 = (nbq[0] + B - 1) / B, b1 = (nbq[1] + B - 1) / B;
-      ce = (b0 > 0) + (b1 > 0);
-      cb = b0 + b1;
-    };
-    auto list_write = [&](const int32_t (&nbq)[2], const bool (&roq)[2],
-                          const uint32_t (&baseq)[2], const int32_t (&rq)[2], int32_t pc,
+    // Lists the hyperedges with batches: thread j looks at hyperedge j and
+    // passes in its chunk count nb, run-on flag, slice start and pin count,
+    // and the place of its entry and first batch (from a block scan of the
+    // batch counts; a hyperedge with batches takes one entry).
+    auto list_write = [&](int32_t nb, bool ro, uint32_t base, int32_t r, int32_t pc,
                           int32_t pb) {
-      const int32_t b0 = (nbq[0] + B - 1) / B, b1 = (nbq[1] + B - 1) / B;
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int32_t bq = q == 0 ? b0 : b1;
-        if (bq > 0) {
-          const int32_t j = 2 * tid + q;
-          const int64_t cover = (int64_t)nbq[q] * kWave;
-          S.c_list[pc] = j | (roq[q] ? (int32_t)0x80000000 : 0);
-          S.c_pre[pc] = pb;
-          S.c_base[pc] = baseq[q] - (uint32_t)pb * (uint32_t)kBatchPins;
-          S.c_end[pc] = baseq[q] + (uint32_t)(rq[q] < cover ? rq[q] : cover);
-          ++pc;
-          pb += bq;
-        }
+      if (nb > 0) {
+        const int64_t cover = (int64_t)nb * kWave;
+        S.c_list[pc] = tid | (ro ? (int32_t)0x80000000 : 0);
+        S.c_pre[pc] = pb;
+        S.c_base[pc] = base - (uint32_t)pb * (uint32_t)kBatchPins;
+        S.c_end[pc] = base + (uint32_t)(r < cover ? r : cover);
       }
     };
 
@@ -928,39 +913,32 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       // the window (or has at most two left), else a generous estimate of the
       // slice, flagged as possibly running on
       {
-        int32_t nbq[2] = {0, 0}, rq[2] = {0, 0};
-        bool roq[2] = {false, false};
-        uint32_t baseq[2] = {0, 0};
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int32_t j = 2 * tid + q;
-          if (j < deg) {
-            const int32_t r = S.m_rem[j];
-            const int32_t full = (r + kWave - 1) / kWave;
-            int32_t nb = full;
-            if (S.m_last[j] >= hi32 && full > 2) {
-              // (the hardware reciprocal and square root: an estimate only,
-              // and the same on every run)
-              const uint32_t span = S.m_last[j] - lo32 + 1u;
-              const float est = (float)r * (float)(hi32 - lo32) *
-                                __builtin_amdgcn_rcpf((float)span);
-              const float body = est + 2.0f * __builtin_amdgcn_sqrtf(est) + (float)kWave;
-              nb = (int32_t)(body * (1.0f / (float)kWave)) + 1;
-              nb = nb < full ? nb : full;
-            }
-            nbq[q] = nb;
-            roq[q] = nb < full;
-            rq[q] = r;
-            baseq[q] = S.m_base[j];
-            S.m_cnt[j] = 0;
+        int32_t nb = 0, r = 0, full = 0;
+        uint32_t base = 0;
+        if (tid < deg) {
+          r = S.m_rem[tid];
+          full = (r + kWave - 1) / kWave;
+          nb = full;
+          const uint32_t last = S.m_last[tid];
+          if (last >= hi32 && full > 2) {
+            // (the hardware reciprocal and square root: an estimate only,
+            // and the same on every run)
+            const uint32_t span = last - lo32 + 1u;
+            const float est =
+                (float)r * (float)(hi32 - lo32) * __builtin_amdgcn_rcpf((float)span);
+            const float body = est + 2.0f * __builtin_amdgcn_sqrtf(est) + (float)kWave;
+            nb = (int32_t)(body * (1.0f / (float)kWave)) + 1;
+            nb = nb < full ? nb : full;
           }
+          base = S.m_base[tid];
+          S.m_cnt[tid] = 0;
         }
-        int32_t x3[3] = {0, 0, 0}, p3[3], t3[3];
-        list_counts(nbq, x3[0], x3[1]);
+        const int32_t nbat = (nb + B - 1) / B;
+        int32_t x3[3] = {nbat > 0, nbat, 0}, p3[3], t3[3];
         block_scan3<THREADS>(x3, p3, t3, S.ws);
         nc = t3[0];
         tb = t3[1];
-        list_write(nbq, roq, baseq, rq, p3[0], p3[1]);
+        list_write(nb, nb < full, base, r, p3[0], p3[1]);
         if (tid == 0) S.c_pre[nc] = tb;
       }
       // the bitmap starts empty (the last window's fold left its repeated ids)
@@ -982,26 +960,23 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       auto process1 = [&](const Batch& t, const uint32_t (&pin)[B]) {
         const uint32_t lim4 = (uint32_t)t.lim * 4u;
         uint32_t id[B], bit[B], old[B];
-        int32_t cnt = 0;
 #pragma unroll
         for (int u = 0; u < B; ++u) {
           id[u] = pin[u] & kIdMask;
           const bool in = (lofs[u] < lim4) & (id[u] < hi32);  // ids >= lo: cursor order
-          cnt += (int32_t)__popcll(ballot(in));
           const uint32_t rel = id[u] - lo32;
           const uint32_t word = in ? rel >> 5 : (uint32_t)lane;
           bit[u] = in ? 1u << (rel & 31) : 0u;
           old[u] = atomicOr(&S.seen[word], bit[u]);
         }
-        // count here, in a scalar register: left to itself the compiler sinks
-        // the count below the list appends and keeps the B lane masks alive
-        // across them as 0/1 vectors
-        asm volatile("" : "+s"(cnt));
+        // the pins below the window end (a lane has a bit iff it has one),
+        // and the repeat visits
         bool rep[B];
         uint64_t rb[B];
-        int32_t nr = 0;
+        int32_t nr = 0, cnt = 0;
 #pragma unroll
         for (int u = 0; u < B; ++u) {
+          cnt += (int32_t)__popcll(ballot(bit[u] != 0));
           rep[u] = (old[u] & bit[u]) != 0;
           rb[u] = ballot(rep[u]);
           nr += (int32_t)__popcll(rb[u]);
@@ -1085,17 +1060,12 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       // sweep 2 never takes it for a single.  Thread t then ranks its 16
       // words: one block scan gives the list places and the ranks, stored
       // per word two to a 32-bit store; the scores start at 0.
-      int32_t nbq[2] = {0, 0}, rq[2] = {0, 0};
-      const bool roq[2] = {false, false};
-      uint32_t baseq[2] = {0, 0};
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int32_t j = 2 * tid + q;
-        if (j < deg) {
-          rq[q] = S.m_cnt[j];
-          nbq[q] = (rq[q] + kWave - 1) / kWave;
-          baseq[q] = S.m_base[j];
-        }
+      int32_t nb2 = 0, r2 = 0;
+      uint32_t base2 = 0;
+      if (tid < deg) {
+        r2 = S.m_cnt[tid];
+        nb2 = (r2 + kWave - 1) / kWave;
+        base2 = S.m_base[tid];
       }
       __syncthreads();  // bitmap cleared
       for (int o = lane; o < wcnt; o += kWave) {
@@ -1108,9 +1078,8 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       int32_t nrank = 0;  // repeated ids of the window
       {
         uint4 q[4];
-        int32_t x3[3], p3[3], t3[3];
-        list_counts(nbq, x3[0], x3[1]);
-        x3[2] = 0;
+        const int32_t nbat = (nb2 + B - 1) / B;
+        int32_t x3[3] = {nbat > 0, nbat, 0}, p3[3], t3[3];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           q[i] = seen4[4 * tid + i];
@@ -1120,7 +1089,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         nc = t3[0];
         tb = t3[1];
         nrank = t3[2];
-        list_write(nbq, roq, baseq, rq, p3[0], p3[1]);
+        list_write(nb2, false, base2, r2, p3[0], p3[1]);
         if (tid == 0) S.c_pre[nc] = tb;
         uint32_t run = (uint32_t)p3[2], pk[8];
 #pragma unroll
@@ -1230,10 +1199,10 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         const uint64_t key = ((uint64_t)S.sc[rank] << 32) | (uint64_t)(kSent - id);
         if (id != n && key > best && (v.all_valid || merge_valid(a, v, id, 0))) best = key;
       }
-      for (int jj = tid; jj < deg; jj += THREADS) {
-        const int32_t c = S.m_cnt[jj];
-        S.m_base[jj] += (uint32_t)c;
-        S.m_rem[jj] -= c;
+      if (tid < deg) {
+        const int32_t c = S.m_cnt[tid];
+        S.m_base[tid] += (uint32_t)c;
+        S.m_rem[tid] -= c;
       }
       lo = hi;
       if (nrep < kList / 4 && width < (int64_t)kWinIds) {
