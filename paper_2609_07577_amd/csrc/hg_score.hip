@@ -644,7 +644,8 @@ template <int THREADS>
 __device__ inline void block_scan3(const int32_t (&x)[3], int32_t (&px)[3], int32_t (&tx)[3],
                                    int32_t* ws) {
   constexpr int NW = THREADS / kWave;
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   int32_t ix[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -652,17 +653,18 @@ __device__ inline void block_scan3(const int32_t (&x)[3], int32_t (&px)[3], int3
     if (lane == kWave - 1) ws[c * NW + wid] = ix[c];
   }
   __syncthreads();
+  // the wave totals, one per lane, scanned again; a wave takes the sum of
+  // the waves before it and the total with readlane
+  static_assert(NW <= kWave, "one lane per wave");
+  int32_t wt[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) wt[c] = lane < NW ? ws[c * NW + lane] : 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    int32_t b = 0, t = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      const int32_t a = ws[c * NW + w];
-      b += w < wid ? a : 0;
-      t += a;
-    }
-    px[c] = b + ix[c] - x[c];
-    tx[c] = t;
+    const int32_t inc = wave_incl_scan(wt[c]);
+    const int32_t before = wid > 0 ? __builtin_amdgcn_readlane(inc, wid - 1) : 0;
+    px[c] = before + ix[c] - x[c];
+    tx[c] = __builtin_amdgcn_readlane(inc, NW - 1);
   }
 }
 
