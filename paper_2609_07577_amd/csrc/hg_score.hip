@@ -770,6 +770,13 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
   const int32_t* list = a.b.list + (int64_t)bucket * maxV;
   uint4* const seen4 = reinterpret_cast<uint4*>(S.seen);
   uint4* const wpre4 = reinterpret_cast<uint4*>(S.wpre);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) seen4[4 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
+  // What the last completed window left in the bitmap: the words of the
+  // wave's repeat visits (ids relative to prev_lo) and of n (prev_nword,
+  // -1 for none).  They are cleared at the next window's start.
+  int32_t prev_wcnt = 0, prev_nword = -1;
+  uint32_t prev_lo = 0;
   // byte offset of the lane's pin in each chunk of a batch
   uint32_t lofs[B];
 #pragma unroll
@@ -943,9 +950,12 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         list_write(nb, nb < full, base, r, p3[0], p3[1]);
         if (tid == 0) S.c_pre[nc] = tb;
       }
-      // the bitmap starts empty (the last window's fold left its repeated ids)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) seen4[4 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
+      // the bitmap starts empty: the last window left only its repeated ids
+      for (int o = lane; o < prev_wcnt; o += kWave)
+        S.seen[(S.lst[wid * kSeg + o] - prev_lo) >> 5] = 0;
+      if (tid == 0 && prev_nword >= 0) S.seen[prev_nword] = 0;
+      prev_wcnt = 0;
+      prev_nword = -1;
       __syncthreads();
       bnext = wid;
       ci = 0;
@@ -1040,14 +1050,11 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       }
       S.s_wcnt[wid] = over ? -1 : wcnt;  // every lane stores the same value
       __syncthreads();
-      bool any_over = false;
-      int32_t nrep = 0;  // repeat visits of the window
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        const int32_t c = S.s_wcnt[w];
-        any_over |= c < 0;
-        nrep += c > 0 ? c : 0;
-      }
+      // the waves' counts, one per lane
+      const int32_t wc = lane < NW ? S.s_wcnt[lane] : 0;
+      bool any_over = ballot(wc < 0) != 0;
+      const int32_t nrep =  // repeat visits of the window
+          __builtin_amdgcn_readlane(wave_incl_scan(wc > 0 ? wc : 0), kWave - 1);
       // more repeated ids than scores (at most nrep, and n)
       any_over |= nrep >= kScores;  // more repeated ids than scores (at most nrep)
 #pragma unroll
@@ -1206,6 +1213,9 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         S.m_base[tid] += (uint32_t)c;
         S.m_rem[tid] -= c;
       }
+      prev_wcnt = wcnt;
+      prev_lo = lo32;
+      prev_nword = n_in ? (int32_t)((n - lo32) >> 5) : -1;
       lo = hi;
       if (nrep < kList / 4 && width < (int64_t)kWinIds) {
         width *= 2;
