@@ -347,3 +347,23 @@ def test_window_slice_runs_past_its_estimate(ctx):
     g = synth.from_axons(n, axons)
     assert len(_window_bucket_vertices(g)) >= 4000
     run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
+
+
+def test_window_degree_limit(ctx):
+    """Two large neighbourhoods on either side of the window kernel's limit
+    on incident hyperedges: vertex 0 is a target of 768 axons (scored in
+    windows), vertex 1 of 769 (scored by the global multipass kernel); each
+    axon also reaches 20 random neurons.  The levels must be the oracle's."""
+    rng = np.random.default_rng(7)
+    n = 70_000
+    axons = []
+    src = 2
+    for target, k in ((0, 768), (1, 769)):
+        for _ in range(k):
+            others = rng.choice(np.arange(2_000, n), size=20, replace=False)
+            axons.append((src, [target] + sorted(int(x) for x in others), int(rng.integers(1, 100))))
+            src += 1
+    g = synth.from_axons(n, axons)
+    wb = set(_window_bucket_vertices(g).tolist())
+    assert 0 in wb and 1 not in wb
+    run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
