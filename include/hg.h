@@ -201,9 +201,9 @@ int hg_connectivity(hg_ctx* ctx, const hg_level* lvl, const int32_t* part, int64
  * expansion, the sum of the sizes of its incident hyperedges, capped by the
  * vertex count) is at most single_pass_load16/16 of the table's slots.
  * Larger neighbourhoods are scored in windows of neighbour ids with an
- * on-chip bitmap.  Where the distinct-axon overlap of Section 3 can bind,
- * they are scored in passes over a table, each range aimed at
- * pass_fill16/16 of it.  Results never depend on these values, only the
+ * on-chip bitmap.  Where the distinct-axon overlap of Section 3 can bind, or
+ * a vertex has more than 768 incident hyperedges, they are scored in passes
+ * over a table, each range aimed at pass_fill16/16 of it.  Results never depend on these values, only the
  * speed does.  Defaults 8 and 5; accepted ranges 1..12 and 1..10
  * (HG_ERR_INVALID_ARG otherwise).
  */

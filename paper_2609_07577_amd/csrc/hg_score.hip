@@ -22,6 +22,7 @@
 // Delta; it is then the summed multiplicity of hyperedges in which both n and
 // m carry the destination flag, found by binary search of m in n's inbound
 // hyperedges.
+#include <type_traits>
 #include "hg_internal.h"
 
 namespace hg {
@@ -678,25 +679,30 @@ __device__ inline void block_scan3(const int32_t (&x)[3], int32_t (&px)[3], int3
 //     to the window end, setting one LDS bit per id; a visit that finds its
 //     bit already set appends the id to the wave's part of a list of repeat
 //     visits, and the pins below the window end are counted;
-//   the bitmap is then rebuilt to hold just the repeated ids, and a prefix
-//     count per bitmap word gives every repeated id a dense rank (the number
-//     of repeated ids below it in the window);
+//   the bitmap is then rebuilt to hold just the repeated ids (n, visited
+//     like any id, counts as repeated), and a prefix count per bitmap word
+//     gives every repeated id a dense rank (the number of repeated ids below
+//     it in the window);
 //   sweep 2 visits the same pins again: a repeated id adds the hyperedge
 //     weight to the score at its rank, any other id has its complete score
 //     and is compared with the lane's best;
-//   the repeated ids' scores are folded into the best (validity tested only
-//     for those that beat it), and the cursors move past the counted pins.
+//   the fold: each repeat visit names a repeated id, whose score (at its
+//     rank) is compared with the lane's best (validity tested only for
+//     those that beat it; n is left out), and the cursors move past the
+//     counted pins.
 // No step probes a table: each visit is one LDS bit operation, and a
 // repeated one one more LDS add.  A window whose repeat visits overflow a
-// wave's part of the list is abandoned and retried at half the width.
+// wave's part of the list, or whose repeated ids could outnumber the
+// scores, is abandoned and retried at half the width.
 //
 // Work balance: hyperedge sizes follow a heavy-tailed law, so each sweep cuts
 // the vertex's slices into batches of B chunks (64 pins each), numbers the
 // batches of all hyperedges in a row, and deals them to the waves round
-// robin.  The listed hyperedges carry everything a wave needs to load and
-// process a batch (slice start, pin count, chunk count, weight), so a wave
-// finds its next batch with one LDS read per lane, a ballot and a few
-// readlanes.  A wave issues the B loads of its next batch before it
+// robin.  A list entry per hyperedge with batches holds its first batch
+// number, a virtual base and the end of the pins its batches cover, so a
+// wave finds its next batch with one LDS read per lane, a ballot and a few
+// readlanes, and the batch's start and pin count with two scalar
+// operations each.  A wave issues the B loads of its next batch before it
 // processes the current one.  In sweep 1 the slice end is not known in
 // advance: the batches cover an estimate of it (from the pins' id density,
 // plus two standard deviations and a chunk), every pin is tested against
@@ -705,11 +711,11 @@ __device__ inline void block_scan3(const int32_t (&x)[3], int32_t (&px)[3], int3
 // of pins below the window end is exact whatever the estimate; a poor one
 // only costs loads.
 //
-// The sweeps are bound by instruction issue (a batch holds 150-250 useful
-// pins), so the per-batch bookkeeping is kept scalar and short: batch
-// fields are a pin offset and a pin count, lanes are tested against the
-// count with one compare per chunk, and loads take a scalar base and a
-// lane offset clamped to the batch's last live pin.
+// The sweeps are bound by each wave's instruction stream (a batch holds
+// 150-250 useful pins), so the per-batch bookkeeping is kept scalar and
+// short: lanes are tested against the batch's pin count with one compare
+// per chunk, and loads take a scalar base and a lane offset clamped to the
+// batch's last live pin.
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int bucket,
                                                               int64_t maxV) {
@@ -722,7 +728,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
   constexpr int kSeg = kList / NW;    // a wave's part of them
   constexpr int kScores = 4096;       // repeated ids of a window
   constexpr uint32_t kSent = 0x7FFFFFFFu;
-  // thread t ranks and drains the bitmap words [16 t, 16 t + 16)
+  // thread t ranks the bitmap words [16 t, 16 t + 16)
   static_assert(kWords == 16 * THREADS, "a thread owns 16 consecutive bitmap words");
   static_assert(kWinDeg <= THREADS, "thread j lists hyperedge j");
   static_assert(kWinDeg <= 1024, "a list entry holds the hyperedge in 10 bits");
@@ -913,7 +919,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     while (lo < hi_all) {
       const int64_t hi = lo + width < hi_all ? lo + width : hi_all;
       const uint32_t lo32 = (uint32_t)lo, hi32 = (uint32_t)hi;  // ids are below 2^31
-      __syncthreads();  // previous window drained / cleared, flags read, cursors committed
+      __syncthreads();  // previous window folded, flags read, cursors committed
       if (++passes > kMaxPasses) {
         if (tid == 0) atomicOr(a.err, kErrPassLimit);
         break;
@@ -1125,7 +1131,9 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       __syncthreads();  // list of batches, bitmap, ranks and scores ready
 
       // ---- sweep 2 ----
-      auto process2 = [&](const Batch& t, const uint32_t (&pin)[B]) {
+      // (allv: std::true_type when no merge of n can break a limit, so that
+      // the loop for that case carries no validity test)
+      auto process2 = [&](const Batch& t, const uint32_t (&pin)[B], auto allv) {
         if (t.lim == 0) {  // wave-uniform: no batch (its pins may lie outside
                            // the window; they are not looked at)
           asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
@@ -1143,7 +1151,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
           w[u] = S.seen[(id[u] - lo32) >> 5];
         }
         bool anyadd = false;
-        if (v.all_valid) {  // block-uniform
+        if (decltype(allv)::value) {
           // every single scores the batch's weight: the best of them is the
           // smallest id
           uint32_t mid = kSent;
@@ -1183,17 +1191,21 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         // as in sweep 1: every batch's loads are complete here
         asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
       };
-      {
+      auto sweep2 = [&](auto allv) {
         Batch ta, tb2;
         uint32_t pa[B], pb[B];
         fetch(ta, pa, false);
         while (ta.lim > 0) {
           fetch(tb2, pb, false);
-          process2(ta, pa);
+          process2(ta, pa, allv);
           fetch(ta, pa, false);
-          process2(tb2, pb);
+          process2(tb2, pb, allv);
         }
-      }
+      };
+      if (v.all_valid)  // block-uniform: one sweep-2 loop per case
+        sweep2(std::true_type{});
+      else
+        sweep2(std::false_type{});
       __syncthreads();  // sweep 2 done: scores complete
       // The fold: every repeat visit of the wave's part names a repeated id
       // (an id visited k times has k - 1 of them); its score is at its rank.
