@@ -674,7 +674,9 @@ __device__ inline void block_scan3(const int32_t (&x)[3], int32_t (&px)[3], int3
 // neighbourhood most neighbours share a single hyperedge with n: the score
 // of such a neighbour is that hyperedge's weight, known from the visit
 // itself, and needs no table.  Per window [lo, lo + width) of ids, width at
-// most kWinIds:
+// most kWinMax, the bitmap starts at the word holding lo (bit i of word k
+// stands for id 32 (lo / 32 + k) + i), so that an id's word and bit come
+// from the id alone:
 //   sweep 1 visits the pins of every incident hyperedge from its cursor up
 //     to the window end, setting one LDS bit per id; a visit that finds its
 //     bit already set appends the id to the wave's part of a list of repeat
@@ -698,32 +700,38 @@ __device__ inline void block_scan3(const int32_t (&x)[3], int32_t (&px)[3], int3
 // Work balance: hyperedge sizes follow a heavy-tailed law, so each sweep cuts
 // the vertex's slices into batches of B chunks (64 pins each), numbers the
 // batches of all hyperedges in a row, and deals them to the waves round
-// robin.  A list entry per hyperedge with batches holds its first batch
-// number, a virtual base and the end of the pins its batches cover, so a
-// wave finds its next batch with one LDS read per lane, a ballot and a few
-// readlanes, and the batch's start and pin count with two scalar
-// operations each.  A wave issues the B loads of its next batch before it
+// robin.  A 16-byte list entry per hyperedge with batches holds its first
+// batch number, the hyperedge, a virtual base and the end of the pins its
+// batches cover, so a wave finds its next batch with one 16-byte LDS read
+// per lane, a ballot and a few readlanes, and the batch's start and pin
+// count with two scalar operations each.  A wave issues the B loads of its next batch before it
 // processes the current one.  In sweep 1 the slice end is not known in
 // advance: the batches cover an estimate of it (from the pins' id density,
 // plus two standard deviations and a chunk), every pin is tested against
 // the window end, and when a slice runs on past its batches the wave holding
 // the last of them continues with further batches until the end.  The count
 // of pins below the window end is exact whatever the estimate; a poor one
-// only costs loads.
+// only costs loads.  Since a hyperedge's pins ascend, that count is a batch's
+// ballot of ids below the window end (lanes past the batch hold its last
+// pin), capped at the batch's size.
 //
 // The sweeps are bound by each wave's instruction stream (a batch holds
 // 150-250 useful pins), so the per-batch bookkeeping is kept scalar and
 // short: lanes are tested against the batch's pin count with one compare
-// per chunk, and loads take a scalar base and a lane offset clamped to the
-// batch's last live pin.
+// per chunk, loads take a scalar base and a lane offset clamped to the
+// batch's last live pin, and an id's bitmap word and bit come from the id
+// (a bit-field extract and the id's low five bits) without the window
+// origin subtracted first.
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int bucket,
                                                               int64_t maxV) {
   constexpr int NW = THREADS / kWave;
   constexpr int B = 4;  // chunks per batch
   constexpr int kBatchPins = B * kWave;
-  constexpr uint32_t kWinIds = 1u << 19;
+  constexpr uint32_t kWinIds = 1u << 19;       // ids the bitmap holds
   constexpr int kWords = (int)(kWinIds / 32);
+  // the widest window: from any lo, its ids fall in kWords words
+  constexpr int64_t kWinMax = (int64_t)kWinIds - 32;
   constexpr int kList = 4096;         // repeat visits of a window
   constexpr int kSeg = kList / NW;    // a wave's part of them
   constexpr int kScores = 4096;       // repeated ids of a window
@@ -737,16 +745,16 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
   // hyperedges and the bitmap come first, so that their offsets fit the
   // immediate field of the LDS instructions of the sweeps.
   struct Lds {
-    // The hyperedges that have batches in the current sweep (one extra
-    // entry: c_pre there holds the number of batches).
-    int32_t c_pre[kWinDeg + 1];    // batches before the hyperedge
-    // the hyperedge j (bits 0-9) and, in sweep 1, whether its slice may run
-    // on past its batches (bit 31)
-    int32_t c_list[kWinDeg + 1];
-    // the first pin of its slice less c_pre * kBatchPins (modulo 2^32), so
-    // that batch b starts at pin c_base + b * kBatchPins
-    uint32_t c_base[kWinDeg + 1];
-    uint32_t c_end[kWinDeg + 1];   // the pin after the last its batches cover
+    // The hyperedges that have batches in the current sweep, one 16-byte
+    // entry each, read by a lane in one LDS access (one extra entry: its x
+    // holds the number of batches):
+    //   x  batches before the hyperedge
+    //   y  the hyperedge j (bits 0-9) and, in sweep 1, whether its slice may
+    //      run on past its batches (bit 31)
+    //   z  the first pin of its slice less x * kBatchPins (modulo 2^32), so
+    //      that batch b starts at pin z + b * kBatchPins
+    //   w  the pin after the last its batches cover
+    uint4 c_ent[kWinDeg + 1];
     alignas(16) uint32_t seen[kWords];
     // the ids of sweep 1's repeat visits, wave w's from w * kSeg on (plus a
     // slot per lane that takes no visit); they stay for the final fold
@@ -779,10 +787,11 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
 #pragma unroll
   for (int i = 0; i < 4; ++i) seen4[4 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
   // What the last completed window left in the bitmap: the words of the
-  // wave's repeat visits (ids relative to prev_lo) and of n (prev_nword,
-  // -1 for none).  They are cleared at the next window's start.
+  // wave's repeat visits (the bitmap starting at word prev_lw of the ids)
+  // and of n (prev_nword, -1 for none).  They are cleared at the next
+  // window's start.
   int32_t prev_wcnt = 0, prev_nword = -1;
-  uint32_t prev_lo = 0;
+  uint32_t prev_lw = 0;
   // byte offset of the lane's pin in each chunk of a batch
   uint32_t lofs[B];
 #pragma unroll
@@ -829,7 +838,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     block_min_max_i64<THREADS>(mn, mx, (int64_t*)S.red);  // also orders the staging
     const int64_t hi_all = mx + 1;
     int64_t lo = mn;
-    int64_t width = hi_all - lo < (int64_t)kWinIds ? hi_all - lo : (int64_t)kWinIds;
+    int64_t width = hi_all - lo < kWinMax ? hi_all - lo : kWinMax;
     int passes = 0;
 
     // Lists the hyperedges with batches: thread j looks at hyperedge j and
@@ -840,10 +849,9 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
                           int32_t pb) {
       if (nb > 0) {
         const int64_t cover = (int64_t)nb * kWave;
-        S.c_list[pc] = tid | (ro ? (int32_t)0x80000000 : 0);
-        S.c_pre[pc] = pb;
-        S.c_base[pc] = base - (uint32_t)pb * (uint32_t)kBatchPins;
-        S.c_end[pc] = base + (uint32_t)(r < cover ? r : cover);
+        S.c_ent[pc] = make_uint4((uint32_t)pb, (uint32_t)tid | (ro ? 0x80000000u : 0u),
+                                 base - (uint32_t)pb * (uint32_t)kBatchPins,
+                                 base + (uint32_t)(r < cover ? r : cover));
       }
     };
 
@@ -877,8 +885,9 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         // form a prefix, and it lies within NW entries of ci.  Every lane
         // reads its entry, and the chosen one is taken with readlane.
         const int32_t idx = ci + lane < nc ? ci + lane : nc;
-        const int32_t pre_l = S.c_pre[idx], e_l = S.c_list[idx];
-        const uint32_t base_l = S.c_base[idx], end_l = S.c_end[idx];
+        const uint4 ent = S.c_ent[idx];
+        const int32_t pre_l = (int32_t)ent.x, e_l = (int32_t)ent.y;
+        const uint32_t base_l = ent.z, end_l = ent.w;
         const uint64_t m = ballot(pre_l <= bnext);
         const int32_t sel = (int32_t)__popcll(m) - 1;
         ci += sel;
@@ -897,8 +906,6 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         if (!sweep1) wt = (uint32_t)S.m_w[j];
         bnext += NW;
       }
-      // the fields are wave-uniform; say so, so that the tests on them stay
-      // scalar
       t.base = rfl_u32(base);
       t.lim = rfl_i32(lim);
       t.j = rfl_i32(j);
@@ -914,11 +921,18 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         const uint32_t off = lofs[u] < last4 ? lofs[u] : last4;
         pin[u] = *reinterpret_cast<const uint32_t*>(p + off);
       }
+      // the batch's loads leave before any work on the previous batch
+      __builtin_amdgcn_sched_barrier(0);
     };
 
     while (lo < hi_all) {
       const int64_t hi = lo + width < hi_all ? lo + width : hi_all;
       const uint32_t lo32 = (uint32_t)lo, hi32 = (uint32_t)hi;  // ids are below 2^31
+      const uint32_t lw = lo32 >> 5;  // the ids' word at the bitmap's start
+      // the bitmap indexed by an id's word (id / 32) itself, and the lane's
+      // own word in that indexing
+      uint32_t* const seenw = S.seen - lw;
+      const uint32_t lane_w = (uint32_t)lane + lw;
       __syncthreads();  // previous window folded, flags read, cursors committed
       if (++passes > kMaxPasses) {
         if (tid == 0) atomicOr(a.err, kErrPassLimit);
@@ -954,11 +968,11 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         nc = t3[0];
         tb = t3[1];
         list_write(nb, nb < full, base, r, p3[0], p3[1]);
-        if (tid == 0) S.c_pre[nc] = tb;
+        if (tid == 0) S.c_ent[nc].x = (uint32_t)tb;
       }
       // the bitmap starts empty: the last window left only its repeated ids
       for (int o = lane; o < prev_wcnt; o += kWave)
-        S.seen[(S.lst[wid * kSeg + o] - prev_lo) >> 5] = 0;
+        S.seen[(S.lst[wid * kSeg + o] >> 5) - prev_lw] = 0;
       if (tid == 0 && prev_nword >= 0) S.seen[prev_nword] = 0;
       prev_wcnt = 0;
       prev_nword = -1;
@@ -982,23 +996,25 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         for (int u = 0; u < B; ++u) {
           id[u] = pin[u] & kIdMask;
           const bool in = (lofs[u] < lim4) & (id[u] < hi32);  // ids >= lo: cursor order
-          const uint32_t rel = id[u] - lo32;
-          const uint32_t word = in ? rel >> 5 : (uint32_t)lane;
-          bit[u] = in ? 1u << (rel & 31) : 0u;
-          old[u] = atomicOr(&S.seen[word], bit[u]);
+          const uint32_t word = in ? id[u] >> 5 : lane_w;
+          bit[u] = in ? 1u << (id[u] & 31) : 0u;
+          old[u] = atomicOr(&seenw[word], bit[u]);
         }
-        // the pins below the window end (a lane has a bit iff it has one),
+        // the pins below the window end: the batch's pins ascend and the
+        // lanes past it hold its last live pin, so the lanes below the end
+        // are its first cnt pins, or all lanes when cnt is the batch's size;
         // and the repeat visits
         bool rep[B];
         uint64_t rb[B];
         int32_t nr = 0, cnt = 0;
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-          cnt += (int32_t)__popcll(ballot(bit[u] != 0));
+          cnt += (int32_t)__popcll(ballot(id[u] < hi32));
           rep[u] = (old[u] & bit[u]) != 0;
           rb[u] = ballot(rep[u]);
           nr += (int32_t)__popcll(rb[u]);
         }
+        cnt = cnt < t.lim ? cnt : t.lim;
         if (nr > 0 && !over) {  // wave-uniform (most batches hold a few)
           if (wcnt + nr > kSeg) {
             over = true;
@@ -1084,11 +1100,11 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       }
       __syncthreads();  // bitmap cleared
       for (int o = lane; o < wcnt; o += kWave) {
-        const uint32_t rel = S.lst[wid * kSeg + o] - lo32;
-        atomicOr(&S.seen[rel >> 5], 1u << (rel & 31));
+        const uint32_t id = S.lst[wid * kSeg + o];
+        atomicOr(&S.seen[(id >> 5) - lw], 1u << (id & 31));
       }
       const bool n_in = n >= lo32 && n < hi32;  // block-uniform
-      if (tid == 0 && n_in) atomicOr(&S.seen[(n - lo32) >> 5], 1u << ((n - lo32) & 31));
+      if (tid == 0 && n_in) atomicOr(&S.seen[(n >> 5) - lw], 1u << (n & 31));
       __syncthreads();  // repeated ids marked
       int32_t nrank = 0;  // repeated ids of the window
       {
@@ -1105,7 +1121,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         tb = t3[1];
         nrank = t3[2];
         list_write(nb2, false, base2, r2, p3[0], p3[1]);
-        if (tid == 0) S.c_pre[nc] = tb;
+        if (tid == 0) S.c_ent[nc].x = (uint32_t)tb;
         uint32_t run = (uint32_t)p3[2], pk[8];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -1148,7 +1164,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         for (int u = 0; u < B; ++u) {
           id[u] = pin[u] & kIdMask;
           act[u] = lofs[u] < lim4;  // n is marked repeated: never a single
-          w[u] = S.seen[(id[u] - lo32) >> 5];
+          w[u] = seenw[id[u] >> 5];
         }
         bool anyadd = false;
         if (decltype(allv)::value) {
@@ -1157,7 +1173,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
           uint32_t mid = kSent;
 #pragma unroll
           for (int u = 0; u < B; ++u) {
-            rep[u] = ((w[u] >> ((id[u] - lo32) & 31)) & 1u) != 0;
+            rep[u] = __builtin_amdgcn_ubfe(w[u], id[u], 1u) != 0;  // (bit id % 32)
             const bool single = act[u] & !rep[u];
             mid = single && id[u] < mid ? id[u] : mid;
             anyadd |= act[u] & rep[u];
@@ -1167,7 +1183,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         } else {
 #pragma unroll
           for (int u = 0; u < B; ++u) {
-            rep[u] = ((w[u] >> ((id[u] - lo32) & 31)) & 1u) != 0;
+            rep[u] = __builtin_amdgcn_ubfe(w[u], id[u], 1u) != 0;  // (bit id % 32)
             const uint64_t key = ((uint64_t)t.wt << 32) | (uint64_t)(kSent - id[u]);
             bool better = act[u] & !rep[u] & (key > best);
             if (ballot(better) != 0) {  // wave-uniform
@@ -1181,9 +1197,8 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
 #pragma unroll
           for (int u = 0; u < B; ++u) {
             if (act[u] & rep[u]) {
-              const uint32_t rel = id[u] - lo32;
-              const uint32_t rank = (uint32_t)S.wpre[rel >> 5] +
-                                    (uint32_t)__popc(w[u] & ((1u << (rel & 31)) - 1u));
+              const uint32_t rank = (uint32_t)S.wpre[(id[u] >> 5) - lw] +
+                                    (uint32_t)__popc(w[u] & ((1u << (id[u] & 31)) - 1u));
               atomicAdd(&S.sc[rank], t.wt);
             }
           }
@@ -1213,10 +1228,10 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       // candidate of its own.
       for (int o = lane; o < wcnt; o += kWave) {
         const uint32_t id = S.lst[wid * kSeg + o];
-        const uint32_t rel = id - lo32;
-        const uint32_t w = S.seen[rel >> 5];
+        const uint32_t word = (id >> 5) - lw;
+        const uint32_t w = S.seen[word];
         const uint32_t rank =
-            (uint32_t)S.wpre[rel >> 5] + (uint32_t)__popc(w & ((1u << (rel & 31)) - 1u));
+            (uint32_t)S.wpre[word] + (uint32_t)__popc(w & ((1u << (id & 31)) - 1u));
         const uint64_t key = ((uint64_t)S.sc[rank] << 32) | (uint64_t)(kSent - id);
         if (id != n && key > best && (v.all_valid || merge_valid(a, v, id, 0))) best = key;
       }
@@ -1226,12 +1241,12 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         S.m_rem[tid] -= c;
       }
       prev_wcnt = wcnt;
-      prev_lo = lo32;
-      prev_nword = n_in ? (int32_t)((n - lo32) >> 5) : -1;
+      prev_lw = lw;
+      prev_nword = n_in ? (int32_t)((n >> 5) - lw) : -1;
       lo = hi;
-      if (nrep < kList / 4 && width < (int64_t)kWinIds) {
+      if (nrep < kList / 4 && width < kWinMax) {
         width *= 2;
-        if (width > (int64_t)kWinIds) width = kWinIds;
+        if (width > kWinMax) width = kWinMax;
       }
     }
     best = block_max_u64<THREADS>(best, S.red);
