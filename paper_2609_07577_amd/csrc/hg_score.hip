@@ -698,9 +698,11 @@ __device__ inline void block_scan3(const int32_t (&x)[3], int32_t (&px)[3], int3
 // scores, is abandoned and retried at half the width.
 //
 // Work balance: hyperedge sizes follow a heavy-tailed law, so each sweep cuts
-// the vertex's slices into batches of B chunks (64 pins each), numbers the
-// batches of all hyperedges in a row, and deals them to the waves round
-// robin.  A 16-byte list entry per hyperedge with batches holds its first
+// the vertex's slices into batches of B chunks (64 pins each) and numbers
+// the batches of all hyperedges in a row; each wave starts on the batch of
+// its own number and claims its next one from a counter in LDS, a fetch
+// ahead (waves of one CU do not progress at one rate, and a fixed deal
+// left the faster ones idle at the sweep's end).  A 16-byte list entry per hyperedge with batches holds its first
 // batch number, the hyperedge, a virtual base and the end of the pins its
 // batches cover, so a wave finds its next batch with one 16-byte LDS read
 // per lane, a ballot and a few readlanes, and the batch's start and pin
@@ -771,6 +773,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     int32_t ws[3 * NW];
     uint64_t red[2 * NW];
     int32_t s_item;
+    int32_t s_next;                // the next batch of the sweep no wave holds
   };
   __shared__ Lds S;
 
@@ -865,6 +868,10 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     };
     int32_t nc = 0, tb = 0;  // listed hyperedges, batches of the current sweep
     int32_t bnext = 0, ci = 0;
+    // The waves take batches as they go: each claims its next batch from
+    // s_next one fetch ahead (the claim in lane 0 of bclaim), so that a wave
+    // held up on one batch leaves the rest to the others.
+    int32_t bclaim = 0;
     bool has_cont = false;
     int32_t cont_j = 0, cont_rem = 0;  // a continuation: hyperedge, pins left
     uint32_t cont_base = 0;            // and its first pin
@@ -873,22 +880,35 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     auto fetch = [&](Batch& t, uint32_t (&pin)[B], bool sweep1) {
       uint32_t base = 0, wt = 0;
       int32_t lim = 0, j = deg, rem = 0;
+      bool took = false;  // a claimed batch taken: claim the next
       if (sweep1 && has_cont) {  // wave-uniform
         has_cont = false;
         j = cont_j;
         base = cont_base;
         lim = cont_rem < kBatchPins ? cont_rem : kBatchPins;
         rem = cont_rem - lim;
-      } else if (bnext < tb) {  // wave-uniform
+      } else if ((bnext = __builtin_amdgcn_readlane(bclaim, 0)) < tb) {  // wave-uniform
         // The last listed hyperedge (from ci on) whose first batch is at most
         // bnext: the entries are strictly increasing, so the lanes that pass
-        // form a prefix, and it lies within NW entries of ci.  Every lane
-        // reads its entry, and the chosen one is taken with readlane.
-        const int32_t idx = ci + lane < nc ? ci + lane : nc;
-        const uint4 ent = S.c_ent[idx];
-        const int32_t pre_l = (int32_t)ent.x, e_l = (int32_t)ent.y;
+        // form a prefix, the lane at ci always among them.  Every lane reads
+        // its entry, and the chosen one is taken with readlane; when all 64
+        // pass, the search moves on by 63 entries (the extra entry at nc
+        // holds tb, which no batch reaches, so it ends).
+        // (the whole entry is read at once: left to itself the compiler
+        // reads the other fields only after the search, a second round trip)
+        int32_t idx = ci + lane < nc ? ci + lane : nc;
+        uint4 ent = S.c_ent[idx];
+        asm volatile("" : "+v"(ent.x), "+v"(ent.y), "+v"(ent.z), "+v"(ent.w));
+        uint64_t m = ballot((int32_t)ent.x <= bnext);
+        while (m == ~0ull) {
+          ci += kWave - 1;
+          idx = ci + lane < nc ? ci + lane : nc;
+          ent = S.c_ent[idx];
+          asm volatile("" : "+v"(ent.x), "+v"(ent.y), "+v"(ent.z), "+v"(ent.w));
+          m = ballot((int32_t)ent.x <= bnext);
+        }
+        const int32_t e_l = (int32_t)ent.y;
         const uint32_t base_l = ent.z, end_l = ent.w;
-        const uint64_t m = ballot(pre_l <= bnext);
         const int32_t sel = (int32_t)__popcll(m) - 1;
         ci += sel;
         const int32_t e = __builtin_amdgcn_readlane(e_l, sel);
@@ -904,7 +924,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         if (sweep1 && e < 0 && left <= (uint32_t)kBatchPins)
           rem = (int32_t)(S.m_base[j] + (uint32_t)S.m_rem[j] - end);
         if (!sweep1) wt = (uint32_t)S.m_w[j];
-        bnext += NW;
+        took = true;
       }
       t.base = rfl_u32(base);
       t.lim = rfl_i32(lim);
@@ -920,6 +940,11 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       for (int u = 0; u < B; ++u) {
         const uint32_t off = lofs[u] < last4 ? lofs[u] : last4;
         pin[u] = *reinterpret_cast<const uint32_t*>(p + off);
+      }
+      if (took) {  // wave-uniform; after the loads, so that they leave first
+        int32_t c = 0;
+        if (lane == 0) c = atomicAdd(&S.s_next, 1);
+        bclaim = c;
       }
       // the batch's loads leave before any work on the previous batch
       __builtin_amdgcn_sched_barrier(0);
@@ -968,7 +993,10 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         nc = t3[0];
         tb = t3[1];
         list_write(nb, nb < full, base, r, p3[0], p3[1]);
-        if (tid == 0) S.c_ent[nc].x = (uint32_t)tb;
+        if (tid == 0) {
+          S.c_ent[nc].x = (uint32_t)tb;
+          S.s_next = NW;  // batches 0 .. NW - 1: one for each wave to start
+        }
       }
       // the bitmap starts empty: the last window left only its repeated ids
       for (int o = lane; o < prev_wcnt; o += kWave)
@@ -977,7 +1005,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
       prev_wcnt = 0;
       prev_nword = -1;
       __syncthreads();
-      bnext = wid;
+      bclaim = wid;
       ci = 0;
       has_cont = false;
 
@@ -1121,7 +1149,10 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         tb = t3[1];
         nrank = t3[2];
         list_write(nb2, false, base2, r2, p3[0], p3[1]);
-        if (tid == 0) S.c_ent[nc].x = (uint32_t)tb;
+        if (tid == 0) {
+          S.c_ent[nc].x = (uint32_t)tb;
+          S.s_next = NW;  // batches 0 .. NW - 1: one for each wave to start
+        }
         uint32_t run = (uint32_t)p3[2], pk[8];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -1142,7 +1173,7 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
           for (int i = tid; i < nrank; i += THREADS) S.sc[i] = 0;
         }
       }
-      bnext = wid;
+      bclaim = wid;
       ci = 0;
       __syncthreads();  // list of batches, bitmap, ranks and scores ready
 
