@@ -687,7 +687,9 @@ __device__ inline void block_scan3(const int32_t (&x)[3], int32_t (&px)[3], int3
 //     it in the window);
 //   sweep 2 visits the same pins again: a repeated id adds the hyperedge
 //     weight to the score at its rank, any other id has its complete score
-//     and is compared with the lane's best;
+//     and is compared with the lane's best (when no merge of n can break a
+//     limit, a batch lighter than one in which the wave already scored such
+//     an id is not compared: it cannot hold the vertex's best);
 //   the fold: each repeat visit names a repeated id, whose score (at its
 //     rank) is compared with the lane's best (validity tested only for
 //     those that beat it; n is left out), and the cursors move past the
@@ -825,6 +827,10 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
     const uint32_t n = (uint32_t)v.n;
     const int32_t deg = (int32_t)v.deg;  // 1 .. kWinDeg
     uint64_t best = 0;
+    // the heaviest batch in which the wave has scored a single (sweep 2,
+    // no merge of n invalid): the block's best key is at least sw << 32,
+    // so a lighter batch holds no single that could win
+    uint32_t sw = 0;
 
     int64_t mn = INT64_MAX, mx = -1;
     for (int j = tid; j < deg; j += THREADS) {
@@ -1199,18 +1205,24 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
         }
         bool anyadd = false;
         if (decltype(allv)::value) {
-          // every single scores the batch's weight: the best of them is the
-          // smallest id
-          uint32_t mid = kSent;
 #pragma unroll
           for (int u = 0; u < B; ++u) {
             rep[u] = __builtin_amdgcn_ubfe(w[u], id[u], 1u) != 0;  // (bit id % 32)
-            const bool single = act[u] & !rep[u];
-            mid = single && id[u] < mid ? id[u] : mid;
             anyadd |= act[u] & rep[u];
           }
-          const uint64_t key = ((uint64_t)t.wt << 32) | (uint64_t)(kSent - mid);
-          best = mid != kSent && key > best ? key : best;
+          if (t.wt >= sw) {  // wave-uniform
+            // every single scores the batch's weight: the best of them is
+            // the smallest id
+            uint32_t mid = kSent;
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+              const bool single = act[u] & !rep[u];
+              mid = single && id[u] < mid ? id[u] : mid;
+            }
+            const uint64_t key = ((uint64_t)t.wt << 32) | (uint64_t)(kSent - mid);
+            best = mid != kSent && key > best ? key : best;
+            if (ballot(mid != kSent) != 0) sw = t.wt;
+          }
         } else {
 #pragma unroll
           for (int u = 0; u < B; ++u) {
