@@ -367,3 +367,24 @@ def test_window_degree_limit(ctx):
     wb = set(_window_bucket_vertices(g).tolist())
     assert 0 in wb and 1 not in wb
     run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
+
+
+@pytest.mark.parametrize("weights", [(1,), (1, 2)], ids=["equal", "two-valued"])
+def test_window_weight_ties(ctx, weights):
+    """Large neighbourhoods whose hyperedges share few weight values: 1250
+    axons of 400 random targets over 20,000 neurons (about 25 axons reach
+    each neuron, 16,000 of which are scored in windows), weights all 1 or
+    drawn from {1, 2}.  Most neighbours share one hyperedge with n, so the
+    best single of a vertex is decided among many batches of equal weight
+    by the smallest id (Eq. 12 scores, lowest id on ties), across waves
+    and windows; the levels must be the oracle's."""
+    rng = np.random.default_rng(11)
+    n, na = 20_000, 1250
+    axons = []
+    for src in range(na):
+        t = rng.choice(n - 1, size=400, replace=False)
+        t = t + (t >= src)  # any neuron but the source
+        axons.append((src, sorted(int(x) for x in t), int(rng.choice(weights))))
+    g = synth.from_axons(n, axons)
+    assert len(_window_bucket_vertices(g)) >= 15_000
+    run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=3, verbose=True)
