@@ -34,6 +34,17 @@
  * only its scratch arena, grown on demand and freed by hg_destroy.  A context
  * must not be used from two host threads at once.  No call throws; each
  * returns an hg_status and hg_last_error() holds a message.
+ *
+ * Environment, read by hg_create for the context it creates:
+ *   HG_VALIDATE=1        hg_coarsen_level, hg_contract and hg_connectivity
+ *                        first run hg_validate_level on their input level
+ *                        (synchronously) and return its status
+ *   HG_SCRATCH_CAP=B     the scratch arena never grows above B bytes; a call
+ *                        that needs more fails with HG_ERR_NO_MEMORY
+ *   HG_TEST_FP_BITS=n    (tests only) keeps n bits of the fingerprints that
+ *                        group identical coarse hyperedges, so that unequal
+ *                        lists share fingerprints and the exact comparison of
+ *                        such collisions is exercised; results are unchanged
  */
 #ifndef HG_H_
 #define HG_H_
@@ -161,6 +172,10 @@ int hg_init_state(hg_ctx* ctx, int32_t n_vertices, int32_t n_edges, int64_t n_pi
 int hg_coarsen_level(hg_ctx* ctx, const hg_level* in, const hg_limits* limits,
                      int32_t* cand, int32_t* cscore, int32_t* match, int32_t* vmap,
                      int32_t* n_coarse, int32_t* any_candidate);
+/* Input weights are checked on the device before the scores: a weight below
+ * 1 makes the next hg_sync return HG_ERR_INVALID_LEVEL, weights summing to
+ * 2^31 or more HG_ERR_OVERFLOW (scores are exact int32 sums); the outputs of
+ * the call are then undefined.  hg_contract runs the same check. */
 
 /*
  * Contraction G -> G_P for any vertex map (Section 3, "Partitioning
@@ -262,6 +277,17 @@ int hg_batch_result(hg_batch* batch, int32_t slot, int32_t* part, int32_t* n_par
                     int32_t* n_levels);
 int hg_batch_compact(hg_batch* batch);
 int hg_batch_sizes(hg_batch* batch, int64_t* sizes);
+
+/*
+ * Census of the score step (Eq. 12) of the most recent hg_coarsen_level on
+ * the context (synchronous): out[k] = vertices scored by work list k and
+ * out[8 + k] = their neighbour visits (sum over incident hyperedges of the
+ * hyperedge's size less one), for the 8 lists of the bucket rule described
+ * at hg_tuning: single pass in the small table, single pass in the big
+ * table, windows, passes over a table; lists 4-7 the same where the
+ * distinct-axon overlap of Section 3 can bind.  `out` is host int64[16].
+ */
+int hg_score_census(hg_ctx* ctx, int64_t* out);
 
 /*
  * Synchronous structural check of a level: offsets non-decreasing and within

@@ -1,4 +1,6 @@
 // C ABI entry points: context, scratch arena, argument checks, dispatch.
+#include <stdlib.h>
+
 #include <new>
 
 #include "hg_host.h"
@@ -42,6 +44,48 @@ __global__ void validate_kernel(LevelView L, int64_t V, int64_t E, int64_t P,
     if (L.size && (L.size[v] < 1)) atomicOr(bad, 8);
     if (L.syn && L.syn[v] < 0) atomicOr(bad, 8);
     if (L.ax && L.ax[v] < 0) atomicOr(bad, 8);
+  }
+}
+
+// Weights of a level (Section 2 model: spike rates, integers >= 1 here) and
+// their sum, which must stay below 2^31 so that every score and every merged
+// weight fits an int32 (the score step packs scores next to ids).  Runs on
+// the device before the scores; a violation is recorded in the error word
+// and reported by hg_sync.
+__global__ void weight_check_kernel(const Dims* __restrict__ d, const int32_t* __restrict__ w,
+                                    unsigned long long* __restrict__ wsum,
+                                    int32_t* __restrict__ err) {
+  const int64_t E = d->E;
+  const int lane = threadIdx.x & (kWave - 1);
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long acc = 0;
+  bool bad = false;
+  for (; i < E; i += stride) {
+    const int32_t x = w[i];
+    bad |= x < 1;
+    acc += (unsigned long long)(x > 0 ? x : 0);
+  }
+#pragma unroll
+  for (int k = kWave / 2; k > 0; k >>= 1) acc += __shfl_xor(acc, k, kWave);
+  if (lane == 0 && acc) atomicAdd(wsum, acc);
+  if (bad) atomicOr(err, kErrWeight);
+}
+
+__global__ void weight_sum_kernel(unsigned long long* __restrict__ wsum,
+                                  int32_t* __restrict__ err) {
+  if (*wsum >= (1ull << 31)) atomicOr(err, kErrWeightSum);
+  *wsum = 0;
+}
+
+// Keeps the score step's census (vertices and neighbour visits per work
+// list) of the last level in the context's own memory.
+__global__ void census_kernel(const int32_t* __restrict__ count,
+                              const int64_t* __restrict__ visits, int64_t* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k < kNumBuckets) {
+    out[k] = count[k];
+    out[kNumBuckets + k] = visits[k];
   }
 }
 
@@ -92,13 +136,25 @@ int hg_create(int device, void* hip_stream, hg_ctx** out) {
   if (!c) return HG_ERR_NO_MEMORY;
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  if (const char* v = getenv("HG_VALIDATE")) c->validate = atoi(v) != 0;
+  if (const char* v = getenv("HG_SCRATCH_CAP")) c->scratch_cap = (size_t)strtoull(v, nullptr, 10);
+  if (const char* v = getenv("HG_TEST_FP_BITS")) {
+    const int bits = atoi(v);
+    if (bits >= 1 && bits < 64) c->fp_mask = (1ull << bits) - 1;
+  }
   hipError_t e = hipSetDevice(device);
-  if (e == hipSuccess) e = hipMalloc((void**)&c->dev_err, 256);
+  char* blk = nullptr;
+  if (e == hipSuccess) e = hipMalloc((void**)&blk, 1024);
   if (e != hipSuccess) {
     delete c;
     return HG_ERR_HIP;
   }
+  c->dev_err = reinterpret_cast<int32_t*>(blk);
+  c->dev_wsum = reinterpret_cast<unsigned long long*>(blk + 64);
+  c->dev_census = reinterpret_cast<int64_t*>(blk + 128);
   fill_i32(c->dev_err, 0, 1, c->stream);
+  fill_u64((uint64_t*)c->dev_wsum, 0, 1, c->stream);
+  fill_i64(c->dev_census, 0, 2 * kNumBuckets, c->stream);
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     (void)hipFree(c->dev_err);
@@ -145,6 +201,16 @@ int hg_sync(hg_ctx* c) {
       return fail(c, HG_ERR_INVALID_ARG,
                   "a vmap or part value, or n_coarse, was outside its range; the outputs of "
                   "that call are undefined (flags 0x%x)",
+                  flags);
+    if (flags & kErrWeight)
+      return fail(c, HG_ERR_INVALID_LEVEL,
+                  "a hyperedge weight below 1; the outputs of that call are undefined "
+                  "(flags 0x%x)",
+                  flags);
+    if (flags & kErrWeightSum)
+      return fail(c, HG_ERR_OVERFLOW,
+                  "the hyperedge weights of a level sum to 2^31 or more; the outputs of that "
+                  "call are undefined (flags 0x%x)",
                   flags);
     return fail(c, HG_ERR_INTERNAL,
                 "a kernel reached an internal bound (flags 0x%x: 1 score table, 2 passes, "
@@ -231,6 +297,7 @@ int hg_coarsen_level(hg_ctx* c, const hg_level* in, const hg_limits* lim, int32_
     return fail(c, HG_ERR_INVALID_ARG, "bad limits");
   if ((in->n_vertices > 0 && (!match || !vmap)) || !n_coarse || !any_candidate)
     return fail(c, HG_ERR_INVALID_ARG, "null output");
+  if (c->validate && (rc = hg_validate_level(c, in)) != HG_OK) return rc;
   const int64_t V = in->n_vertices, E = in->n_edges, P = in->n_pins;
   Sizer sz;
   CoarsenScratch<Sizer> ls;
@@ -246,9 +313,13 @@ int hg_coarsen_level(hg_ctx* c, const hg_level* in, const hg_limits* lim, int32_
   LevelView L = view_of(in, S.dims);
   // S0, S1
   mark(c, 0, 0);
+  weight_check_kernel<<<grid_for(E, 256 * 8, 1024), 256, 0, s>>>(S.dims, in->edge_weight,
+                                                                  c->dev_wsum, c->dev_err);
+  weight_sum_kernel<<<1, 1, 0, s>>>(c->dev_wsum, c->dev_err);
   build_incidence(L, V, E, P, S.vcount, S.voff, S.vinc, S.partials, s);
-  Buckets b{S.bcount, S.blist};
+  Buckets b{S.bcount, S.blist, S.bvisits};
   expansion_and_buckets(L, S.voff, S.vinc, V, S.xn, S.gc, 1, b, c->tuning, s);
+  census_kernel<<<1, 64, 0, s>>>(S.bcount, S.bvisits, c->dev_census);
   mark(c, 0, 1);
   // S2
   int32_t* cd = cand ? cand : S.cand;
@@ -281,6 +352,7 @@ int hg_contract(hg_ctx* c, const hg_level* in, const int32_t* vmap, const int32_
   if (out->cap_vertices < V || out->cap_edges < E || out->cap_pins < P)
     return fail(c, HG_ERR_CAPACITY, "output capacities (%d, %d, %lld) below input sizes",
                 out->cap_vertices, out->cap_edges, (long long)out->cap_pins);
+  if (c->validate && (rc = hg_validate_level(c, in)) != HG_OK) return rc;
   Sizer sz;
   ContractLayout<Sizer> ls;
   ls.carve(sz, V, E, P);
@@ -297,7 +369,11 @@ int hg_contract(hg_ctx* c, const hg_level* in, const int32_t* vmap, const int32_
   set_dims(S.dims, V, E, P, s);
   LevelView L = view_of(in, S.dims);
   S.cs.err = c->dev_err;
+  S.cs.fp_mask = c->fp_mask;
   mark(c, 3, 0);
+  weight_check_kernel<<<grid_for(E, 256 * 8, 1024), 256, 0, s>>>(S.dims, in->edge_weight,
+                                                                  c->dev_wsum, c->dev_err);
+  weight_sum_kernel<<<1, 1, 0, s>>>(c->dev_wsum, c->dev_err);
   check_map_kernel<<<grid_for(V, 256, 4096), 256, 0, s>>>(vmap, V, n_coarse, map, nc,
                                                         c->dev_err);
   contract_level(L, V, E, P, map, nc, out, S.cs, s);
@@ -310,6 +386,7 @@ int hg_connectivity(hg_ctx* c, const hg_level* lvl, const int32_t* part, int64_t
   int rc = check_level(c, lvl, false);
   if (rc) return rc;
   if ((lvl->n_vertices > 0 && !part) || !conn) return fail(c, HG_ERR_INVALID_ARG, "null argument");
+  if (c->validate && (rc = hg_validate_level(c, lvl)) != HG_OK) return rc;
   const int64_t V = lvl->n_vertices, E = lvl->n_edges, P = lvl->n_pins;
   Sizer sz;
   ConnLayout<Sizer> ls;
@@ -331,6 +408,15 @@ int hg_connectivity(hg_ctx* c, const hg_level* lvl, const int32_t* part, int64_t
   connectivity(L, E, V, map, conn, S.cs, s);
   mark(c, 4, 1);
   return launch_status(c);
+}
+
+int hg_score_census(hg_ctx* c, int64_t* out) {
+  if (!c || !out) return HG_ERR_INVALID_ARG;
+  hipError_t e = hipMemcpyAsync(out, c->dev_census, 2 * kNumBuckets * sizeof(int64_t),
+                                hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "census read-back");
+  return HG_OK;
 }
 
 int hg_validate_level(hg_ctx* c, const hg_level* L) {

@@ -431,7 +431,7 @@ void level_step(hg_batch* b, int from, int to) {
   auto& S = b->cs;
   LevelView L{F.dims, F.eoff, F.pins, F.w, F.mult, F.size, F.syn, F.ax, F.gid};
   build_incidence(L, V, E, P, S.vcount, S.voff, S.vinc, S.partials, s);
-  Buckets bk{S.bcount, S.blist};
+  Buckets bk{S.bcount, S.blist, S.bvisits};
   expansion_and_buckets(L, S.voff, S.vinc, V, S.xn, b->gc, b->max_graphs, bk, c->tuning, s);
   ScoreArgs sa{L,  S.voff, S.vinc, S.xn,      b->gc, S.cursor,         b->cand,
                b->cscore, S.work, bk, c->dev_err, c->tuning.fill16};
@@ -445,6 +445,7 @@ void level_step(hg_batch* b, int from, int to) {
   hg_level_out out{(int32_t)V, (int32_t)E, P,    T.eoff, T.pins, T.w,
                    T.mult,     T.size,     T.syn, T.ax,   reinterpret_cast<int64_t*>(T.dims)};
   b->ks.cs.err = c->dev_err;
+  b->ks.cs.fp_mask = c->fp_mask;
   contract_level(L, V, E, P, b->vmap, b->n_coarse, &out, b->ks.cs, s);
   gid_kernel<<<blocks_for(V), 256, 0, s>>>(F.dims, b->vmap, F.gid, T.gid);
   compose_kernel<<<blocks_for(V), 256, 0, s>>>(b->pool_n, b->owner, b->vmap, b->part);

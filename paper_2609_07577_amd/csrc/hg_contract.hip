@@ -119,6 +119,7 @@ struct S6Args {
   const int32_t* n_coarse;
   int32_t* err;
   int64_t max_items;
+  uint64_t fp_mask;  // fingerprint bits kept (all of them outside tests)
 };
 
 __device__ inline void emit_pin(const S6Args& a, int64_t e, int64_t pos, uint32_t pin,
@@ -170,7 +171,7 @@ __global__ void s6_small_kernel(S6Args a) {
     h = wave_sum(h);
     // every lane stores the same values (no lane-only code in this loop)
     a.tlen[e] = n_out;
-    a.fp[e] = (h + mix64(0x5151ull + (uint64_t)n_out)) | 1ull;
+    a.fp[e] = ((h + mix64(0x5151ull + (uint64_t)n_out)) & a.fp_mask) | 1ull;
   }
 }
 
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(kBlockThreads) void s6_block_kernel(S6Args a) {
     h = block_sum_u64(h, red);
     if (tid == 0) {
       a.tlen[e] = total;
-      a.fp[e] = (h + mix64(0x5151ull + (uint64_t)total)) | 1ull;
+      a.fp[e] = ((h + mix64(0x5151ull + (uint64_t)total)) & a.fp_mask) | 1ull;
     }
   }
 }
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(kBlockThreads) void s6_huge_kernel(S6Args a) {
     h = block_sum_u64(h, red);
     if (tid == 0) {
       a.tlen[e] = (int32_t)base;
-      a.fp[e] = (h + mix64(0x5151ull + (uint64_t)base)) | 1ull;
+      a.fp[e] = ((h + mix64(0x5151ull + (uint64_t)base)) & a.fp_mask) | 1ull;
     }
   }
 }
@@ -544,7 +545,7 @@ int contract_level(const LevelView& L, int64_t maxV, int64_t maxE, int64_t maxP,
   fill_i32(cs.work, 0, 4, s);
   classify_edges_kernel<<<gridE, 256, 0, s>>>(L.dims, L.eoff, cs.ebucket, cs.ecount, maxE);
   S6Args a6{L, vmap, cs.tpin, cs.tlen, cs.fp, out->v_axons, nullptr, nullptr, cs.work,
-            cs.bitmap, cs.bitmap_words, n_coarse, cs.err, maxE};
+            cs.bitmap, cs.bitmap_words, n_coarse, cs.err, maxE, cs.fp_mask};
   a6.list = cs.ebucket;
   a6.count = cs.ecount;
   s6_small_kernel<<<gridEw, 256, 0, s>>>(a6);

@@ -17,10 +17,18 @@ struct hg_ctx {
   char* arena = nullptr;
   size_t arena_bytes = 0;
   int32_t* dev_err = nullptr;  // device error word (bounds reached by kernels)
+  // small device block owned by the context: the error word, the weight sum
+  // of the level check and the score-step census of the last level
+  unsigned long long* dev_wsum = nullptr;
+  int64_t* dev_census = nullptr;  // [2 * kNumBuckets]: vertices, visits
   bool timing = false;
   hipEvent_t ev[2 * HG_NUM_PHASES] = {};
   bool recorded[HG_NUM_PHASES] = {};
   hg::Tuning tuning;
+  // switches read from the environment at hg_create
+  bool validate = false;       // HG_VALIDATE=1: check every input level first
+  size_t scratch_cap = 0;      // HG_SCRATCH_CAP=bytes: refuse a larger arena
+  uint64_t fp_mask = ~0ull;    // HG_TEST_FP_BITS=n: keep n fingerprint bits
 };
 
 namespace hg {
@@ -65,6 +73,9 @@ inline int hip_fail(hg_ctx* c, hipError_t e, const char* what) {
 
 inline int ensure_arena(hg_ctx* c, size_t bytes) {
   if (bytes <= c->arena_bytes) return HG_OK;
+  if (c->scratch_cap && bytes > c->scratch_cap)
+    return fail(c, HG_ERR_NO_MEMORY, "%zu bytes of scratch needed, above the cap of %zu", bytes,
+                c->scratch_cap);
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
   if (c->arena) {
@@ -73,6 +84,7 @@ inline int ensure_arena(hg_ctx* c, size_t bytes) {
     c->arena_bytes = 0;
   }
   size_t want = bytes + bytes / 8;
+  if (c->scratch_cap && want > c->scratch_cap) want = c->scratch_cap;
   e = hipMalloc((void**)&c->arena, want);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -128,6 +140,7 @@ struct CoarsenScratch {
   int64_t* xn;
   int32_t* bcount;
   int32_t* blist;
+  int64_t* bvisits;
   int32_t* work;
   int32_t* cursor;
   int32_t* cand;
@@ -148,6 +161,7 @@ struct CoarsenScratch {
     xn = a.template take<int64_t>(V);
     bcount = a.template take<int32_t>(kNumBuckets);
     blist = a.template take<int32_t>(kNumBuckets * V);
+    bvisits = a.template take<int64_t>(kNumBuckets);
     work = a.template take<int32_t>(kNumBuckets);
     cursor = a.template take<int32_t>(2 * P);
     cand = a.template take<int32_t>(V);

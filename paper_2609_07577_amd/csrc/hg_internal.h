@@ -23,6 +23,8 @@ enum : int32_t {
   kErrWorkCount = 16,   // a work-list count above its capacity
   kErrListLength = 32,  // S7 list longer than its source hyperedge
   kErrMapRange = 64,    // a caller's vmap / part value (or n_coarse) out of range
+  kErrWeight = 128,     // a hyperedge weight below 1
+  kErrWeightSum = 256,  // the weights of a level sum to 2^31 or more
 };
 
 // Level sizes kept in device memory so that a chain of kernels can run
@@ -133,8 +135,9 @@ constexpr int kBigSlotsOv = 8192;
 constexpr int kMetaDeg = 1280;
 constexpr int kWinDeg = 768;  // incident hyperedges of a window-kernel vertex
 struct Buckets {
-  int32_t* count;  // [kNumBuckets] device counters
-  int32_t* list;   // [kNumBuckets * maxV]
+  int32_t* count;   // [kNumBuckets] device counters
+  int32_t* list;    // [kNumBuckets * maxV]
+  int64_t* visits;  // [kNumBuckets] sum of X_n over each list
 };
 void expansion_and_buckets(const LevelView& L, const int64_t* voff, const uint32_t* vinc,
                            int64_t maxV, int64_t* xn, GraphConst* gc, int32_t n_graphs,
@@ -200,6 +203,7 @@ struct ContractScratch {
   int64_t bitmap_words; // per work-group
   Dims* out_dims;       // device Dims of the output level
   int32_t* err;
+  uint64_t fp_mask = ~0ull;  // bits of the S7 fingerprints kept (all but in tests)
 };
 int contract_level(const LevelView& L, int64_t maxV, int64_t maxE, int64_t maxP,
                    const int32_t* vmap, const int32_t* n_coarse, hg_level_out* out,

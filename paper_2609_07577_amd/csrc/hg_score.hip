@@ -1331,7 +1331,13 @@ int persistent_grid(K kernel, int threads) {
 void score_candidates(const ScoreArgs& a, int64_t maxV, int64_t maxP, hipStream_t s) {
   no_candidate_kernel<<<grid_for(maxV, 256, 8192), 256, 0, s>>>(a.L.dims, a.cand, a.cscore,
                                                                a.work);
-  static int g[kNumBuckets] = {0};
+  // persistent grids, per device (the CU count and the occupancy of each
+  // kernel are fixed for a device)
+  constexpr int kMaxDevices = 64;
+  static int grids[kMaxDevices][kNumBuckets] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+  int* g = grids[dev];
   auto k0 = score_block_kernel<256, kSmallSlots, false, false>;
   auto k1 = score_block_kernel<512, kBigSlots, false, false>;
   auto k2 = score_window_kernel<1024>;

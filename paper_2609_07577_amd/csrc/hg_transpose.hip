@@ -64,7 +64,8 @@ __global__ void level0_finish_kernel(const Dims* __restrict__ d, int32_t* __rest
   for (int64_t e = i; e < E; e += stride) mult[e] = 1;
 }
 
-__global__ void reset_maxima_kernel(GraphConst* gc, int32_t n_graphs, int32_t* bcount) {
+__global__ void reset_maxima_kernel(GraphConst* gc, int32_t n_graphs, int32_t* bcount,
+                                    int64_t* visits) {
   int i = threadIdx.x;
   for (int g = i; g < n_graphs; g += blockDim.x) {
     gc[g].max_size = 0;
@@ -72,7 +73,10 @@ __global__ void reset_maxima_kernel(GraphConst* gc, int32_t n_graphs, int32_t* b
     gc[g].max_ax = 0;
     gc[g].nverts = 0;
   }
-  if (i < kNumBuckets) bcount[i] = 0;
+  if (i < kNumBuckets) {
+    bcount[i] = 0;
+    visits[i] = 0;
+  }
 }
 
 __global__ void expansion_kernel(LevelView L, const int64_t* __restrict__ voff,
@@ -160,6 +164,16 @@ __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
     }
     const int32_t pos = wave_bucket_slot<kNumBuckets>(bk, b.count);
     if (bk >= 0) b.list[(int64_t)bk * maxV + pos] = (int32_t)v;
+    // the neighbour visits of each list (a census read back by the host)
+    const int64_t xv = (bk >= 0) ? xn[v] : 0;
+#pragma unroll
+    for (int k = 0; k < kNumBuckets; ++k) {
+      if (__builtin_amdgcn_ballot_w64(bk == k) == 0) continue;  // wave-uniform
+      int64_t s = bk == k ? xv : 0;
+#pragma unroll
+      for (int d = kWave / 2; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
+      if (lane == 0) atomicAdd((unsigned long long*)&b.visits[k], (unsigned long long)s);
+    }
   }
 }
 
@@ -189,7 +203,7 @@ void level0_state(const Dims* d, const int64_t* eoff, const uint32_t* pins, int6
 void expansion_and_buckets(const LevelView& L, const int64_t* voff, const uint32_t* vinc,
                            int64_t maxV, int64_t* xn, GraphConst* gc, int32_t n_graphs,
                            Buckets b, Tuning t, hipStream_t s) {
-  reset_maxima_kernel<<<1, 256, 0, s>>>(gc, n_graphs, b.count);
+  reset_maxima_kernel<<<1, 256, 0, s>>>(gc, n_graphs, b.count, b.visits);
   expansion_kernel<<<grid_for(maxV, 4, 16384), 256, 0, s>>>(L, voff, vinc, xn, gc, b, maxV);
   bucket_kernel<<<grid_for(maxV, 256, 16384), 256, 0, s>>>(L, xn, voff, gc, b, maxV,
                                                           t.load16);

@@ -33,7 +33,7 @@ _i64 = ctypes.c_int64
 EXPORTED = ("hg_create", "hg_destroy", "hg_set_stream", "hg_last_error", "hg_sync",
             "hg_scratch_bytes", "hg_enable_timing", "hg_phase_times", "hg_init_state",
             "hg_coarsen_level", "hg_contract", "hg_connectivity", "hg_validate_level",
-            "hg_set_tuning", "hg_get_tuning",
+            "hg_set_tuning", "hg_get_tuning", "hg_score_census",
             "hg_batch_create", "hg_batch_destroy", "hg_batch_bytes", "hg_batch_add_graph",
             "hg_batch_step", "hg_batch_done", "hg_batch_result", "hg_batch_compact",
             "hg_batch_sizes")
@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH):
     lib.hg_phase_times.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
     lib.hg_set_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
     lib.hg_get_tuning.argtypes = [_P, ctypes.POINTER(Tuning)]
+    lib.hg_score_census.argtypes = [_P, ctypes.POINTER(_i64)]
     lib.hg_batch_create.argtypes = [_P, _i32, _i32, _i32, _i64, ctypes.POINTER(_P)]
     lib.hg_batch_destroy.argtypes = [_P]
     lib.hg_batch_bytes.argtypes = [_P]
@@ -191,6 +192,12 @@ class Context:
         t = Tuning()
         self._check(self.lib.hg_get_tuning(self.h, ctypes.byref(t)))
         return dict(single_pass_load16=t.single_pass_load16, pass_fill16=t.pass_fill16)
+
+    def score_census(self) -> tuple[list[int], list[int]]:
+        """(vertices, neighbour visits) per score work list of the last level."""
+        buf = (_i64 * 16)()
+        self._check(self.lib.hg_score_census(self.h, buf))
+        return [int(buf[k]) for k in range(8)], [int(buf[8 + k]) for k in range(8)]
 
     def enable_timing(self, on: bool = True):
         self._check(self.lib.hg_enable_timing(self.h, 1 if on else 0))

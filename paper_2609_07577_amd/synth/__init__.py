@@ -207,3 +207,46 @@ LIMITS = {
     "powerlaw": Limits(4_096, 262_144, 16_384),
     "batch": Limits(512, 32_768, 2_048),
 }
+
+
+def hub_graph(seed: int, n: int, fan: int, n_hubs: int, hub_p: float, w_max: int = 100,
+              skew: float = 0.0) -> Level0:
+    """Recurrent network with a few hub neurons (test sizes).
+
+    Every neuron's axon reaches ``fan`` distinct other neurons, drawn with
+    probability proportional to (id + 1)^-skew (uniform for skew 0), and in
+    addition each of ``n_hubs`` hub neurons with probability ``hub_p``, so
+    that the hubs have about ``hub_p * n`` inbound axons.  Weights uniform in
+    [1, w_max]."""
+    rng = np.random.default_rng(seed)
+    hubs = np.arange(n_hubs, dtype=np.int64) * (n // max(n_hubs, 1)) + 7
+    cdf = None
+    if skew > 0:
+        cdf = np.cumsum((np.arange(n, dtype=np.float64) + 1.0) ** -skew)
+        cdf /= cdf[-1]
+    eoff = [0]
+    pins = []
+    w = np.empty(n, dtype=np.int32)
+    for s in range(n):
+        if cdf is None:
+            t = rng.choice(n - 1, size=fan, replace=False)
+            t = t + (t >= s)
+        else:
+            # draws with replacement until fan distinct others are found,
+            # kept in the order they were drawn
+            t = np.empty(0, dtype=np.int64)
+            while t.shape[0] < fan:
+                d = np.searchsorted(cdf, rng.random(4 * fan), side="right")
+                d = np.minimum(d, n - 1)
+                d = np.concatenate([t, d[d != s]])
+                _, first = np.unique(d, return_index=True)
+                t = d[np.sort(first)]
+            t = t[:fan]
+        extra = hubs[rng.random(n_hubs) < hub_p]
+        ids = np.union1d(np.union1d(t, extra[extra != s]), [s]).astype(np.uint32)
+        flag = (ids != s).astype(np.uint32) << np.uint32(31)
+        pins.append(ids | flag)
+        eoff.append(eoff[-1] + ids.shape[0])
+        w[s] = int(rng.integers(1, w_max + 1))
+    return Level0(n, np.array(eoff, dtype=np.int64), np.concatenate(pins).astype(np.uint32), w,
+                  f"hub{n}f{fan}h{n_hubs}s{seed}")

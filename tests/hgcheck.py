@@ -137,3 +137,32 @@ def check_contraction(fine, coarse, vmap):
         starts[coarse["eoff"][1:-1]] = True
         assert np.all((d > 0) | starts[1:]), "coarse pins not strictly ascending"
     assert np.all(np.diff(coarse["eoff"]) >= 2)
+
+
+def score_buckets(level, limits, load16=8, small=4096, big=16384, big_ov=8192, win_deg=768):
+    """Work list of every vertex in the score step, by the rule the library
+    applies before scoring (a host copy of that rule, used to show which
+    scoring kernels an input reaches; results never depend on it).
+
+    ``level`` is an oracle level (eoff, pins, ax, V).  Returns int array
+    [V]: -1 for vertices without neighbours, else 0..7: single pass in the
+    small table, single pass in the big table, windows (at most ``win_deg``
+    incident hyperedges), passes over a table; +4 when the distinct-axon
+    bound can bind for the vertex (its ax plus the level's largest ax above
+    the limit), which makes the step also count shared inbound axons."""
+    eoff = np.asarray(level.eoff, dtype=np.int64)
+    lens = np.diff(eoff)
+    ids = (np.asarray(level.pins) & MASK).astype(np.int64)
+    V = int(level.V)
+    edge_of_pin = np.repeat(np.arange(lens.shape[0]), lens)
+    xn = np.bincount(ids, weights=(lens - 1)[edge_of_pin], minlength=V).astype(np.int64)
+    deg = np.bincount(ids, minlength=V)
+    ax = np.asarray(level.ax, dtype=np.int64)
+    max_ax = int(ax.max(initial=0))
+    ov = ax + max_ax > limits.max_axons
+    dist = np.minimum(xn, V - 1)
+    b = np.where(dist <= small * load16 // 16, 0,
+                 np.where(dist <= np.where(ov, big_ov, big) * load16 // 16, 1,
+                          np.where(deg <= win_deg, 2, 3)))
+    b = b + 4 * ov
+    return np.where(xn > 0, b, -1)

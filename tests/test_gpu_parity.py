@@ -40,14 +40,23 @@ def assert_level_equal(gpu_level, olev, where=""):
     np.testing.assert_array_equal(g["ax"], olev.ax, err_msg=f"ax {where}")
 
 
-def run_hierarchy_parity(ctx, g, lim, max_levels=64, check_conn=True, verbose=False):
+def run_hierarchy_parity(ctx, g, lim, max_levels=None, check_conn=True, verbose=False,
+                         census=None):
     """Run GPU and oracle level by level from the same level 0; compare all.
-    Each level's outputs are checked before the next GPU step consumes them."""
+    Each level's outputs are checked before the next GPU step consumes them.
+    ``max_levels=None`` runs to the stop rule (no vertex proposes a
+    candidate; Section 4.1) and asserts that both sides stop at the same
+    level.  The score step's census of work lists is compared on every level
+    with the host copy of the bucket rule; ``census`` (an int array of 8)
+    accumulates the vertices scored by each list."""
     from paper_2609_07577_amd import hg  # noqa: F401
-    oh = oracle.hierarchy(g, lim, max_levels=max_levels)
+    oh = oracle.hierarchy(g, lim, max_levels=max_levels or 100000)
+    if max_levels is None:
+        assert not oh.levels[-1].any_candidate, "oracle did not reach the stop rule"
     if verbose:
         print(f"  {g.name}: V={g.n_vertices} P={g.n_pins}, oracle levels={len(oh.levels)}",
               flush=True)
+    load16 = ctx.get_tuning()["single_pass_load16"]
     L = ctx.upload(g)
     ctx.sync()
     assert_level_equal(L, oh.levels[0].level, "level 0 state")
@@ -57,6 +66,12 @@ def run_hierarchy_parity(ctx, g, lim, max_levels=64, check_conn=True, verbose=Fa
             print(f"  {where}: coarsen V={L.V} E={L.E} P={L.P}", flush=True)
         out = ctx.coarsen_level(L, lim)
         ctx.sync()
+        nv, _visits = ctx.score_census()
+        b = hgcheck.score_buckets(r.level, lim, load16=load16)
+        expect = np.bincount(b[b >= 0], minlength=8)
+        assert nv == expect.tolist(), f"score work lists {where}: {nv} vs {expect.tolist()}"
+        if census is not None:
+            census += expect
         np.testing.assert_array_equal(_np(out["cand"]), r.cand, err_msg=f"cand {where}")
         np.testing.assert_array_equal(_np(out["cscore"]), r.cscore, err_msg=f"cscore {where}")
         np.testing.assert_array_equal(_np(out["match"]), r.match, err_msg=f"match {where}")
@@ -134,14 +149,60 @@ def test_tiny_random_graphs(ctx, block):
 
 
 def test_layered_full_hierarchy(ctx):
+    """The layered 4 x 1024 workload to the stop rule: every level (395
+    contractions) equals the oracle's, and the GPU finds no candidate at the
+    same level as the oracle."""
     g = synth.layered(1)
-    oh = run_hierarchy_parity(ctx, g, synth.LIMITS["layered"], verbose=True)
-    assert oh.n_levels >= 8
+    oh = run_hierarchy_parity(ctx, g, synth.LIMITS["layered"])
+    print(f"  layered: {oh.n_levels} contractions to the stop rule", flush=True)
+    assert oh.n_levels > 300
 
 
 def test_conv_small_hierarchy(ctx):
-    g = synth.conv(2, layers=4, height=12, width=12, channels=8)
-    run_hierarchy_parity(ctx, g, synth.Limits(256, 8192, 1024), verbose=True)
+    oh = run_hierarchy_parity(ctx, synth.conv(2, layers=4, height=12, width=12, channels=8),
+                              synth.Limits(256, 8192, 1024))
+    print(f"  conv small: {oh.n_levels} contractions to the stop rule", flush=True)
+
+
+def test_overlap_kernels_hub_levels(ctx):
+    """Levels where the distinct-axon bound of Section 3 binds with thousands
+    of distinct neighbours: 12,000 neurons, each axon reaching 100 random
+    neurons, plus 8 hubs that about 900 axons reach; Delta = 1000, so every
+    vertex needs the shared inbound count in its scores, the typical vertex
+    is scored in passes over a table with that count (more than 4,096
+    distinct neighbours, fewer than 769 incident hyperedges) and the hubs
+    in passes with their incident hyperedges read from global memory.  Six
+    levels against the oracle, element by element."""
+    g = synth.hub_graph(1, 12000, 100, 8, 0.075)
+    census = np.zeros(8, np.int64)
+    run_hierarchy_parity(ctx, g, synth.Limits(512, 65536, 1000), max_levels=6, census=census,
+                         verbose=True)
+    print(f"  census {census.tolist()}", flush=True)
+    assert census[6] >= 20000 and census[7] >= 200
+
+
+def test_passes_without_overlap_hubs(ctx):
+    """Hubs with more than 768 incident hyperedges and no binding axon limit
+    are scored in passes over a table with the hyperedges read from global
+    memory; six levels against the oracle."""
+    g = synth.hub_graph(2, 20000, 30, 16, 0.05)
+    census = np.zeros(8, np.int64)
+    run_hierarchy_parity(ctx, g, synth.Limits(512, 65536, 1 << 30), max_levels=6,
+                         census=census)
+    print(f"  census {census.tolist()}", flush=True)
+    assert census[3] >= 16
+
+
+def test_batch_mix_graph_coarse_levels(ctx):
+    """A recurrent graph of the batch mix (6,789 neurons, fan-out 16..256)
+    under the batch limits: from its fifth level on, super-nodes whose
+    distinct-axon bound binds are scored with the shared inbound count in
+    both multipass kernels; twelve levels against the oracle."""
+    g = synth.batch_graph(1001, 0, 1000, 8000, 16, 256)
+    census = np.zeros(8, np.int64)
+    run_hierarchy_parity(ctx, g, synth.LIMITS["batch"], max_levels=12, census=census)
+    print(f"  census {census.tolist()}", flush=True)
+    assert census[5] > 0 and census[6] > 0 and census[7] > 0
 
 
 def test_uniform_tight_axon_limit(ctx):
@@ -233,31 +294,41 @@ def test_empty_and_degenerate(ctx):
 
 def test_tuning_never_changes_results(ctx):
     """The score-step settings (single-pass load, multipass fill target)
-    choose between table sizes and pass widths; the result is the same."""
+    move vertices between the work lists and change pass widths; the result
+    is the oracle's under every setting.  The input spreads the expansion
+    sizes from hundreds to hundreds of thousands (targets drawn with a
+    preference for low ids) and sets Delta to the largest inbound-axon count
+    plus the median, so that about half of the vertices need the shared
+    inbound count: under the settings below vertices move between the
+    one-pass tables, the windows and the passes with the overlap table (the
+    only kernel that reads the fill target)."""
     from paper_2609_07577_amd import hg
-    g = synth.powerlaw(5, n=30_000, dmin=20, dmax=3_000)
-    lim = synth.LIMITS["powerlaw"]
+    g = synth.hub_graph(4, 20000, 60, 0, 0.0, skew=0.6)
+    OL = oracle.level0(g)
+    lim = synth.Limits(512, 1 << 20, int(OL.ax.max()) + int(np.median(OL.ax)))
+    expect = oracle.coarsen_level(OL, lim)
     L = ctx.upload(g)
-    ref = None
+    seen = {}
     try:
-        for load, fill in ((8, 5), (1, 1), (12, 10), (4, 3)):
+        for load, fill in ((8, 5), (1, 1), (12, 10), (4, 3), (1, 10)):
             ctx.set_tuning(load, fill)
             out = ctx.coarsen_level(L, lim)
-            got = tuple(_np(out[k]) for k in ("cand", "cscore", "match", "vmap"))
-            if ref is None:
-                ref = got
-            for a, b in zip(ref, got):
-                np.testing.assert_array_equal(a, b, err_msg=f"tuning {load}/{fill}")
+            ctx.sync()
+            nv, _ = ctx.score_census()
+            b = hgcheck.score_buckets(OL, lim, load16=load)
+            assert nv == np.bincount(b[b >= 0], minlength=8).tolist(), (load, nv)
+            seen[(load, fill)] = tuple(nv)
+            for k, ref in (("cand", expect.cand), ("cscore", expect.cscore),
+                           ("match", expect.match), ("vmap", expect.vmap)):
+                np.testing.assert_array_equal(_np(out[k]), ref, err_msg=f"{k} tuning {load}/{fill}")
         for bad in ((0, 5), (13, 5), (8, 0), (8, 11)):
             with pytest.raises(hg.HgError):
                 ctx.set_tuning(*bad)
     finally:
         ctx.set_tuning(8, 5)
-    OL = oracle.level0(g)
-    q = np.sort(np.random.default_rng(3).choice(g.n_vertices, 200, replace=False)).astype(np.int32)
-    oc, ocs = oracle.candidates(OL, lim, query=q)
-    np.testing.assert_array_equal(ref[0][q], oc)
-    np.testing.assert_array_equal(ref[1][q], ocs)
+    print(f"  census per setting {seen}", flush=True)
+    assert len(set(seen.values())) >= 3, "the settings did not move vertices between lists"
+    assert seen[(1, 1)][2] > 1000 and seen[(1, 1)][6] > 1000  # windows and overlap passes
 
 
 def test_out_of_range_maps_are_rejected(ctx):
@@ -308,19 +379,11 @@ def test_out_of_range_maps_are_rejected(ctx):
         assert int(ctx.connectivity(L, good).item()) == expect_conn, f"after {what}"
 
 
-def _window_bucket_vertices(g, load16=8, big_slots=16384):
-    """Vertices the score step gives to the multipass window kernel: the
-    distinct-neighbour bound min(X_n, V - 1) above the single-pass capacity
-    (load16/16 of the big table) with at most 768 incident hyperedges
-    (the overlap bound cannot bind for these level-0 limits)."""
-    L0 = oracle.level0(g)
-    lens = np.diff(L0.eoff).astype(np.int64)
-    edge_of_pin = np.repeat(np.arange(L0.E), lens)
-    ids = (L0.pins & 0x7FFFFFFF).astype(np.int64)
-    xn = np.bincount(ids, weights=lens[edge_of_pin], minlength=g.n_vertices)
-    deg = np.bincount(ids, minlength=g.n_vertices)
-    dist = np.minimum(xn, g.n_vertices - 1)
-    return np.flatnonzero((dist > big_slots * load16 // 16) & (deg <= 768))
+def _window_bucket_vertices(g, lim=synth.LIMITS["powerlaw"], load16=8):
+    """Vertices of level 0 that the score step gives to the window kernel
+    (host copy of the bucket rule)."""
+    b = hgcheck.score_buckets(oracle.level0(g), lim, load16=load16)
+    return np.flatnonzero(b == 2)
 
 
 def test_window_list_overflow_halves_the_window(ctx):
@@ -370,14 +433,12 @@ def test_window_degree_limit(ctx):
 
 
 @pytest.mark.parametrize("weights", [(1,), (1, 2)], ids=["equal", "two-valued"])
-def test_window_weight_ties(ctx, weights):
-    """Large neighbourhoods whose hyperedges share few weight values: 1250
-    axons of 400 random targets over 20,000 neurons (about 25 axons reach
-    each neuron, 16,000 of which are scored in windows), weights all 1 or
-    drawn from {1, 2}.  Most neighbours share one hyperedge with n, so the
-    best single of a vertex is decided among many batches of equal weight
-    by the smallest id (Eq. 12 scores, lowest id on ties), across waves
-    and windows; the levels must be the oracle's."""
+def test_window_random_neighbourhoods_few_weights(ctx, weights):
+    """Large random neighbourhoods whose hyperedges share few weight values:
+    1250 axons of 400 random targets over 20,000 neurons (about 25 axons
+    reach each neuron, 16,000 of which are scored in windows), weights all 1
+    or drawn from {1, 2}; most candidates are neighbours met in several
+    hyperedges.  The levels must be the oracle's."""
     rng = np.random.default_rng(11)
     n, na = 20_000, 1250
     axons = []
@@ -388,3 +449,64 @@ def test_window_weight_ties(ctx, weights):
     g = synth.from_axons(n, axons)
     assert len(_window_bucket_vertices(g)) >= 15_000
     run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=3, verbose=True)
+
+
+def _disjoint_neighbourhoods(seed, n, hubs, k, fan, heavy):
+    """Hub neurons each reached by ``k`` axons whose other pins (source and
+    ``fan - 1`` targets) are distinct neurons met nowhere else, spread over
+    ``n`` ids: every neighbour of a hub shares exactly one hyperedge with it,
+    so its Eq. 12 score is that hyperedge's weight.  All weights are 1,
+    except, with ``heavy``, weight 2 on three hyperedges per hub chosen among
+    those whose smallest neighbour lies above the median, so that the hub's
+    smallest neighbour sits in a lighter hyperedge than its candidate."""
+    rng = np.random.default_rng(seed)
+    ids = rng.permutation(n)
+    hub_ids = ids[:hubs]
+    pool = ids[hubs:]
+    axons = []
+    cursor = 0
+    for h in hub_ids.tolist():
+        groups = []
+        for _ in range(k):
+            grp = pool[cursor:cursor + fan]
+            cursor += fan
+            groups.append(grp)
+        w = [1] * k
+        if heavy:
+            lows = np.array([int(gr.min()) for gr in groups])
+            late = np.flatnonzero(lows > np.median(lows))
+            for j in rng.choice(late, size=3, replace=False).tolist():
+                w[j] = 2
+        for grp, wt in zip(groups, w):
+            src = int(grp[0])
+            axons.append((src, sorted([h] + [int(x) for x in grp[1:]]), wt))
+    return synth.from_axons(n, axons), hub_ids
+
+
+@pytest.mark.parametrize("heavy", [False, True], ids=["equal", "heavy-late"])
+def test_window_lowest_id_single(ctx, heavy):
+    """Hubs scored in windows (600,000 ids, two windows) whose neighbours
+    are all singles (disjoint target sets): the candidate is decided by the
+    lowest id among the batches of the heaviest weight, spread over many
+    batches, waves and both windows.  With all weights equal it is the
+    hub's smallest neighbour; with three weight-2 hyperedges placed above
+    the median it is the smallest neighbour among those, while lighter
+    batches holding smaller ids are also processed (before or after them,
+    on other waves).  The levels must be the oracle's."""
+    g, hubs = _disjoint_neighbourhoods(5, 600_000, 8, 400, 50, heavy)
+    L0 = oracle.level0(g)
+    b = hgcheck.score_buckets(L0, synth.LIMITS["powerlaw"])
+    assert np.all(b[hubs] == 2), "hubs must be scored in windows"
+    r0 = oracle.coarsen_level(L0, synth.LIMITS["powerlaw"])
+    for h in hubs.tolist():
+        # the hub's neighbours and the candidate the definition gives
+        edges = [e for e in range(L0.E)
+                 if h in (L0.pins[L0.eoff[e]:L0.eoff[e + 1]] & 0x7FFFFFFF).tolist()]
+        best_w = max(int(L0.w[e]) for e in edges)
+        nb = [(int(v), int(L0.w[e])) for e in edges
+              for v in (L0.pins[L0.eoff[e]:L0.eoff[e + 1]] & 0x7FFFFFFF).tolist() if v != h]
+        assert r0.cand[h] == min(v for v, w in nb if w == best_w)
+        assert r0.cscore[h] == best_w
+        if heavy:
+            assert r0.cand[h] > min(v for v, _ in nb)
+    run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
