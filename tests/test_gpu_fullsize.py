@@ -7,7 +7,8 @@ benchmark times.
   GPU candidates; the contraction is checked by its conservation laws and by
   Eq. 1 evaluated two ways (and by the oracle) on the fine level.
 * The convolutional level (262,144 neurons, 27.9M pins): the whole level,
-  every array, against the oracle.
+  every array, against the oracle; and the whole convolutional hierarchy
+  (409 contractions) to the stop rule, every level against the oracle.
 """
 import numpy as np
 import pytest
@@ -98,3 +99,15 @@ def test_conv_level0_full(ctx):
         np.testing.assert_array_equal(ch[k], ov, err_msg=k)
     conn = int(ctx.connectivity(L, out["vmap"]).item())
     assert conn == oracle.connectivity(OL.eoff, OL.pins, OL.w, ores.vmap)
+
+
+@pytest.mark.timeout(900)
+def test_conv_full_hierarchy(ctx):
+    """The convolutional workload (4 layers of 64 x 64 x 16, limits
+    1024 / 65536 / 4096) coarsened to the stop rule: every level's
+    candidates, scores, matching, vertex map, coarse level and Eq. 1 value
+    equal the oracle's, and both stop at the same level."""
+    import test_gpu_parity as tp
+    g = synth.conv(1)
+    oh = tp.run_hierarchy_parity(ctx, g, synth.LIMITS["conv"])
+    print(f"  conv: {oh.n_levels} contractions to the stop rule", flush=True)
