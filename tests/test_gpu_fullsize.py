@@ -109,5 +109,5 @@ def test_conv_full_hierarchy(ctx):
     equal the oracle's, and both stop at the same level."""
     import test_gpu_parity as tp
     g = synth.conv(1)
-    oh = tp.run_hierarchy_parity(ctx, g, synth.LIMITS["conv"])
+    oh = tp.run_hierarchy_parity(ctx, g, synth.LIMITS["conv"], verbose=True)
     print(f"  conv: {oh.n_levels} contractions to the stop rule", flush=True)
