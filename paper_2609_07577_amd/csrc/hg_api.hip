@@ -387,27 +387,9 @@ int hg_connectivity(hg_ctx* c, const hg_level* lvl, const int32_t* part, int64_t
   if (rc) return rc;
   if ((lvl->n_vertices > 0 && !part) || !conn) return fail(c, HG_ERR_INVALID_ARG, "null argument");
   if (c->validate && (rc = hg_validate_level(c, lvl)) != HG_OK) return rc;
-  const int64_t V = lvl->n_vertices, E = lvl->n_edges, P = lvl->n_pins;
-  Sizer sz;
-  ConnLayout<Sizer> ls;
-  ls.carve(sz, V, E);
-  sz.take<int32_t>(V);
-  rc = ensure_arena(c, sz.off);
+  rc = ensure_arena(c, connectivity_scratch_bytes(lvl->n_vertices, lvl->n_edges));
   if (rc) return rc;
-  Carver cv{c->arena};
-  ConnLayout<Carver> S;
-  S.carve(cv, V, E);
-  int32_t* map = cv.take<int32_t>(V);
-  hipStream_t s = c->stream;
-  set_dims(S.dims, V, E, P, s);
-  LevelView L = view_of(lvl, S.dims);
-  S.cs.err = c->dev_err;
-  mark(c, 4, 0);
-  check_map_kernel<<<grid_for(V, 256, 4096), 256, 0, s>>>(part, V, nullptr, map, nullptr,
-                                                        c->dev_err);
-  connectivity(L, E, V, map, conn, S.cs, s);
-  mark(c, 4, 1);
-  return launch_status(c);
+  return run_connectivity(c, lvl, part, conn, c->arena);
 }
 
 int hg_score_census(hg_ctx* c, int64_t* out) {
@@ -423,12 +405,36 @@ int hg_validate_level(hg_ctx* c, const hg_level* L) {
   if (!c) return HG_ERR_INVALID_ARG;
   int rc = check_level(c, L, false);
   if (rc) return rc;
-  Sizer sz;
-  sz.take<unsigned long long>(1);
-  sz.take<int32_t>(1);
-  rc = ensure_arena(c, sz.off);
+  rc = ensure_arena(c, validate_scratch_bytes());
   if (rc) return rc;
-  Carver cv{c->arena};
+  return validate_with(c, L, c->arena);
+}
+
+}  // extern "C"
+
+namespace hg {
+
+int run_connectivity(hg_ctx* c, const hg_level* lvl, const int32_t* part, int64_t* conn,
+                     char* base) {
+  const int64_t V = lvl->n_vertices, E = lvl->n_edges, P = lvl->n_pins;
+  Carver cv{base};
+  ConnLayout<Carver> S;
+  S.carve(cv, V, E);
+  int32_t* map = cv.take<int32_t>(V);
+  hipStream_t s = c->stream;
+  set_dims(S.dims, V, E, P, s);
+  LevelView L = view_of(lvl, S.dims);
+  S.cs.err = c->dev_err;
+  mark(c, 4, 0);
+  check_map_kernel<<<grid_for(V, 256, 4096), 256, 0, s>>>(part, V, nullptr, map, nullptr,
+                                                        c->dev_err);
+  connectivity(L, E, V, map, conn, S.cs, s);
+  mark(c, 4, 1);
+  return launch_status(c);
+}
+
+int validate_with(hg_ctx* c, const hg_level* L, char* base) {
+  Carver cv{base};
   unsigned long long* wsum = cv.take<unsigned long long>(1);
   int32_t* bad = cv.take<int32_t>(1);
   hipStream_t s = c->stream;
@@ -438,7 +444,7 @@ int hg_validate_level(hg_ctx* c, const hg_level* L) {
                L->v_size, L->v_syn, L->v_axons, nullptr};
   validate_kernel<<<grid_for(L->n_edges > L->n_vertices ? L->n_edges : L->n_vertices, 256, 4096),
                     256, 0, s>>>(lv, L->n_vertices, L->n_edges, L->n_pins, wsum, bad);
-  rc = launch_status(c);
+  int rc = launch_status(c);
   if (rc) return rc;
   unsigned long long hw = 0;
   int32_t hb = 0;
@@ -451,4 +457,4 @@ int hg_validate_level(hg_ctx* c, const hg_level* L) {
   return HG_OK;
 }
 
-}  // extern "C"
+}  // namespace hg

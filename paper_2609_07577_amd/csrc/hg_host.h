@@ -225,4 +225,28 @@ struct ConnLayout {
   }
 };
 
+inline size_t connectivity_scratch_bytes(int64_t V, int64_t E) {
+  Sizer sz;
+  ConnLayout<Sizer> ls;
+  ls.carve(sz, V, E);
+  sz.take<int32_t>(V);  // checked copy of the partition
+  return sz.off;
+}
+
+inline size_t validate_scratch_bytes() {
+  Sizer sz;
+  sz.take<unsigned long long>(1);
+  sz.take<int32_t>(1);
+  return sz.off;
+}
+
+// Bodies of hg_connectivity and hg_validate_level over a given scratch base
+// (the context's arena, or the library's fixed scratch).
+int run_connectivity(hg_ctx* c, const hg_level* lvl, const int32_t* part, int64_t* conn,
+                     char* base);
+int validate_with(hg_ctx* c, const hg_level* L, char* base);
+
+// The library's fixed device scratch (hg_static.hip): its address on the
+// current device is looked up once per device by hg_create.
+int static_scratch_setup(int device);
 }  // namespace hg
