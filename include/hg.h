@@ -211,6 +211,21 @@ int hg_contract(hg_ctx* ctx, const hg_level* in, const int32_t* vmap,
 int hg_connectivity(hg_ctx* ctx, const hg_level* lvl, const int32_t* part, int64_t* conn);
 
 /*
+ * hg_connectivity with no allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation in their loop).  Same arguments, result and checks
+ * as hg_connectivity; its kernels use a fixed device array of the library
+ * (64 MiB per GPU, held until the process ends) instead of the context's
+ * arena.  A level needing more than that (about 12 bytes per vertex plus 12
+ * per hyperedge, e.g. 2.7M of each) fails with HG_ERR_CAPACITY before any
+ * work.  All calls on one GPU share the array: calls that overlap on one GPU
+ * (other streams or host threads) race, and the caller must serialise them.
+ * With HG_VALIDATE=1 the level check also uses the fixed array.
+ */
+int hg_connectivity_static(hg_ctx* ctx, const hg_level* lvl, const int32_t* part,
+                           int64_t* conn);
+
+/*
  * Score-step tuning of a context.  The score step (Eq. 12) scores a vertex in
  * one pass over an on-chip table when its distinct-neighbour bound (its
  * expansion, the sum of the sizes of its incident hyperedges, capped by the

@@ -149,6 +149,9 @@ int hg_create(int device, void* hip_stream, hg_ctx** out) {
     delete c;
     return HG_ERR_HIP;
   }
+  // the fixed scratch of hg_connectivity_static, once per device (the
+  // device is current here); a failure only disables that call
+  (void)static_scratch_setup(device);
   c->dev_err = reinterpret_cast<int32_t*>(blk);
   c->dev_wsum = reinterpret_cast<unsigned long long*>(blk + 64);
   c->dev_census = reinterpret_cast<int64_t*>(blk + 128);

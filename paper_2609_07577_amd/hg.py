@@ -33,7 +33,7 @@ _i64 = ctypes.c_int64
 EXPORTED = ("hg_create", "hg_destroy", "hg_set_stream", "hg_last_error", "hg_sync",
             "hg_scratch_bytes", "hg_enable_timing", "hg_phase_times", "hg_init_state",
             "hg_coarsen_level", "hg_contract", "hg_connectivity", "hg_validate_level",
-            "hg_set_tuning", "hg_get_tuning", "hg_score_census",
+            "hg_set_tuning", "hg_get_tuning", "hg_score_census", "hg_connectivity_static",
             "hg_batch_create", "hg_batch_destroy", "hg_batch_bytes", "hg_batch_add_graph",
             "hg_batch_step", "hg_batch_done", "hg_batch_result", "hg_batch_compact",
             "hg_batch_sizes")
@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH):
                                      _P, _P, _P, _P]
     lib.hg_contract.argtypes = [_P, ctypes.POINTER(_Level), _P, _P, ctypes.POINTER(_LevelOut)]
     lib.hg_connectivity.argtypes = [_P, ctypes.POINTER(_Level), _P, _P]
+    lib.hg_connectivity_static.argtypes = [_P, ctypes.POINTER(_Level), _P, _P]
     lib.hg_validate_level.argtypes = [_P, ctypes.POINTER(_Level)]
     lib.hg_enable_timing.argtypes = [_P, ctypes.c_int]
     lib.hg_phase_times.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
@@ -295,6 +296,19 @@ class Context:
             conn = torch.zeros(1, dtype=torch.int64, device=self.device)
             self._check(self.lib.hg_connectivity(self.h, ctypes.byref(lv), _ptr(part),
                                                  _ptr(conn)))
+        return conn
+
+    def connectivity_static(self, L: DeviceLevel, part: torch.Tensor,
+                            conn: torch.Tensor | None = None) -> torch.Tensor:
+        """Eq. (1) through hg_connectivity_static: no device allocation inside
+        the call (the result tensor is created here unless ``conn`` is given)."""
+        lv = L.c_struct()
+        assert part.dtype == torch.int32
+        with torch.cuda.stream(self.stream):
+            if conn is None:
+                conn = torch.zeros(1, dtype=torch.int64, device=self.device)
+            self._check(self.lib.hg_connectivity_static(self.h, ctypes.byref(lv), _ptr(part),
+                                                        _ptr(conn)))
         return conn
 
     def validate(self, L: DeviceLevel):
