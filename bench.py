@@ -99,9 +99,28 @@ def read_traffic(workload):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(g, lim, X, P, seconds):
-    """The oracle's candidate step (the whole level's dominant cost) on a
-    seeded vertex sample, extrapolated to the level by neighbour visits."""
+def _edge_subset(OL, frac, rng):
+    """The level restricted to a seeded fraction of its hyperedges (all
+    vertices and their state kept): a sample for timing the contraction."""
+    import oracle
+    E = OL.E
+    keep = np.sort(rng.choice(E, size=max(1, int(frac * E)), replace=False))
+    lens = np.diff(OL.eoff)[keep]
+    eoff = np.zeros(keep.shape[0] + 1, np.int64)
+    np.cumsum(lens, out=eoff[1:])
+    starts = OL.eoff[keep]
+    idx = np.repeat(starts - eoff[:-1], lens) + np.arange(eoff[-1])
+    return oracle.OLevel(OL.V, eoff, OL.pins[idx].copy(), OL.w[keep].copy(),
+                         OL.mult[keep].copy(), OL.size, OL.syn, OL.soff, OL.sids)
+
+
+def cpu_baseline(g, lim, X, P, seconds, gpu_cand, gpu_cscore, gpu_vmap, n_coarse):
+    """The oracle's time for the whole level, every step timed on a bounded
+    sample and scaled to the level: candidates (Eq. 12) for a seeded vertex
+    sample, scaled by neighbour visits; the incidence build in full;
+    matching (Eq. 13) and the vertex map in full (on the GPU's candidates,
+    equal to the oracle's); the contraction on two seeded hyperedge subsets
+    (4% and 8% of the hyperedges, every vertex), scaled linearly in pins."""
     import oracle
     oracle.build(force=False)
     nthreads = len(os.sched_getaffinity(0))
@@ -113,6 +132,7 @@ def cpu_baseline(g, lim, X, P, seconds):
     ids = (g.pins & 0x7FFFFFFF).astype(np.int64)
     edge_of_pin = np.repeat(np.arange(g.n_edges), lens)
     xn = np.bincount(ids, weights=(lens - 1)[edge_of_pin], minlength=g.n_vertices)
+    del edge_of_pin, ids
     rng = np.random.default_rng(12345)
     # sample size from an a-priori cost of 14 ns per neighbour visit per thread
     # (measured on 16 host threads: 5.99e9 visits in 5.4 s)
@@ -122,16 +142,36 @@ def cpu_baseline(g, lim, X, P, seconds):
     secs = np.zeros(2, np.float64)
     t0 = time.perf_counter()
     oracle.candidates(OL, lim, query=q, nthreads=nthreads, seconds=secs)
-    t = time.perf_counter() - t0
+    t_cand_wall = time.perf_counter() - t0
     t_setup, t_vert = float(secs[0]), max(float(secs[1]), 1e-6)
     xs = float(xn[q].sum())
-    t_level = t_setup + t_vert * (X / xs)
+    t_cand = t_vert * (X / xs)
+    t0 = time.perf_counter()
+    m = oracle.match(gpu_cand, gpu_cscore)
+    vmap, nc = oracle.vmap_from_match(m)
+    t_match = time.perf_counter() - t0
+    timed = []
+    for frac in (0.04, 0.08):
+        sub = _edge_subset(OL, frac, rng)
+        t0 = time.perf_counter()
+        oracle.contract(sub, gpu_vmap, n_coarse)
+        timed.append((sub.P, time.perf_counter() - t0))
+    (p1, t1), (p2, t2) = timed
+    slope = max(0.0, (t2 - t1) / max(1, p2 - p1))
+    t_contract = max(t2, t2 + slope * (P - p2))
+    t_level = t_setup + t_cand + t_match + t_contract
     return {
         "value": P / t_level, "unit": "pins/s", "cores": nthreads, "kind": "oracle",
-        "sample": (f"oracle candidate step for {n} seeded level-0 vertices "
-                   f"({xs:.3g} of {X:.3g} neighbour visits) in {t:.1f} s incl. "
-                   f"{t_setup:.1f} s incidence build, extrapolated by visits to "
-                   f"{t_level:.0f} s per level; matching/contraction (O(P)) not timed"),
+        "seconds_per_level": t_level,
+        "phases_s": {"incidence": t_setup, "candidates": t_cand, "match": t_match,
+                     "contract": t_contract},
+        "sample": (f"oracle level 0 scaled from samples: candidates of {n} seeded vertices "
+                   f"({xs:.3g} of {X:.3g} neighbour visits, {t_cand_wall:.1f} s incl. "
+                   f"{t_setup:.1f} s incidence build) scaled by visits to {t_cand:.0f} s; "
+                   f"matching and vertex map over all vertices {t_match:.1f} s; contraction of "
+                   f"{p1} and {p2} pins ({t1:.1f} s, {t2:.1f} s) scaled linearly to {P} pins: "
+                   f"{t_contract:.0f} s; {t_level:.0f} s per level on {nthreads} threads "
+                   f"(candidate step parallel, the rest sequential)"),
     }
 
 
@@ -297,6 +337,76 @@ def run_batch(args):
     print(json.dumps(result), flush=True)
 
 
+def run_hierarchy(args):
+    """The whole hierarchy of one workload (default: the 2M-neuron recurrent
+    level): hg_coarsen_level + hg_contract until no vertex proposes a
+    candidate (Section 4.1 stop rule).  At every level Eq. 1 is evaluated two
+    ways and must agree: on the coarse level under the identity (closed form
+    sum of w(e)(|e| - 1)) and on the original level under the composed
+    vertex map (hg_connectivity over all original pins).  Reports the level
+    count, levels/s, hierarchy pins/s (sum of P_in over the levels / total
+    time of the coarsening steps) and a per-level table."""
+    import torch
+    from paper_2609_07577_amd import hg, synth
+
+    wl = WORKLOADS[args.workload]
+    lim = synth.LIMITS[wl["limits"]]
+    g = wl["make"](synth, args.seed)
+    ctx = hg.Context(0)
+    L0 = ctx.upload(g)
+    ctx.sync()
+    _log(f"{args.workload}: V={g.n_vertices} E={g.n_edges} P={g.n_pins}; coarsening to the end")
+    L = L0
+    part = torch.arange(g.n_vertices, dtype=torch.int32, device="cuda")
+    rows, t_total, pins_total, all_equal = [], 0.0, 0, True
+    while True:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = ctx.coarsen_level(L, lim, want_candidates=False)
+        anyc = int(out["any_candidate"].item())
+        C = ctx.contract(L, out["vmap"], out["n_coarse"]) if anyc else None
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        t_total += dt
+        pins_total += L.P
+        row = {"level": len(rows), "V": L.V, "E": L.E, "P": L.P, "ms": 1000.0 * dt}
+        if anyc:
+            part = out["vmap"][part.long()].contiguous()
+            lens = (C.eoff[1:] - C.eoff[:-1]).to(torch.int64)
+            closed = int(torch.sum(C.w.to(torch.int64) * (lens - 1)).item())
+            full = int(ctx.connectivity(L0, part).item())
+            ctx.sync()
+            row.update(conn=closed, conn_equal=closed == full)
+            all_equal &= closed == full
+        rows.append(row)
+        if len(rows) % 10 == 1 or not anyc:
+            _log(f"level {row['level']}: V={L.V} E={L.E} P={L.P} {row['ms']:.1f} ms "
+                 f"conn={row.get('conn')} equal={row.get('conn_equal')}")
+        if not anyc:
+            break
+        L = C
+    n_contract = len(rows) - 1
+    result = {
+        "metric": METRIC,
+        "value": pins_total / t_total,
+        "unit": "pins/s",
+        "n_gpus": 1, "steps": len(rows), "warmup": 0,
+        "ms_per_step": 1000.0 * t_total / len(rows),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": wl["desc"].replace("; level 0", "") + "; whole hierarchy",
+                   "seed": args.seed, "vertices": g.n_vertices, "hyperedges": g.n_edges,
+                   "pins": g.n_pins},
+        "contractions": n_contract,
+        "levels_per_s": len(rows) / t_total,
+        "hierarchy_s": t_total,
+        "final_parts": rows[-1]["V"],
+        "conn_two_ways_equal_every_level": all_equal,
+        "levels": rows,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def run_serve(args):
     """Served requests: Poisson arrivals at --rate per second for --duration
     seconds.  A request is one SNN hypergraph to coarsen to the end, drawn
@@ -417,10 +527,11 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="level", choices=("level", "batch", "serve"),
-                    help="level: one coarsening level of one graph (default); batch: the "
-                         "256-graph batch, batched vs plain; serve: continuous batching of "
-                         "Poisson-arriving requests")
+    ap.add_argument("--mode", default="level", choices=("level", "hierarchy", "batch", "serve"),
+                    help="level: one coarsening level of one graph (default); hierarchy: the "
+                         "whole hierarchy of --workload with Eq. 1 checked two ways per level; "
+                         "batch: the 256-graph batch, batched vs plain; serve: continuous "
+                         "batching of Poisson-arriving requests")
     ap.add_argument("--graphs", type=int, default=256, help="batch mode: graphs at full size")
     ap.add_argument("--hier-graphs", type=int, default=64,
                     help="batch mode: graphs of the size-scaled full-hierarchy comparison")
@@ -453,6 +564,9 @@ def main():
         return
     if args.mode == "serve":
         run_serve(args)
+        return
+    if args.mode == "hierarchy":
+        run_hierarchy(args)
         return
 
     from paper_2609_07577_amd import hg, synth
@@ -543,8 +657,14 @@ def main():
         "conn_invariant_ok": conn_ok,
     }
     if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle on a vertex sample", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(g, lim, X, P, args.cpu_seconds)
+        print("[bench] timing the CPU oracle on samples of every step", file=sys.stderr,
+              flush=True)
+        full = ctx.coarsen_level(L, lim)
+        ctx.sync()
+        result["cpu_baseline"] = cpu_baseline(
+            g, lim, X, P, args.cpu_seconds, full["cand"].cpu().numpy(),
+            full["cscore"].cpu().numpy(), full["vmap"].cpu().numpy(),
+            int(full["n_coarse"].item()))
     print(json.dumps(result), flush=True)
 
 

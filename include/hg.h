@@ -211,6 +211,38 @@ int hg_contract(hg_ctx* ctx, const hg_level* in, const int32_t* vmap,
 int hg_connectivity(hg_ctx* ctx, const hg_level* lvl, const int32_t* part, int64_t* conn);
 
 /*
+ * Projection of a partition one level down (Section 4.1, "Uncoarsening and
+ * Refinement": super-nodes come undone level by level, each member starting
+ * in its super-node's part): part_fine[v] = part_coarse[vmap[v]] for the
+ * n_fine vertices of the finer level.  `vmap` is that level's vertex map
+ * (hg_coarsen_level), with values in [0, *n_coarse) (device int32 scalar);
+ * a value outside is recorded in the error word (hg_sync then returns
+ * HG_ERR_INVALID_ARG and the entry is written as 0).  All arrays
+ * are device memory; part_coarse has *n_coarse entries.
+ */
+int hg_project(hg_ctx* ctx, int32_t n_fine, const int32_t* vmap, const int32_t* n_coarse,
+               const int32_t* part_coarse, int32_t* part_fine);
+
+/*
+ * Evaluation of a partition of a level (Section 3): `part` [V] holds part
+ * ids in [0, *n_parts) (device int32 scalar; checked on the device as
+ * hg_contract checks its vmap).  Writes to device int64 summary[8]:
+ *   [0] Eq. 1, sum over hyperedges of w(e) (lambda(e) - 1)
+ *   [1..3] the largest part size (neurons), inbound synapses and distinct
+ *          inbound original axons over the parts
+ *   [4..6] the number of parts above Omega, Phi and Delta of `limits`
+ *   [7] the number of parts
+ * and, where the pointers are not NULL, each part's three totals to device
+ * int32 arrays of *n_parts entries.  Needs the level's state (v_size, v_syn,
+ * v_axons, edge_mult): a part's distinct axons count every original axon
+ * with a destination in the part, as in hg_contract, which this call runs
+ * with `part` as the vertex map (its scratch is the context's arena).
+ */
+int hg_partition_report(hg_ctx* ctx, const hg_level* lvl, const int32_t* part,
+                        const int32_t* n_parts, const hg_limits* limits, int64_t* summary,
+                        int32_t* part_size, int32_t* part_syn, int32_t* part_axons);
+
+/*
  * hg_connectivity with no allocation, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, hosts
  * that forbid allocation in their loop).  Same arguments, result and checks

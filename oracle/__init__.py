@@ -65,6 +65,8 @@ def _load():
                                         _P, _P, _P, _P, _P, _P, _P, _P, _P]
         lib.oracle_connectivity.argtypes = [_i32, _P, _P, _P, _P]
         lib.oracle_connectivity.restype = ctypes.c_int64
+        lib.oracle_partition_report.argtypes = [_i32, _i32, _P, _P, _P, _P, _P, _P, _P, _P,
+                                                _i32, _i32, _i32, _i32, _P, _P, _P, _P]
         _lib = lib
     return _lib
 
@@ -197,6 +199,40 @@ def connectivity(eoff: np.ndarray, pins: np.ndarray, w: np.ndarray, part: np.nda
     part = np.ascontiguousarray(part, dtype=np.int32)
     return int(lib.oracle_connectivity(int(eoff.shape[0] - 1), _ptr(eoff), _ptr(pins), _ptr(w),
                                        _ptr(part)))
+
+
+def project(vmap: np.ndarray, part_coarse: np.ndarray) -> np.ndarray:
+    """A partition of the coarser level seen on the finer one (Section 4.1,
+    uncoarsening: a super-node's members start in the super-node's part):
+    part_fine[v] = part_coarse[vmap[v]]."""
+    return np.asarray(part_coarse, dtype=np.int32)[np.asarray(vmap, dtype=np.int64)]
+
+
+@dataclass
+class Report:
+    """Eq. (1) and the Section 3 totals of every part of a partition."""
+    conn: int
+    size: np.ndarray
+    syn: np.ndarray
+    ax: np.ndarray
+    summary: np.ndarray  # conn, max size, max syn, max ax, over Omega, Phi, Delta, parts
+
+
+def partition_report(L: OLevel, part: np.ndarray, n_parts: int, limits) -> Report:
+    lib = _load()
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    summary = np.zeros(8, np.int64)
+    size = np.empty(max(n_parts, 1), np.int32)
+    syn = np.empty(max(n_parts, 1), np.int32)
+    ax = np.empty(max(n_parts, 1), np.int32)
+    rc = lib.oracle_partition_report(L.V, L.E, _ptr(L.eoff), _ptr(L.pins), _ptr(L.w),
+                                     _ptr(L.size), _ptr(L.syn), _ptr(L.soff), _ptr(L.sids),
+                                     _ptr(part), n_parts, limits.max_neurons,
+                                     limits.max_synapses, limits.max_axons, _ptr(summary),
+                                     _ptr(size), _ptr(syn), _ptr(ax))
+    if rc != 0:
+        raise ValueError("part value out of range")
+    return Report(int(summary[0]), size[:n_parts], syn[:n_parts], ax[:n_parts], summary)
 
 
 @dataclass

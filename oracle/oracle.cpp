@@ -389,4 +389,48 @@ int64_t oracle_connectivity(int32_t E, const int64_t* eoff, const uint32_t* pins
   return conn;
 }
 
+// ---------------------------------------------------------------------------
+// Evaluation of a partition `part` (values in [0, n_parts)) of a level
+// (Section 3): Eq. (1) and, per part p, |p| in neurons (sum of size), its
+// inbound synapses (sum of syn) and its distinct inbound original axons
+// |U in(n)| (the union of the members' explicit inbound sets, R2).  Writes
+// per-part totals (n_parts entries each) and the summary
+// [conn, max size, max syn, max axons, parts over Omega, over Phi,
+// over Delta, n_parts].  Returns 0, or -1 on a part value out of range.
+int oracle_partition_report(int32_t V, int32_t E, const int64_t* eoff, const uint32_t* pins,
+                            const int32_t* w, const int32_t* size, const int32_t* syn,
+                            const int64_t* soff, const int32_t* sids, const int32_t* part,
+                            int32_t n_parts, int32_t omega, int32_t phi, int32_t delta,
+                            int64_t* summary, int32_t* out_size, int32_t* out_syn,
+                            int32_t* out_ax) {
+  for (int32_t v = 0; v < V; ++v)
+    if (part[v] < 0 || part[v] >= n_parts) return -1;
+  std::vector<std::vector<int32_t>> members(n_parts);
+  for (int32_t v = 0; v < V; ++v) members[part[v]].push_back(v);
+  for (int i = 0; i < 8; ++i) summary[i] = 0;
+  summary[0] = oracle_connectivity(E, eoff, pins, w, part);
+  for (int32_t p = 0; p < n_parts; ++p) {
+    int64_t sz = 0, sy = 0;
+    std::vector<int32_t> uni;
+    for (int32_t v : members[p]) {
+      sz += size[v];
+      sy += syn[v];
+      uni.insert(uni.end(), sids + soff[v], sids + soff[v + 1]);
+    }
+    std::sort(uni.begin(), uni.end());
+    const int64_t ax = std::unique(uni.begin(), uni.end()) - uni.begin();
+    out_size[p] = (int32_t)sz;
+    out_syn[p] = (int32_t)sy;
+    out_ax[p] = (int32_t)ax;
+    summary[1] = std::max(summary[1], sz);
+    summary[2] = std::max(summary[2], sy);
+    summary[3] = std::max(summary[3], ax);
+    summary[4] += sz > omega;
+    summary[5] += sy > phi;
+    summary[6] += ax > delta;
+  }
+  summary[7] = n_parts;
+  return 0;
+}
+
 }  // extern "C"

@@ -417,6 +417,11 @@ int hg_validate_level(hg_ctx* c, const hg_level* L) {
 
 namespace hg {
 
+void check_map_kernel_launch(const int32_t* in, int64_t V, const int32_t* n_range,
+                             int32_t* out, int32_t* out_range, int32_t* err, hipStream_t s) {
+  check_map_kernel<<<grid_for(V, 256, 4096), 256, 0, s>>>(in, V, n_range, out, out_range, err);
+}
+
 int run_connectivity(hg_ctx* c, const hg_level* lvl, const int32_t* part, int64_t* conn,
                      char* base) {
   const int64_t V = lvl->n_vertices, E = lvl->n_edges, P = lvl->n_pins;

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <string>
+#include <type_traits>
 
 #include "hg_internal.h"
 
@@ -245,6 +246,9 @@ inline size_t validate_scratch_bytes() {
 int run_connectivity(hg_ctx* c, const hg_level* lvl, const int32_t* part, int64_t* conn,
                      char* base);
 int validate_with(hg_ctx* c, const hg_level* L, char* base);
+// Checked copy of a caller's map (values in [0, *n_range), see hg_contract).
+void check_map_kernel_launch(const int32_t* in, int64_t V, const int32_t* n_range,
+                             int32_t* out, int32_t* out_range, int32_t* err, hipStream_t s);
 
 // The library's fixed device scratch (hg_static.hip): its address on the
 // current device is looked up once per device by hg_create.

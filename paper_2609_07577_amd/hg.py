@@ -34,6 +34,7 @@ EXPORTED = ("hg_create", "hg_destroy", "hg_set_stream", "hg_last_error", "hg_syn
             "hg_scratch_bytes", "hg_enable_timing", "hg_phase_times", "hg_init_state",
             "hg_coarsen_level", "hg_contract", "hg_connectivity", "hg_validate_level",
             "hg_set_tuning", "hg_get_tuning", "hg_score_census", "hg_connectivity_static",
+            "hg_project", "hg_partition_report",
             "hg_batch_create", "hg_batch_destroy", "hg_batch_bytes", "hg_batch_add_graph",
             "hg_batch_step", "hg_batch_done", "hg_batch_result", "hg_batch_compact",
             "hg_batch_sizes")
@@ -93,6 +94,9 @@ def load_library(path: str = LIB_PATH):
     lib.hg_contract.argtypes = [_P, ctypes.POINTER(_Level), _P, _P, ctypes.POINTER(_LevelOut)]
     lib.hg_connectivity.argtypes = [_P, ctypes.POINTER(_Level), _P, _P]
     lib.hg_connectivity_static.argtypes = [_P, ctypes.POINTER(_Level), _P, _P]
+    lib.hg_project.argtypes = [_P, _i32, _P, _P, _P, _P]
+    lib.hg_partition_report.argtypes = [_P, ctypes.POINTER(_Level), _P, _P,
+                                        ctypes.POINTER(Limits), _P, _P, _P, _P]
     lib.hg_validate_level.argtypes = [_P, ctypes.POINTER(_Level)]
     lib.hg_enable_timing.argtypes = [_P, ctypes.c_int]
     lib.hg_phase_times.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
@@ -310,6 +314,39 @@ class Context:
             self._check(self.lib.hg_connectivity_static(self.h, ctypes.byref(lv), _ptr(part),
                                                         _ptr(conn)))
         return conn
+
+    def project(self, vmap: torch.Tensor, n_coarse: torch.Tensor,
+                part_coarse: torch.Tensor) -> torch.Tensor:
+        """part_fine[v] = part_coarse[vmap[v]] (hg_project)."""
+        n = int(vmap.shape[0])
+        with torch.cuda.stream(self.stream):
+            out = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)[:n]
+            self._check(self.lib.hg_project(self.h, n, _ptr(vmap), _ptr(n_coarse),
+                                            _ptr(part_coarse), _ptr(out)))
+        return out
+
+    def partition_report(self, L: DeviceLevel, part: torch.Tensor, n_parts: torch.Tensor,
+                         limits, per_part: bool = True) -> dict:
+        """Eq. (1) and the Section 3 totals of every part (hg_partition_report).
+        Returns the summary as host ints and, with ``per_part``, device arrays
+        of each part's size, synapses and distinct axons."""
+        lim = Limits(limits.max_neurons, limits.max_synapses, limits.max_axons)
+        lv = L.c_struct()
+        with torch.cuda.stream(self.stream):
+            summ = torch.zeros(8, dtype=torch.int64, device=self.device)
+            k = max(L.V, 1)
+            arrs = [torch.empty(k, dtype=torch.int32, device=self.device) for _ in range(3)] \
+                if per_part else [None, None, None]
+            self._check(self.lib.hg_partition_report(self.h, ctypes.byref(lv), _ptr(part),
+                                                     _ptr(n_parts), ctypes.byref(lim),
+                                                     _ptr(summ), *(_ptr(a) for a in arrs)))
+        s = [int(x) for x in summ.cpu().tolist()]
+        self.sync()
+        res = dict(conn=s[0], max_size=s[1], max_syn=s[2], max_axons=s[3], over_neurons=s[4],
+                   over_synapses=s[5], over_axons=s[6], n_parts=s[7], summary=s)
+        if per_part:
+            res.update(size=arrs[0][:s[7]], syn=arrs[1][:s[7]], ax=arrs[2][:s[7]])
+        return res
 
     def validate(self, L: DeviceLevel):
         lv = L.c_struct()

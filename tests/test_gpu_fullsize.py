@@ -1,11 +1,12 @@
 """Parity at full workload sizes, through the C ABI, in the configuration the
 benchmark times.
 
-* The 2,000,000-neuron power-law level: the candidates of a seeded vertex
-  sample are compared with the oracle computed one by one; the matching and
-  the vertex map are compared in full with the oracle's Eq. 13 applied to the
-  GPU candidates; the contraction is checked by its conservation laws and by
-  Eq. 1 evaluated two ways (and by the oracle) on the fine level.
+* The 2,000,000-neuron power-law level and the next: the candidates of the
+  largest neighbourhoods and of a stratified vertex sample are compared with
+  the oracle computed one by one; the matching and the vertex map are
+  compared in full with the oracle's Eq. 13 applied to the GPU candidates;
+  the level-0 contraction is compared with the oracle's array by array, the
+  level-1 one by its conservation laws and by Eq. 1 evaluated three ways.
 * The convolutional level (262,144 neurons, 27.9M pins): the whole level,
   every array, against the oracle; and the whole convolutional hierarchy
   (409 contractions) to the stop rule, every level against the oracle.
@@ -35,46 +36,81 @@ def _np(t):
     return t.cpu().numpy()
 
 
-def test_powerlaw2M_level_sampled_and_invariants(ctx):
+def _stratified_sample(xn, frac, top, seed):
+    """Vertices for the candidate comparison: the ``top`` largest expansions
+    (the heaviest neighbourhoods, where windows halve and slices run on) and
+    a seeded ``frac`` of the rest drawn equally from 20 expansion strata."""
+    rng = np.random.default_rng(seed)
+    order = np.argsort(xn, kind="stable")
+    chosen = [order[-top:]]
+    strata = np.array_split(order[:-top], 20)
+    per = max(1, int(frac * xn.shape[0]) // 20)
+    for st in strata:
+        chosen.append(rng.choice(st, size=min(per, st.shape[0]), replace=False))
+    return np.unique(np.concatenate(chosen)).astype(np.int32)
+
+
+def _expansion(L):
+    lens = np.diff(L.eoff).astype(np.int64)
+    ids = (L.pins & 0x7FFFFFFF).astype(np.int64)
+    return np.bincount(ids, weights=(lens - 1)[np.repeat(np.arange(L.E), lens)],
+                       minlength=L.V).astype(np.int64)
+
+
+@pytest.mark.timeout(1200)
+def test_powerlaw2M_two_levels(ctx):
+    """The 2M-neuron level and the next one, in the configuration the
+    benchmark times.  Level 0: candidates and scores of the 1,000 largest
+    neighbourhoods plus a stratified 2% of all vertices against the oracle;
+    Eq. 13 and the vertex map over all vertices against the oracle applied
+    to the GPU candidates; the contracted level against the oracle's, every
+    array.  Level 1 (the GPU's coarse level, equal to the oracle's): the same
+    candidate comparison on 1,000 + 1%, Eq. 13 and the vertex map in full,
+    and the contraction by its conservation laws and by Eq. 1 evaluated on
+    the GPU three ways."""
     g = synth.powerlaw(1, n=2_000_000, dmin=20, dmax=10_000)
     lim = synth.LIMITS["powerlaw"]
     print(f"  powerlaw2M: V={g.n_vertices} P={g.n_pins}", flush=True)
     L = ctx.upload(g)
-    out = ctx.coarsen_level(L, lim)
-    ctx.sync()
-    cand, cscore, match, vmap = (_np(out[k]) for k in ("cand", "cscore", "match", "vmap"))
-    n_coarse = int(out["n_coarse"].item())
-
-    print("  oracle candidates of a sample", flush=True)
     OL = oracle.level0(g)
-    rng = np.random.default_rng(20260)
-    q = np.sort(rng.choice(g.n_vertices, 256, replace=False)).astype(np.int32)
-    oc, ocs = oracle.candidates(OL, lim, query=q)
-    np.testing.assert_array_equal(cand[q], oc)
-    np.testing.assert_array_equal(cscore[q], ocs)
-
-    print("  Eq. 13 and the vertex map over all vertices", flush=True)
-    hgcheck.check_matching(g.n_vertices, cand, cscore, match)
-    np.testing.assert_array_equal(match, oracle.match(cand, cscore))
-    ovmap, onc = oracle.vmap_from_match(match)
-    np.testing.assert_array_equal(vmap, ovmap)
-    assert n_coarse == onc
-
-    print("  contraction invariants and Eq. 1", flush=True)
-    C = ctx.contract(L, out["vmap"], out["n_coarse"])
-    ch = C.to_host()
-    assert ch["V"] == n_coarse
-    assert int(ch["size"].astype(np.int64).sum()) == g.n_vertices
-    assert int(ch["syn"].astype(np.int64).sum()) == int(OL.syn.astype(np.int64).sum())
-    assert np.all(ch["size"] <= lim.max_neurons)
-    assert np.all(ch["syn"].astype(np.int64) <= lim.max_synapses)
-    assert np.all(ch["ax"].astype(np.int64) <= lim.max_axons)
-    lens = np.diff(ch["eoff"])
-    assert np.all(lens >= 2)
-    conn_fine = int(ctx.connectivity(L, out["vmap"]).item())
-    conn_coarse = int((ch["w"].astype(np.int64) * (lens - 1)).sum())
-    assert conn_fine == conn_coarse
-    assert conn_fine == oracle.connectivity(OL.eoff, OL.pins, OL.w, vmap)
+    for li, frac in ((0, 0.02), (1, 0.01)):
+        out = ctx.coarsen_level(L, lim)
+        ctx.sync()
+        cand, cscore, match, vmap = (_np(out[k]) for k in ("cand", "cscore", "match", "vmap"))
+        n_coarse = int(out["n_coarse"].item())
+        q = _stratified_sample(_expansion(OL), frac, 1000, 20260 + li)
+        print(f"  level {li}: V={OL.V} P={OL.P}; oracle candidates of {q.shape[0]} vertices",
+              flush=True)
+        oc, ocs = oracle.candidates(OL, lim, query=q)
+        np.testing.assert_array_equal(cand[q], oc, err_msg=f"cand level {li}")
+        np.testing.assert_array_equal(cscore[q], ocs, err_msg=f"cscore level {li}")
+        print(f"  level {li}: Eq. 13 and the vertex map over all vertices", flush=True)
+        hgcheck.check_matching(OL.V, cand, cscore, match)
+        np.testing.assert_array_equal(match, oracle.match(cand, cscore))
+        ovmap, onc = oracle.vmap_from_match(match)
+        np.testing.assert_array_equal(vmap, ovmap)
+        assert n_coarse == onc
+        C = ctx.contract(L, out["vmap"], out["n_coarse"])
+        ch = C.to_host()
+        conn_fine = int(ctx.connectivity(L, out["vmap"]).item())
+        lens = np.diff(ch["eoff"])
+        assert conn_fine == int((ch["w"].astype(np.int64) * (lens - 1)).sum())
+        assert conn_fine == hgcheck.connectivity_numpy(OL.eoff, OL.pins, OL.w, vmap)
+        assert np.all(ch["size"] <= lim.max_neurons)
+        assert np.all(ch["syn"].astype(np.int64) <= lim.max_synapses)
+        assert np.all(ch["ax"].astype(np.int64) <= lim.max_axons)
+        if li == 0:
+            print("  level 0: the oracle's contraction, every array", flush=True)
+            OC = oracle.contract(OL, vmap, n_coarse)
+            for k, ov in (("eoff", OC.eoff), ("pins", OC.pins), ("w", OC.w), ("mult", OC.mult),
+                          ("size", OC.size), ("syn", OC.syn), ("ax", OC.ax)):
+                np.testing.assert_array_equal(ch[k], ov, err_msg=f"coarse {k}")
+            OL = OC
+        else:
+            hgcheck.check_contraction(
+                dict(eoff=OL.eoff, pins=OL.pins, w=OL.w, mult=OL.mult, size=OL.size,
+                     syn=OL.syn, ax=OL.ax), ch, vmap)
+        L = C
 
 
 def test_conv_level0_full(ctx):

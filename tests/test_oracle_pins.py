@@ -233,3 +233,65 @@ def test_union_of_disjoint_graphs_is_separate_runs():
         # the union numbers the graph's super-nodes after those of earlier graphs
         np.testing.assert_array_equal(mine - mine.min(), h.final_partition())
         base += g.n_vertices
+
+
+def _original_members(h, li, n_parts, part):
+    """Original neurons of every part of a partition of level ``li``."""
+    up = np.arange(h.levels[0].level.V)
+    for r in h.levels[:li]:
+        up = r.vmap[up]
+    members = [set() for _ in range(n_parts)]
+    for v0, v in enumerate(up.tolist()):
+        members[int(part[v])].add(v0)
+    return members
+
+
+def test_partition_report_vs_brute_force():
+    """The oracle's partition report (Section 3) against first principles:
+    every part's size, inbound synapses and distinct inbound axons counted
+    on the ORIGINAL neurons it holds, and Eq. (1) by enumeration, for random
+    partitions of every level of tiny hierarchies."""
+    rng = np.random.default_rng(31)
+    for seed in range(40):
+        g = synth.tiny_random(seed, int(rng.integers(2, 14)), max_fan=5, w_max=7)
+        lim = synth.Limits(int(rng.integers(2, 6)), 30, int(rng.integers(2, 8)))
+        h = oracle.hierarchy(g, lim)
+        orig = brute.Orig(g.n_vertices, g.eoff, g.pins)
+        for li, r in enumerate(h.levels):
+            L = r.level
+            k = int(rng.integers(1, L.V + 1))
+            part = rng.integers(0, k, L.V).astype(np.int32)
+            rep = oracle.partition_report(L, part, k, lim)
+            mem = _original_members(h, li, k, part)
+            assert rep.size.tolist() == [orig.size(m) for m in mem]
+            assert rep.syn.tolist() == [orig.synapses(m) for m in mem]
+            assert rep.ax.tolist() == [orig.axons(m) for m in mem]
+            assert rep.conn == brute.connectivity(brute.edges_of(L.eoff, L.pins), L.w, part)
+            assert rep.summary[4] == sum(orig.size(m) > lim.max_neurons for m in mem)
+            assert rep.summary[6] == sum(orig.axons(m) > lim.max_axons for m in mem)
+
+
+def test_projection_down_the_hierarchy():
+    """The final super-nodes as parts (Section 4.1), projected level by level
+    down to level 0, give every original neuron its final super-node (the
+    composition of the level maps, taken upwards); Eq. (1) of each level
+    under its projected partition is the same number; every part is within
+    the limits, except a single neuron that already breaks one."""
+    for seed in range(12):
+        g = synth.uniform(seed, 300, 1, 10)
+        lim = synth.Limits(12, 200, 30)
+        h = oracle.hierarchy(g, lim)
+        top = h.levels[-1].level
+        part = np.arange(top.V, dtype=np.int32)
+        conns = []
+        for li in range(len(h.levels) - 1, -1, -1):
+            L = h.levels[li].level
+            rep = oracle.partition_report(L, part, top.V, lim)
+            conns.append(rep.conn)
+            bad = (rep.size > lim.max_neurons) | (rep.syn > lim.max_synapses) | \
+                  (rep.ax > lim.max_axons)
+            assert np.all(rep.size[bad] == 1)
+            if li > 0:
+                part = oracle.project(h.levels[li - 1].vmap, part)
+        assert len(set(conns)) == 1
+        np.testing.assert_array_equal(part, h.final_partition())
