@@ -67,6 +67,8 @@ def _load():
         lib.oracle_connectivity.restype = ctypes.c_int64
         lib.oracle_partition_report.argtypes = [_i32, _i32, _P, _P, _P, _P, _P, _P, _P, _P,
                                                 _i32, _i32, _i32, _i32, _P, _P, _P, _P]
+        lib.oracle_refine_round.argtypes = [_i32, _i32, _P, _P, _P, _P, _P, _P, _P, _P, _i32,
+                                            _i32, _i32, _i32, _P]
         _lib = lib
     return _lib
 
@@ -233,6 +235,55 @@ def partition_report(L: OLevel, part: np.ndarray, n_parts: int, limits) -> Repor
     if rc != 0:
         raise ValueError("part value out of range")
     return Report(int(summary[0]), size[:n_parts], syn[:n_parts], ax[:n_parts], summary)
+
+
+def refine_round(L: OLevel, part: np.ndarray, n_parts: int, limits):
+    """One refinement round (Section 4.1, "Uncoarsening and Refinement") on a
+    copy of ``part``.  Returns (new part, [proposals, moves applied, Eq. (1)
+    decrease])."""
+    lib = _load()
+    out = np.array(part, dtype=np.int32, copy=True)
+    ax = np.ascontiguousarray(L.ax, dtype=np.int32)
+    info = np.zeros(3, np.int64)
+    rc = lib.oracle_refine_round(L.V, L.E, _ptr(L.eoff), _ptr(L.pins), _ptr(L.w), _ptr(L.mult),
+                                 _ptr(L.size), _ptr(L.syn), _ptr(ax), _ptr(out), n_parts,
+                                 limits.max_neurons, limits.max_synapses, limits.max_axons,
+                                 _ptr(info))
+    if rc != 0:
+        raise ValueError("part value out of range")
+    return out, info
+
+
+def refine(L: OLevel, part: np.ndarray, n_parts: int, limits, max_rounds: int = 16):
+    """Refinement rounds on one level until a round moves nothing (at most
+    ``max_rounds``).  Returns (part, rounds run, total Eq. (1) decrease)."""
+    total, rounds = 0, 0
+    for _ in range(max_rounds):
+        part, info = refine_round(L, part, n_parts, limits)
+        rounds += 1
+        total += int(info[2])
+        if info[1] == 0:
+            break
+    return part, rounds, total
+
+
+def uncoarsen(h: "Hierarchy", limits, max_rounds: int = 16):
+    """The uncoarsening of a hierarchy: the final super-nodes as initial
+    parts, then level by level down to level 0, projection and refinement.
+    Returns (level-0 partition, number of parts, per-level list of
+    (level, Eq. (1) after projection, Eq. (1) after refinement, rounds))."""
+    top = h.levels[-1].level
+    n_parts = top.V
+    part = np.arange(n_parts, dtype=np.int32)
+    trace = []
+    for li in range(len(h.levels) - 1, -1, -1):
+        L = h.levels[li].level
+        if li < len(h.levels) - 1:
+            part = project(h.levels[li].vmap, part)
+        before = connectivity(L.eoff, L.pins, L.w, part)
+        part, rounds, dec = refine(L, part, n_parts, limits, max_rounds)
+        trace.append((li, before, before - dec, rounds))
+    return part, n_parts, trace
 
 
 @dataclass

@@ -433,4 +433,146 @@ int oracle_partition_report(int32_t V, int32_t E, const int64_t* eoff, const uin
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// One refinement round on a level (Section 4.1, "Uncoarsening and
+// Refinement"), written step by step as the paper states it.  `part` (values
+// in [0, n_parts)) is updated in place.  Readings (design notes R8-R12):
+//   R8  the parts a vertex may move to are those sharing a hyperedge with it
+//       (any other part has loss(n, p) = the vertex's whole incident weight);
+//   R9  every vertex with a feasible target proposes its best move, whatever
+//       the sign of its gain; best = largest gain, then lowest part id;
+//   R10 moves are ordered by gain (descending), then vertex id (ascending);
+//   R11 a prefix is valid when no part that was within a limit before the
+//       round is above it after the prefix's moves; the chosen prefix has
+//       the largest cumulative recomputed gain among valid prefixes with a
+//       positive one (the shortest on ties); no prefix, no move;
+//   R12 "inbound" for a part: a hyperedge is inbound to p when p holds one
+//       of its destination-flagged pins; the distinct axons of p are the
+//       members' axons already internal to them plus the multiplicities of
+//       the hyperedges inbound to p (the same count as the level's state).
+// Writes info = [proposals, moves applied, Eq. (1) decrease].  Returns 0, or
+// -1 on a part value out of range.
+int oracle_refine_round(int32_t V, int32_t E, const int64_t* eoff, const uint32_t* pins,
+                        const int32_t* w, const int32_t* mult, const int32_t* size,
+                        const int32_t* syn, const int32_t* ax, int32_t* part, int32_t n_parts,
+                        int32_t omega, int32_t phi, int32_t delta, int64_t* info) {
+  for (int32_t v = 0; v < V; ++v)
+    if (part[v] < 0 || part[v] >= n_parts) return -1;
+  Incidence inc = build_incidence(V, E, eoff, pins);
+  // pins(p, e) and the destination-flagged pins of p in e
+  std::vector<std::map<int32_t, int64_t>> pc(E), dpc(E);
+  for (int32_t e = 0; e < E; ++e)
+    for (int64_t k = eoff[e]; k < eoff[e + 1]; ++k) {
+      int32_t v = (int32_t)(pins[k] & IDMASK);
+      pc[e][part[v]] += 1;
+      if (pins[k] & DST) dpc[e][part[v]] += 1;
+    }
+  // per-vertex axons internal to the vertex (not on any flagged pin)
+  std::vector<int64_t> internal(V);
+  for (int32_t v = 0; v < V; ++v) {
+    int64_t flagged = 0;
+    for (int64_t j = inc.off[v]; j < inc.off[v + 1]; ++j)
+      if (inc.is_dst[j]) flagged += mult[inc.edge[j]];
+    internal[v] = ax[v] - flagged;
+  }
+  // part state
+  std::vector<int64_t> psize(n_parts, 0), psyn(n_parts, 0), pax(n_parts, 0);
+  for (int32_t v = 0; v < V; ++v) {
+    psize[part[v]] += size[v];
+    psyn[part[v]] += syn[v];
+    pax[part[v]] += internal[v];
+  }
+  for (int32_t e = 0; e < E; ++e)
+    for (auto& kv : dpc[e])
+      if (kv.second > 0) pax[kv.first] += mult[e];
+  // proposals: save(n), loss(n, p), the best feasible move
+  struct Move {
+    int64_t gain;
+    int32_t n, from, to;
+  };
+  std::vector<Move> moves;
+  for (int32_t n = 0; n < V; ++n) {
+    const int32_t a = part[n];
+    int64_t save = 0, whole = 0;
+    std::map<int32_t, int64_t> touch, hit;  // part -> weight with pins > 0; flagged overlap
+    for (int64_t j = inc.off[n]; j < inc.off[n + 1]; ++j) {
+      const int32_t e = inc.edge[j];
+      whole += w[e];
+      if (pc[e][a] == 1) save += w[e];
+      for (auto& kv : pc[e]) {
+        if (kv.first == a || kv.second == 0) continue;
+        touch[kv.first] += w[e];
+        if (inc.is_dst[j] && dpc[e].count(kv.first) && dpc[e][kv.first] > 0)
+          hit[kv.first] += mult[e];
+      }
+    }
+    bool found = false;
+    Move best{0, n, a, -1};
+    for (auto& kv : touch) {
+      const int32_t p = kv.first;
+      const int64_t loss = whole - kv.second;
+      const int64_t gain = save - loss;
+      const int64_t h = hit.count(p) ? hit[p] : 0;
+      const bool ok = psize[p] + size[n] <= omega && psyn[p] + syn[n] <= phi &&
+                      pax[p] + ax[n] - h <= delta;
+      if (!ok) continue;
+      if (!found || gain > best.gain) {  // parts visited in ascending order
+        best = Move{gain, n, a, p};
+        found = true;
+      }
+    }
+    if (found) moves.push_back(best);
+  }
+  std::sort(moves.begin(), moves.end(), [](const Move& x, const Move& y) {
+    return x.gain != y.gain ? x.gain > y.gain : x.n < y.n;
+  });
+  // the prefixes, applied one move at a time: recomputed gains and validity
+  std::vector<uint8_t> within(3 * (size_t)n_parts);
+  for (int32_t p = 0; p < n_parts; ++p) {
+    within[3 * p] = psize[p] <= omega;
+    within[3 * p + 1] = psyn[p] <= phi;
+    within[3 * p + 2] = pax[p] <= delta;
+  }
+  auto over = [&](int32_t p) {
+    return (within[3 * p] && psize[p] > omega) || (within[3 * p + 1] && psyn[p] > phi) ||
+           (within[3 * p + 2] && pax[p] > delta);
+  };
+  int64_t newly_over = 0, cum = 0, best_cum = 0;
+  int64_t best_len = 0;
+  for (size_t i = 0; i < moves.size(); ++i) {
+    const Move& m = moves[i];
+    const int32_t a = m.from, b = m.to;
+    newly_over -= over(a) + over(b);
+    int64_t g = 0;
+    for (int64_t j = inc.off[m.n]; j < inc.off[m.n + 1]; ++j) {
+      const int32_t e = inc.edge[j];
+      if (pc[e][a] == 1) g += w[e];
+      if (pc[e][b] == 0) g -= w[e];
+      pc[e][a] -= 1;
+      pc[e][b] += 1;
+      if (inc.is_dst[j]) {
+        if (--dpc[e][a] == 0) pax[a] -= mult[e];
+        if (dpc[e][b]++ == 0) pax[b] += mult[e];
+      }
+    }
+    psize[a] -= size[m.n];
+    psize[b] += size[m.n];
+    psyn[a] -= syn[m.n];
+    psyn[b] += syn[m.n];
+    pax[a] -= internal[m.n];
+    pax[b] += internal[m.n];
+    newly_over += over(a) + over(b);
+    cum += g;
+    if (newly_over == 0 && cum > 0 && cum > best_cum) {
+      best_cum = cum;
+      best_len = (int64_t)i + 1;
+    }
+  }
+  for (int64_t i = 0; i < best_len; ++i) part[moves[i].n] = moves[i].to;
+  info[0] = (int64_t)moves.size();
+  info[1] = best_len;
+  info[2] = best_cum;
+  return 0;
+}
+
 }  // extern "C"

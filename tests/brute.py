@@ -204,3 +204,65 @@ def hierarchy(n_vertices, eoff, pins, weight, lim, max_levels=64):
         edges, w, mult = contract(edges, w, mult, vmap)
         V = nc
     return out, orig
+
+
+def refine_round(level_edges, w, part, n_parts, members, orig, lim):
+    """One refinement round (Section 4.1, "Uncoarsening and Refinement") by
+    enumeration.  ``level_edges``: the level's hyperedges (vertex, flag)
+    lists; ``members``: the original neurons of every level vertex; every
+    limit is evaluated on original neurons (``orig``).  Each gain is the
+    drop of Eq. (1) recomputed from scratch.  Returns (new part, [proposals,
+    moves applied, Eq. (1) decrease])."""
+    V = len(members)
+    part = [int(x) for x in part]
+
+    def conn(pt):
+        return connectivity(level_edges, w, pt)
+
+    def orig_members(pt):
+        mem = [set() for _ in range(n_parts)]
+        for v in range(V):
+            mem[pt[v]] |= members[v]
+        return mem
+
+    base = conn(part)
+    mem0 = orig_members(part)
+    within0 = [(orig.size(m) <= lim.max_neurons, orig.synapses(m) <= lim.max_synapses,
+                orig.axons(m) <= lim.max_axons) for m in mem0]
+    moves = []
+    for n in range(V):
+        a = part[n]
+        adj = set()
+        for pl in level_edges:
+            vs = [v for v, _ in pl]
+            if n in vs:
+                adj |= {part[v] for v in vs}
+        adj.discard(a)
+        best = None
+        for p in sorted(adj):
+            if not orig.feasible(mem0[p] | members[n], lim):
+                continue
+            pt = list(part)
+            pt[n] = p
+            gain = base - conn(pt)
+            if best is None or gain > best[0]:
+                best = (gain, n, a, p)
+        if best is not None:
+            moves.append(best)
+    moves.sort(key=lambda m: (-m[0], m[1]))
+    best_cum, best_len = 0, 0
+    pt = list(part)
+    for i, (_, n, a, p) in enumerate(moves):
+        pt[n] = p
+        cum = base - conn(pt)
+        mem = orig_members(pt)
+        ok = all(not (within0[q][0] and orig.size(mem[q]) > lim.max_neurons)
+                 and not (within0[q][1] and orig.synapses(mem[q]) > lim.max_synapses)
+                 and not (within0[q][2] and orig.axons(mem[q]) > lim.max_axons)
+                 for q in range(n_parts))
+        if ok and cum > 0 and cum > best_cum:
+            best_cum, best_len = cum, i + 1
+    out = list(part)
+    for _, n, a, p in moves[:best_len]:
+        out[n] = p
+    return out, [len(moves), best_len, best_cum]

@@ -295,3 +295,67 @@ def test_projection_down_the_hierarchy():
                 part = oracle.project(h.levels[li - 1].vmap, part)
         assert len(set(conns)) == 1
         np.testing.assert_array_equal(part, h.final_partition())
+
+
+def _level_members(h, li):
+    """Original neurons of every vertex of level ``li``."""
+    up = np.arange(h.levels[0].level.V)
+    for r in h.levels[:li]:
+        up = r.vmap[up]
+    mem = [set() for _ in range(h.levels[li].level.V)]
+    for v0, v in enumerate(up.tolist()):
+        mem[int(v)].add(v0)
+    return mem
+
+
+@pytest.mark.parametrize("block", range(4))
+def test_refine_round_vs_brute_force(block):
+    """The oracle's refinement round against enumeration: every proposal's
+    gain is the drop of Eq. (1) recomputed from scratch, every limit is
+    checked on the original neurons of a part, every prefix is applied and
+    evaluated from scratch; the chosen prefix and the new partition must be
+    the same.  Tiny hierarchies at every level, with the projected partition
+    of the final super-nodes and with random partitions."""
+    rng = np.random.default_rng(400 + block)
+    for it in range(40):
+        g = synth.tiny_random(int(rng.integers(0, 1 << 30)), int(rng.integers(2, 13)),
+                              p_axon=float(rng.uniform(0.4, 1.0)), max_fan=5,
+                              w_max=int(rng.integers(1, 6)))
+        lim = synth.Limits(int(rng.integers(2, 6)), int(rng.integers(2, 25)),
+                           int(rng.integers(1, 8)))
+        h = oracle.hierarchy(g, lim)
+        orig = brute.Orig(g.n_vertices, g.eoff, g.pins)
+        top = h.levels[-1].level.V
+        proj = np.arange(top, dtype=np.int32)
+        for li in range(len(h.levels) - 1, -1, -1):
+            L = h.levels[li].level
+            if li < len(h.levels) - 1:
+                proj = oracle.project(h.levels[li].vmap, proj)
+            mem = _level_members(h, li)
+            edges = brute.edges_of(L.eoff, L.pins)
+            k = int(rng.integers(1, L.V + 1))
+            for part, n_parts in ((proj, top), (rng.integers(0, k, L.V).astype(np.int32), k)):
+                got, info = oracle.refine_round(L, part, n_parts, lim)
+                exp, einfo = brute.refine_round(edges, L.w, part, n_parts, mem, orig, lim)
+                assert got.tolist() == exp, (it, li)
+                assert info.tolist() == einfo, (it, li)
+
+
+def test_refinement_never_worsens_and_keeps_limits():
+    """Whole uncoarsening (projection and refinement rounds down to level 0):
+    Eq. (1) never rises, the level-0 result is at most that of the final
+    super-nodes, and every part that was within the limits stays so."""
+    for seed in range(6):
+        g = synth.uniform(seed, 400, 1, 12)
+        lim = synth.Limits(16, 300, 40)
+        h = oracle.hierarchy(g, lim)
+        part, n_parts, trace = oracle.uncoarsen(h, lim)
+        for li, before, after, rounds in trace:
+            assert after <= before
+        L0 = h.levels[0].level
+        assert trace[-1][2] == oracle.connectivity(L0.eoff, L0.pins, L0.w, part)
+        assert trace[-1][2] <= trace[0][1]
+        rep = oracle.partition_report(L0, part, n_parts, lim)
+        bad = (rep.size > lim.max_neurons) | (rep.syn > lim.max_synapses) | \
+              (rep.ax > lim.max_axons)
+        assert np.all(rep.size[bad] <= 1)
