@@ -243,6 +243,34 @@ int hg_partition_report(hg_ctx* ctx, const hg_level* lvl, const int32_t* part,
                         int32_t* part_size, int32_t* part_syn, int32_t* part_axons);
 
 /*
+ * Refinement of a partition on one level (Section 4.1, "Uncoarsening and
+ * Refinement").  `part` [V] (device int32, values in [0, n_parts), checked
+ * on the device as hg_contract checks its vmap) is refined in place, in
+ * rounds of:
+ *   * pins(p, e), and per vertex n in part A: save(n) = weight of its
+ *     hyperedges in which n is A's only pin, loss(n, p) = weight of its
+ *     hyperedges without a pin in p, for every part p sharing a hyperedge
+ *     with n; gain = save - loss; each vertex proposes its best move whose
+ *     target stays within `limits` with n added (largest gain, lowest part);
+ *   * the moves sorted by gain (descending), vertex (ascending); each gain
+ *     recomputed as if the moves before it were applied; the prefix sums of
+ *     the recomputed gains; per move, the limits crossed by the part totals
+ *     (neurons, inbound synapses, distinct inbound axons: axons internal to
+ *     the part's vertices plus the multiplicities of the hyperedges in which
+ *     the part holds a destination-flagged pin) in move order, for limits a
+ *     part met before the round;
+ *   * the valid prefix (no crossing left) with the largest positive
+ *     cumulative gain, shortest on ties, is applied.
+ * Rounds stop after one that applies nothing, or after max_rounds.  Writes
+ * host int64 info[4]: rounds run, moves applied, decrease of Eq. 1 (both
+ * summed over the rounds), moves proposed in the last round.  Needs the
+ * level's state.  Synchronous (reads sizes back between steps); its scratch
+ * (about 150 bytes per pin) is the context's arena.
+ */
+int hg_refine(hg_ctx* ctx, const hg_level* lvl, int32_t* part, int32_t n_parts,
+              const hg_limits* limits, int32_t max_rounds, int64_t* info);
+
+/*
  * hg_connectivity with no allocation, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, hosts
  * that forbid allocation in their loop).  Same arguments, result and checks

@@ -34,7 +34,7 @@ EXPORTED = ("hg_create", "hg_destroy", "hg_set_stream", "hg_last_error", "hg_syn
             "hg_scratch_bytes", "hg_enable_timing", "hg_phase_times", "hg_init_state",
             "hg_coarsen_level", "hg_contract", "hg_connectivity", "hg_validate_level",
             "hg_set_tuning", "hg_get_tuning", "hg_score_census", "hg_connectivity_static",
-            "hg_project", "hg_partition_report",
+            "hg_project", "hg_partition_report", "hg_refine",
             "hg_batch_create", "hg_batch_destroy", "hg_batch_bytes", "hg_batch_add_graph",
             "hg_batch_step", "hg_batch_done", "hg_batch_result", "hg_batch_compact",
             "hg_batch_sizes")
@@ -95,6 +95,8 @@ def load_library(path: str = LIB_PATH):
     lib.hg_connectivity.argtypes = [_P, ctypes.POINTER(_Level), _P, _P]
     lib.hg_connectivity_static.argtypes = [_P, ctypes.POINTER(_Level), _P, _P]
     lib.hg_project.argtypes = [_P, _i32, _P, _P, _P, _P]
+    lib.hg_refine.argtypes = [_P, ctypes.POINTER(_Level), _P, _i32, ctypes.POINTER(Limits),
+                              _i32, ctypes.POINTER(_i64)]
     lib.hg_partition_report.argtypes = [_P, ctypes.POINTER(_Level), _P, _P,
                                         ctypes.POINTER(Limits), _P, _P, _P, _P]
     lib.hg_validate_level.argtypes = [_P, ctypes.POINTER(_Level)]
@@ -347,6 +349,20 @@ class Context:
         if per_part:
             res.update(size=arrs[0][:s[7]], syn=arrs[1][:s[7]], ax=arrs[2][:s[7]])
         return res
+
+    def refine(self, L: DeviceLevel, part: torch.Tensor, n_parts: int, limits,
+               max_rounds: int = 16) -> list[int]:
+        """Refinement rounds on one level (hg_refine); ``part`` is updated in
+        place.  Returns [rounds, moves applied, Eq. (1) decrease, proposals
+        in the last round]."""
+        lim = Limits(limits.max_neurons, limits.max_synapses, limits.max_axons)
+        lv = L.c_struct()
+        info = (_i64 * 4)()
+        assert part.dtype == torch.int32 and part.is_contiguous()
+        with torch.cuda.stream(self.stream):
+            self._check(self.lib.hg_refine(self.h, ctypes.byref(lv), _ptr(part), int(n_parts),
+                                           ctypes.byref(lim), int(max_rounds), info))
+        return [int(info[i]) for i in range(4)]
 
     def validate(self, L: DeviceLevel):
         lv = L.c_struct()

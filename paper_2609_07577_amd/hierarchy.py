@@ -65,3 +65,40 @@ def batched_hierarchies(ctx: hg.Context, levels, limits, use_graph: bool = True,
     if pending:
         raise RuntimeError("batched hierarchies did not finish")
     return results
+
+
+def uncoarsen(ctx: hg.Context, levels, maps, limits, max_rounds: int = 16):
+    """The uncoarsening (Section 4.1): the final super-nodes of a hierarchy
+    as initial parts, then level by level down to level 0, the partition
+    projected through the level's vertex map (hg_project) and refined
+    (hg_refine).  ``levels``: the device levels of the hierarchy, level 0
+    first; ``maps``: their (vmap, n_coarse) pairs, one fewer.  Returns the
+    level-0 partition (device int32), the number of parts and a per-level
+    list of (level, Eq. 1 after projection, Eq. 1 after refinement, rounds)."""
+    top = levels[-1]
+    n_parts = top.V
+    part = torch.arange(n_parts, dtype=torch.int32, device=ctx.device)
+    trace = []
+    for li in range(len(levels) - 1, -1, -1):
+        L = levels[li]
+        if li < len(levels) - 1:
+            vmap, nc = maps[li]
+            part = ctx.project(vmap, nc, part)
+        before = int(ctx.connectivity(L, part).item())
+        info = ctx.refine(L, part, n_parts, limits, max_rounds)
+        trace.append((li, before, before - info[2], info[0]))
+    return part, n_parts, trace
+
+
+def hierarchy_levels(ctx: hg.Context, L: hg.DeviceLevel, limits, max_levels: int = 100000):
+    """The plain hierarchy with every level kept on the device: (levels,
+    maps) as uncoarsen() takes them."""
+    levels, maps = [L], []
+    while len(maps) < max_levels:
+        out = ctx.coarsen_level(L, limits, want_candidates=False)
+        if not int(out["any_candidate"].item()):
+            break
+        maps.append((out["vmap"], out["n_coarse"]))
+        L = ctx.contract(L, out["vmap"], out["n_coarse"])
+        levels.append(L)
+    return levels, maps
