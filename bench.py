@@ -58,6 +58,17 @@ WORKLOADS = {
 }
 
 
+# The score kernel of each work list of the library's bucket rule (lists 4-7
+# also count shared inbound axons); list 2 uses the aligned-window variant on
+# levels of at most 16 windows of 2^19 ids.
+SCORE_KERNELS = (
+    "score_block_kernel<256,4096>", "score_block_kernel<512,16384>",
+    "score_window_kernel<1024>", "score_block_kernel<512,16384,multipass>",
+    "score_block_kernel<256,4096,overlap>", "score_block_kernel<512,8192,overlap>",
+    "score_stream_kernel<1024,8192,overlap>", "score_block_kernel<512,8192,multipass,overlap>",
+)
+
+
 def expansion_stats(g):
     """X = sum over hyperedges of |e| (|e| - 1): neighbour visits of the score step."""
     lens = np.diff(g.eoff).astype(np.int64)
@@ -407,6 +418,66 @@ def run_hierarchy(args):
     print(json.dumps(result), flush=True)
 
 
+def run_partition(args):
+    """The whole partitioner on one workload (Section 4.1): the coarsening
+    hierarchy with every level kept on the device, then the uncoarsening
+    (projection of the final super-nodes and refinement rounds, level by
+    level down to level 0), then the partition report of level 0 (Eq. 1 and
+    the parts' totals against the limits).  Reports the time of both phases,
+    Eq. 1 of the final super-nodes and after refinement, and per level the
+    rounds and the decrease."""
+    import torch
+    from paper_2609_07577_amd import hg, hierarchy, synth
+
+    wl = WORKLOADS[args.workload]
+    lim = synth.LIMITS[wl["limits"]]
+    g = wl["make"](synth, args.seed)
+    ctx = hg.Context(0)
+    L0 = ctx.upload(g)
+    ctx.sync()
+    _log(f"{args.workload}: V={g.n_vertices} E={g.n_edges} P={g.n_pins}; partitioning")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    levels, maps = hierarchy.hierarchy_levels(ctx, L0, lim)
+    torch.cuda.synchronize()
+    t_coarsen = time.perf_counter() - t0
+    _log(f"coarsening: {len(maps)} contractions in {t_coarsen:.2f} s; {levels[-1].V} parts")
+    t0 = time.perf_counter()
+    part, n_parts, trace = hierarchy.uncoarsen(ctx, levels, maps, lim, args.rounds)
+    torch.cuda.synchronize()
+    t_uncoarsen = time.perf_counter() - t0
+    rep = ctx.partition_report(L0, part, torch.tensor([n_parts], dtype=torch.int32,
+                                                      device="cuda"), lim, per_part=False)
+    _log(f"uncoarsening: {t_uncoarsen:.2f} s; Eq. 1 {trace[0][1]} -> {trace[-1][2]}")
+    pins_total = sum(L.P for L in levels)
+    result = {
+        "metric": METRIC,
+        "value": pins_total / (t_coarsen + t_uncoarsen),
+        "unit": "pins/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1000.0 * (t_coarsen + t_uncoarsen),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": wl["desc"].replace("; level 0", "") +
+                   "; coarsening, uncoarsening and refinement",
+                   "seed": args.seed, "vertices": g.n_vertices, "hyperedges": g.n_edges,
+                   "pins": g.n_pins, "max_rounds": args.rounds},
+        "contractions": len(maps),
+        "parts": n_parts,
+        "coarsen_s": t_coarsen,
+        "uncoarsen_s": t_uncoarsen,
+        "conn_final_supernodes": trace[0][1],
+        "conn_refined": trace[-1][2],
+        "refinement_gain_pct": 100.0 * (trace[0][1] - trace[-1][2]) / max(1, trace[0][1]),
+        "level0_report": {k: rep[k] for k in ("conn", "max_size", "max_syn", "max_axons",
+                                              "over_neurons", "over_synapses", "over_axons",
+                                              "n_parts")},
+        "levels": [{"level": li, "conn_projected": b, "conn_refined": a_, "rounds": r}
+                   for li, b, a_, r in trace],
+    }
+    print(json.dumps(result), flush=True)
+
+
 def run_serve(args):
     """Served requests: Poisson arrivals at --rate per second for --duration
     seconds.  A request is one SNN hypergraph to coarsen to the end, drawn
@@ -527,9 +598,13 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="level", choices=("level", "hierarchy", "batch", "serve"),
+    ap.add_argument("--rounds", type=int, default=16,
+                    help="partition mode: refinement rounds per level at most")
+    ap.add_argument("--mode", default="level",
+                    choices=("level", "hierarchy", "partition", "batch", "serve"),
                     help="level: one coarsening level of one graph (default); hierarchy: the "
                          "whole hierarchy of --workload with Eq. 1 checked two ways per level; "
+                         "partition: coarsening, uncoarsening and refinement of --workload; "
                          "batch: the 256-graph batch, batched vs plain; serve: continuous "
                          "batching of Poisson-arriving requests")
     ap.add_argument("--graphs", type=int, default=256, help="batch mode: graphs at full size")
@@ -567,6 +642,9 @@ def main():
         return
     if args.mode == "hierarchy":
         run_hierarchy(args)
+        return
+    if args.mode == "partition":
+        run_partition(args)
         return
 
     from paper_2609_07577_amd import hg, synth
@@ -624,6 +702,13 @@ def main():
     conn_coarse = int(torch.sum(C.w.to(torch.int64) * (lens - 1)).item())
     conn_ok = conn_coarse == int(conn.item())
 
+    # the score kernel that carried most neighbour visits on this level (from
+    # the library's census of its work lists)
+    n_by_list, visits_by_list = ctx.score_census()
+    top = int(np.argmax(visits_by_list))
+    kernel = SCORE_KERNELS[top]
+    if top == 2 and V <= (16 << 19):
+        kernel = "score_window2_kernel<1024>"
     value = P / (ms_step / 1000.0)
     b_s2 = s2_bytes(V, E, P, X)
     t_s2 = phases["score"] / 1000.0
@@ -648,8 +733,10 @@ def main():
                    "coarse_hyperedges": C.E, "coarse_pins": C.P},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "score_window_kernel<1024> (Eq. 12 scores and candidates)",
+                     "kernel": kernel + " (Eq. 12 scores and candidates)",
+                     "kernel_visit_share": visits_by_list[top] / max(1, sum(visits_by_list)),
                      "algorithmic_bytes": b_s2, "ms_per_launch": phases["score"]},
+        "score_work_lists": {"vertices": n_by_list, "visits": visits_by_list},
         "level_hbm_frac": b_level / (ms_step / 1000.0) / 1e9 / HBM_PEAK_GBS,
         "phases_ms": phases,
         "levels_per_s": 1000.0 / ms_step,

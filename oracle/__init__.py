@@ -69,6 +69,13 @@ def _load():
                                                 _i32, _i32, _i32, _i32, _P, _P, _P, _P]
         lib.oracle_refine_round.argtypes = [_i32, _i32, _P, _P, _P, _P, _P, _P, _P, _P, _i32,
                                             _i32, _i32, _i32, _P]
+        lib.oracle_hilbert_cores.argtypes = [_i32, _i32, _P]
+        lib.oracle_hilbert_cores.restype = _i32
+        lib.oracle_initial_placement.argtypes = [_i32, _i32, _P, _P, _P, _i32, _i32, _P, _i32,
+                                                 _P]
+        lib.oracle_residual_distance.argtypes = [_i32, _i32, _P, _P, _P, _i32, _P]
+        lib.oracle_residual_distance.restype = ctypes.c_int64
+        lib.oracle_place_refine.argtypes = [_i32, _i32, _P, _P, _P, _i32, _i32, _P, _i32, _P]
         _lib = lib
     return _lib
 
@@ -284,6 +291,66 @@ def uncoarsen(h: "Hierarchy", limits, max_rounds: int = 16):
         part, rounds, dec = refine(L, part, n_parts, limits, max_rounds)
         trace.append((li, before, before - dec, rounds))
     return part, n_parts, trace
+
+
+def hilbert_cores(width: int, height: int) -> np.ndarray:
+    """Cores of the width x height lattice (core = x * height + y) in Hilbert
+    order (Section 4.2, "Initial Placement")."""
+    lib = _load()
+    out = np.empty(width * height, np.int32)
+    n = lib.oracle_hilbert_cores(width, height, _ptr(out))
+    return out[:n]
+
+
+def initial_placement(L: OLevel, width: int, height: int, order0: np.ndarray,
+                      lp_rounds: int = 4) -> np.ndarray:
+    """One start of the initial placement of a partitioned hypergraph G_P
+    (its nodes are the parts): core of every node."""
+    lib = _load()
+    order0 = np.ascontiguousarray(order0, dtype=np.int32)
+    core = np.empty(max(L.V, 1), np.int32)
+    rc = lib.oracle_initial_placement(L.V, L.E, _ptr(L.eoff), _ptr(L.pins), _ptr(L.w), width,
+                                      height, _ptr(order0), lp_rounds, _ptr(core))
+    if rc != 0:
+        raise ValueError("more nodes than cores")
+    return core[:L.V]
+
+
+def residual_distance(L: OLevel, height: int, core: np.ndarray) -> int:
+    """Sum over hyperedges of eta(a) times the Manhattan distances of all
+    unordered pairs of its pins' cores."""
+    lib = _load()
+    core = np.ascontiguousarray(core, dtype=np.int32)
+    return int(lib.oracle_residual_distance(L.V, L.E, _ptr(L.eoff), _ptr(L.pins), _ptr(L.w),
+                                            height, _ptr(core)))
+
+
+def place_refine(L: OLevel, width: int, height: int, core: np.ndarray, max_rounds: int = 1000):
+    """Swap refinement (Section 4.2) on a copy of ``core``.  Returns (core,
+    [rounds, swaps applied, decrease of the residual distance])."""
+    lib = _load()
+    out = np.array(core, dtype=np.int32, copy=True)
+    info = np.zeros(3, np.int64)
+    lib.oracle_place_refine(L.V, L.E, _ptr(L.eoff), _ptr(L.pins), _ptr(L.w), width, height,
+                            _ptr(out), max_rounds, _ptr(info))
+    return out, info
+
+
+def place(L: OLevel, width: int, height: int, orders: np.ndarray, lp_rounds: int = 4,
+          max_rounds: int = 1000):
+    """Multi-start placement: every start's initial placement and swap
+    refinement; the start of least residual distance (lowest index on
+    ties) is chosen.  ``orders`` [starts, V]: the random initial orders.
+    Returns (core of every node, chosen start, residual distance of every
+    start after refinement)."""
+    finals, dists = [], []
+    for order0 in orders:
+        c0 = initial_placement(L, width, height, order0, lp_rounds)
+        c1, _ = place_refine(L, width, height, c0, max_rounds)
+        finals.append(c1)
+        dists.append(residual_distance(L, height, c1))
+    best = int(np.argmin(dists))
+    return finals[best], best, np.array(dists, np.int64)
 
 
 @dataclass

@@ -42,6 +42,7 @@
 #include <chrono>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <vector>
 
@@ -572,6 +573,351 @@ int oracle_refine_round(int32_t V, int32_t E, const int64_t* eoff, const uint32_
   info[0] = (int64_t)moves.size();
   info[1] = best_len;
   info[2] = best_cum;
+  return 0;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Placement (Section 4.2).  The lattice H has width x height cores; core c
+// is (x, y) = (c / height, c % height), so core ids ascend lexicographically
+// over (x, y); dist is the Manhattan distance (Section 2).  The hypergraph is
+// G_P (parts as nodes); only its pins and weights are used.  Readings (design
+// notes P1-P6):
+//   P1 the Hilbert order of H is that of the smallest 2^k x 2^k square
+//      holding H, cores outside H skipped;
+//   P2 a section of s nodes splits into its first ceil(s/2) and last
+//      floor(s/2) positions; a label-propagation round computes every
+//      node's gain of crossing to the other half (cut = hyperedges with pins
+//      in both halves, counting only the section's own nodes), sorts both
+//      halves by (gain desc, id asc) and swaps the i-th pairs while their
+//      gains sum above 0; rounds stop after `lp_rounds` or a round without
+//      swaps;
+//   P3 folding: the connection of a section c to a section u is the weight of
+//      the hyperedges with pins in both; the child of a left (right) section
+//      more connected to the section's sibling goes right (left); ties keep
+//      the order; a flip reverses the pair's concatenation;
+//   P4 a node proposes the swap with the adjacent core of largest tension
+//      (Eq. 15), lowest core id on ties, when that tension is positive;
+//      empty cores propose nothing;
+//   P5 the objective is the residual distance D = sum over hyperedges of
+//      eta(a) times the distances of all unordered pin pairs; the tension of
+//      a swap is exactly its decrease of D;
+//   P6 swaps are matched by Eq. 13 over cores (lowest core id on ties),
+//      ordered by tension (descending) then smaller core id; the prefix of
+//      largest positive cumulative recomputed tension (the shortest on ties)
+//      is applied; rounds until none is applied.
+
+namespace {
+
+// Hilbert curve index -> (x, y) on an n x n square (n a power of two), the
+// classic iterative construction quadrant by quadrant.
+void hilbert_xy(int64_t n, int64_t d, int64_t& x, int64_t& y) {
+  x = y = 0;
+  int64_t t = d;
+  for (int64_t s = 1; s < n; s *= 2) {
+    const int64_t rx = 1 & (t / 2);
+    const int64_t ry = 1 & (t ^ rx);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = s - 1 - x;
+        y = s - 1 - y;
+      }
+      std::swap(x, y);
+    }
+    x += s * rx;
+    y += s * ry;
+    t /= 4;
+  }
+}
+
+struct PlaceGraph {
+  int32_t V, E;
+  const int64_t* eoff;
+  const uint32_t* pins;
+  const int32_t* eta;
+  std::vector<std::vector<int32_t>> inc;  // hyperedges of each node
+  PlaceGraph(int32_t V_, int32_t E_, const int64_t* eo, const uint32_t* pi, const int32_t* et)
+      : V(V_), E(E_), eoff(eo), pins(pi), eta(et), inc(V_) {
+    for (int32_t e = 0; e < E; ++e)
+      for (int64_t k = eoff[e]; k < eoff[e + 1]; ++k) inc[pins[k] & IDMASK].push_back(e);
+  }
+  int32_t pin(int64_t k) const { return (int32_t)(pins[k] & IDMASK); }
+};
+
+int64_t manhattan(int32_t a, int32_t b, int32_t height) {
+  const int64_t dx = (int64_t)(a / height) - (b / height);
+  const int64_t dy = (int64_t)(a % height) - (b % height);
+  return (dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy);
+}
+
+// One section [start, start + len) of the sequence: split, then label
+// propagation between the halves (P2).
+void bisect_section(const PlaceGraph& G, std::vector<int32_t>& seq, int64_t start, int64_t len,
+                    int32_t lp_rounds) {
+  const int64_t nl = len - len / 2;
+  for (int32_t round = 0; round < lp_rounds; ++round) {
+    std::map<int32_t, int> side;  // node -> 0 left, 1 right
+    for (int64_t i = 0; i < len; ++i) side[seq[start + i]] = i < nl ? 0 : 1;
+    std::map<int32_t, std::pair<int64_t, int64_t>> cnt;  // hyperedge -> (left, right) pins
+    for (auto& kv : side)
+      for (int32_t e : G.inc[kv.first]) {
+        auto& c = cnt[e];
+        (kv.second ? c.second : c.first) += 1;
+      }
+    std::vector<std::pair<int64_t, int32_t>> L, R;  // (-gain, node)
+    for (auto& kv : side) {
+      const int32_t u = kv.first;
+      const bool left = kv.second == 0;
+      int64_t g = 0;
+      for (int32_t e : G.inc[u]) {
+        const auto& c = cnt[e];
+        const int64_t mine = left ? c.first : c.second, other = left ? c.second : c.first;
+        if (mine == 1 && other > 0) g += G.eta[e];
+        if (other == 0 && mine > 1) g -= G.eta[e];
+      }
+      (left ? L : R).push_back({-g, u});
+    }
+    std::sort(L.begin(), L.end());
+    std::sort(R.begin(), R.end());
+    std::map<int32_t, int64_t> pos;
+    for (int64_t i = 0; i < len; ++i) pos[seq[start + i]] = start + i;
+    int64_t swaps = 0;
+    for (size_t i = 0; i < L.size() && i < R.size(); ++i) {
+      if (-L[i].first - R[i].first <= 0) break;
+      std::swap(seq[pos[L[i].second]], seq[pos[R[i].second]]);
+      ++swaps;
+    }
+    if (swaps == 0) break;
+  }
+}
+
+int64_t section_conn(const PlaceGraph& G, const std::vector<int32_t>& a, int64_t as, int64_t al,
+                     const std::vector<int32_t>& b, int64_t bs, int64_t bl) {
+  std::vector<uint8_t> in_b(G.E, 0);
+  for (int64_t i = 0; i < bl; ++i)
+    for (int32_t e : G.inc[b[bs + i]]) in_b[e] = 1;
+  std::vector<uint8_t> seen(G.E, 0);
+  int64_t c = 0;
+  for (int64_t i = 0; i < al; ++i)
+    for (int32_t e : G.inc[a[as + i]])
+      if (in_b[e] && !seen[e]) {
+        seen[e] = 1;
+        c += G.eta[e];
+      }
+  return c;
+}
+
+// Folding (P3): returns the folded order of section [start, start + len) of
+// the bisected sequence `bis`; `side` is 0 / 1 for a left / right section,
+// -1 for the root; (us, ul) the section's sibling.
+std::vector<int32_t> fold(const PlaceGraph& G, const std::vector<int32_t>& bis, int64_t start,
+                          int64_t len, int side, int64_t us, int64_t ul) {
+  if (len == 1) return {bis[start]};
+  const int64_t nl = len - len / 2;
+  std::vector<int32_t> c0 = fold(G, bis, start, nl, 0, start + nl, len - nl);
+  std::vector<int32_t> c1 = fold(G, bis, start + nl, len - nl, 1, start, nl);
+  bool flip = false;
+  if (side >= 0) {
+    const int64_t k0 = section_conn(G, bis, start, nl, bis, us, ul);
+    const int64_t k1 = section_conn(G, bis, start + nl, len - nl, bis, us, ul);
+    flip = side == 0 ? k0 > k1 : k1 > k0;
+  }
+  std::vector<int32_t> out(c0);
+  out.insert(out.end(), c1.begin(), c1.end());
+  if (flip) std::reverse(out.begin(), out.end());
+  return out;
+}
+
+int64_t residual(const PlaceGraph& G, const int32_t* core_of, int32_t height) {
+  int64_t d = 0;
+  for (int32_t e = 0; e < G.E; ++e) {
+    int64_t s = 0;
+    for (int64_t i = G.eoff[e]; i < G.eoff[e + 1]; ++i)
+      for (int64_t j = i + 1; j < G.eoff[e + 1]; ++j)
+        s += manhattan(core_of[G.pin(i)], core_of[G.pin(j)], height);
+    d += (int64_t)G.eta[e] * s;
+  }
+  return d;
+}
+
+// Eq. 14: force(p, k) with p at h = core_of[p].
+int64_t force(const PlaceGraph& G, const int32_t* core_of, int32_t height, int32_t p,
+              int32_t k) {
+  const int32_t h = core_of[p];
+  int64_t f = 0;
+  for (int32_t e : G.inc[p]) {
+    int64_t s = 0;
+    for (int64_t i = G.eoff[e]; i < G.eoff[e + 1]; ++i) {
+      const int32_t q = G.pin(i);
+      if (q == p) continue;
+      const int64_t dk = manhattan(k, core_of[q], height);
+      s += manhattan(h, core_of[q], height) - (dk > 1 ? dk : 1);
+    }
+    f += (int64_t)G.eta[e] * s;
+  }
+  return f;
+}
+
+}  // namespace
+
+extern "C" {
+
+// The cores of the width x height lattice in Hilbert order (P1); writes
+// width * height core ids.
+int oracle_hilbert_cores(int32_t width, int32_t height, int32_t* out) {
+  int64_t n = 1;
+  while (n < width || n < height) n *= 2;
+  int64_t k = 0;
+  for (int64_t d = 0; d < n * n; ++d) {
+    int64_t x, y;
+    hilbert_xy(n, d, x, y);
+    if (x < width && y < height) out[k++] = (int32_t)(x * height + y);
+  }
+  return (int32_t)k;
+}
+
+// Initial placement of one start (Section 4.2, "Initial Placement"): the
+// nodes in the order `order0`, recursive bisection with label propagation
+// (P2), folding (P3), and the i-th node of the result on the i-th core of
+// the Hilbert order.  Writes core_of[V]; returns 0, or -1 if V exceeds the
+// cores.
+int oracle_initial_placement(int32_t V, int32_t E, const int64_t* eoff, const uint32_t* pins,
+                             const int32_t* eta, int32_t width, int32_t height,
+                             const int32_t* order0, int32_t lp_rounds, int32_t* core_of) {
+  if ((int64_t)V > (int64_t)width * height) return -1;
+  PlaceGraph G(V, E, eoff, pins, eta);
+  std::vector<int32_t> seq(order0, order0 + V);
+  // bisection, depth by depth: the sections of a depth are disjoint ranges
+  std::vector<std::pair<int64_t, int64_t>> cur = {{0, V}};
+  while (!cur.empty()) {
+    std::vector<std::pair<int64_t, int64_t>> next;
+    for (auto& sl : cur) {
+      if (sl.second < 2) continue;
+      bisect_section(G, seq, sl.first, sl.second, lp_rounds);
+      const int64_t nl = sl.second - sl.second / 2;
+      next.push_back({sl.first, nl});
+      next.push_back({sl.first + nl, sl.second - nl});
+    }
+    cur.swap(next);
+  }
+  std::vector<int32_t> order = V > 0 ? fold(G, seq, 0, V, -1, 0, 0) : std::vector<int32_t>();
+  std::vector<int32_t> hc((size_t)width * height);
+  oracle_hilbert_cores(width, height, hc.data());
+  for (int32_t i = 0; i < V; ++i) core_of[order[i]] = hc[i];
+  return 0;
+}
+
+// Residual distance D (P5) of a placement.
+int64_t oracle_residual_distance(int32_t V, int32_t E, const int64_t* eoff, const uint32_t* pins,
+                                 const int32_t* eta, int32_t height, const int32_t* core_of) {
+  PlaceGraph G(V, E, eoff, pins, eta);
+  return residual(G, core_of, height);
+}
+
+// Swap refinement (Section 4.2, "Swap Proposals" and "Placement
+// Refinement"): rounds of proposals (Eq. 14, 15; P4), matching (Eq. 13 over
+// cores; P6), ordering, recomputed tensions and the best prefix, until a
+// round applies nothing or max_rounds.  core_of[V] is updated in place.
+// info = [rounds, swaps applied, decrease of D].  Returns 0.
+int oracle_place_refine(int32_t V, int32_t E, const int64_t* eoff, const uint32_t* pins,
+                        const int32_t* eta, int32_t width, int32_t height, int32_t* core_of,
+                        int32_t max_rounds, int64_t* info) {
+  PlaceGraph G(V, E, eoff, pins, eta);
+  const int32_t C = width * height;
+  info[0] = info[1] = info[2] = 0;
+  for (int32_t round = 0; round < max_rounds; ++round) {
+    info[0] = round + 1;
+    std::vector<int32_t> occ(C, -1);
+    for (int32_t p = 0; p < V; ++p) occ[core_of[p]] = p;
+    // proposals: tension (Eq. 15) to each adjacent core
+    std::vector<int32_t> cand(C, -1);
+    std::vector<int64_t> score(C, 0);
+    auto tension = [&](int32_t h, int32_t k) {
+      int64_t t = 0;
+      if (occ[h] >= 0) t += force(G, core_of, height, occ[h], k);
+      if (occ[k] >= 0) t += force(G, core_of, height, occ[k], h);
+      return t;
+    };
+    for (int32_t h = 0; h < C; ++h) {
+      if (occ[h] < 0) continue;
+      const int32_t x = h / height, y = h % height;
+      const int32_t nb[4][2] = {{x - 1, y}, {x, y - 1}, {x, y + 1}, {x + 1, y}};
+      int64_t best = 0;
+      int32_t bk = -1;
+      for (auto& q : nb) {  // ascending core ids
+        if (q[0] < 0 || q[0] >= width || q[1] < 0 || q[1] >= height) continue;
+        const int32_t k = q[0] * height + q[1];
+        const int64_t t = tension(h, k);
+        if (t > best) {
+          best = t;
+          bk = k;
+        }
+      }
+      cand[h] = bk;
+      score[h] = best;
+    }
+    // Eq. 13 over cores (the same rule as the coarsening's matching)
+    std::vector<int32_t> bc(C, -1);
+    for (int32_t m = 0; m < C; ++m) {
+      const int32_t pp = cand[m];
+      if (pp < 0) continue;
+      const int32_t cur = bc[pp];
+      if (cur < 0 || score[m] > score[cur] || (score[m] == score[cur] && m < cur)) bc[pp] = m;
+    }
+    std::vector<int32_t> mt(C, -2);  // -2 unknown
+    std::function<int32_t(int32_t)> match_of = [&](int32_t h) -> int32_t {
+      if (mt[h] != -2) return mt[h];
+      const int32_t c = cand[h];
+      bool taken = false;
+      if (c >= 0) taken = cand[c] == h || match_of(c) == h;
+      mt[h] = taken ? c : bc[h];
+      return mt[h];
+    };
+    struct Swap {
+      int64_t t;
+      int32_t a, b;
+    };
+    std::vector<Swap> sw;
+    for (int32_t h = 0; h < C; ++h) {
+      const int32_t m = match_of(h);
+      if (m > h) sw.push_back({tension(h, m), h, m});
+    }
+    std::sort(sw.begin(), sw.end(), [](const Swap& x, const Swap& y) {
+      return x.t != y.t ? x.t > y.t : x.a < y.a;
+    });
+    // recomputed tensions along the order, the best prefix
+    std::vector<int32_t> trial(core_of, core_of + V);
+    std::vector<int32_t> tocc(occ);
+    int64_t cum = 0, best_cum = 0, best_len = 0;
+    for (size_t i = 0; i < sw.size(); ++i) {
+      const int32_t a = sw[i].a, b = sw[i].b;
+      int64_t t = 0;
+      if (tocc[a] >= 0) t += force(G, trial.data(), height, tocc[a], b);
+      if (tocc[b] >= 0) t += force(G, trial.data(), height, tocc[b], a);
+      const int32_t pa = tocc[a], pb = tocc[b];
+      if (pa >= 0) trial[pa] = b;
+      if (pb >= 0) trial[pb] = a;
+      tocc[a] = pb;
+      tocc[b] = pa;
+      cum += t;
+      if (cum > best_cum) {
+        best_cum = cum;
+        best_len = (int64_t)i + 1;
+      }
+    }
+    if (best_len == 0) break;
+    for (int64_t i = 0; i < best_len; ++i) {
+      const int32_t a = sw[i].a, b = sw[i].b;
+      const int32_t pa = occ[a], pb = occ[b];
+      if (pa >= 0) core_of[pa] = b;
+      if (pb >= 0) core_of[pb] = a;
+      occ[a] = pb;
+      occ[b] = pa;
+    }
+    info[1] += best_len;
+    info[2] += best_cum;
+  }
   return 0;
 }
 

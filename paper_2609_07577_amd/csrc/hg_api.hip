@@ -329,6 +329,8 @@ int hg_coarsen_level(hg_ctx* c, const hg_level* in, const hg_limits* lim, int32_
   int32_t* cs = cscore ? cscore : S.cscore;
   ScoreArgs sa{L,  S.voff, S.vinc, S.xn, S.gc, S.cursor, cd,
                cs, S.work, b,      c->dev_err, c->tuning.fill16};
+  sa.splits = S.splits;
+  sa.n_win = S.n_win;
   mark(c, 1, 0);
   score_candidates(sa, V, P, s);
   mark(c, 1, 1);

@@ -152,8 +152,9 @@ struct CoarsenScratch {
   int32_t* rep;
   int64_t* rank;
   int64_t* partials;
+  uint32_t* splits;
+  int32_t n_win;
   void carve(A& a, int64_t V, int64_t E, int64_t P) {
-    (void)E;
     dims = a.template take<Dims>(1);
     gc = a.template take<GraphConst>(1);
     vcount = a.template take<int32_t>(V);
@@ -173,6 +174,9 @@ struct CoarsenScratch {
     rep = a.template take<int32_t>(V);
     rank = a.template take<int64_t>(V + 1);
     partials = a.template take<int64_t>(scan_partials_size());
+    const int64_t w = (V + (1ll << kWinAlignBits) - 1) >> kWinAlignBits;
+    n_win = (w >= 1 && w <= kMaxAlignedWindows) ? (int32_t)w : 0;
+    splits = n_win ? a.template take<uint32_t>(E * (n_win + 1)) : nullptr;
   }
 };
 

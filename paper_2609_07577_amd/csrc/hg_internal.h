@@ -157,7 +157,15 @@ struct ScoreArgs {
   Buckets b;
   int32_t* err;
   int32_t fill16;    // Tuning::fill16
+  // Slices of every hyperedge at the aligned id windows of kWinAlignBits
+  // bits: splits[e * (n_win + 1) + w] = pins of e below id w << kWinAlignBits
+  // (scratch of [E * (n_win + 1)]).  n_win = 0: the windows of the score
+  // step are not aligned (the level has too many ids for the array).
+  uint32_t* splits = nullptr;
+  int32_t n_win = 0;
 };
+constexpr int kWinAlignBits = 19;
+constexpr int kMaxAlignedWindows = 16;
 void score_candidates(const ScoreArgs& a, int64_t maxV, int64_t maxP, hipStream_t s);
 
 // ---- S3-S5 (hg_match.hip) ---------------------------------------------------

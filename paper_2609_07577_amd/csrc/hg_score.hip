@@ -1305,6 +1305,442 @@ __global__ __launch_bounds__(THREADS) void score_window_kernel(ScoreArgs a, int 
   }
 }
 
+// Slices of every hyperedge at the aligned id windows: splits[e (W + 1) + w]
+// = the number of pins of e with id below w << kWinAlignBits (a thread per
+// hyperedge, binary searches over its ascending pins).
+__global__ void window_splits_kernel(const Dims* __restrict__ d, const int64_t* __restrict__ eoff,
+                                     const uint32_t* __restrict__ pins, int32_t W,
+                                     uint32_t* __restrict__ splits) {
+  const int64_t E = d->E;
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; e < E; e += stride) {
+    const int64_t s0 = eoff[e];
+    const uint32_t len = (uint32_t)(eoff[e + 1] - s0);
+    uint32_t* out = splits + e * (int64_t)(W + 1);
+    out[0] = 0;
+    uint32_t lo = 0;
+    for (int32_t w = 1; w < W; ++w) {
+      const uint32_t bound = (uint32_t)w << kWinAlignBits;
+      uint32_t hi = len;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((pins[s0 + mid] & kIdMask) < bound) lo = mid + 1;
+        else hi = mid;
+      }
+      out[w] = lo;
+    }
+    out[W] = len;
+  }
+}
+
+// Windows with exact slices (large neighbourhoods where the distinct-axon
+// overlap cannot bind, at most kWinDeg incident hyperedges).  The id space
+// is cut into aligned windows of 2^kWinAlignBits ids, and every hyperedge's
+// pins at those boundaries are known from `splits`, so a window's slice of
+// each incident hyperedge is exact and no pin is tested against the window.
+// Per window, the slices are cut into chunks of 64 pins listed back to back
+// (a chunk descriptor holds its first pin, its hyperedge and its pin count),
+// so that a batch of B chunks is full whatever the slices' lengths; waves
+// claim batches from an LDS counter a fetch ahead.
+//   sweep 1 sets one bitmap bit per visit; a visit finding its bit set puts
+//     the id on its wave's list of repeat visits;
+//   the bitmap is rebuilt with just the repeated ids (n among them), and
+//     each repeated id gets a dense rank from per-word prefix counts;
+//   singles: an id visited once has the visiting hyperedge's weight as its
+//     score, so the best single of a window is, over the hyperedges, the
+//     first pin of the slice (pins ascend) that is not repeated (and, where
+//     a merge of n may break a limit, is valid): one thread per hyperedge
+//     walks its slice from the start;
+//   sweep 2 visits the chunks again and adds each repeat's weight to the
+//     score at its id's rank; the fold compares the repeated ids' scores.
+// A window whose chunks, repeat visits or repeated ids exceed the LDS room
+// is retried at half the width (slices cut again by binary search), and the
+// width grows back once windows fit.
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void score_window2_kernel(ScoreArgs a, int bucket,
+                                                               int64_t maxV) {
+  constexpr int NW = THREADS / kWave;
+  constexpr int B = 4;  // chunks per batch
+  constexpr uint32_t kWinIds = 1u << kWinAlignBits;
+  constexpr int kWords = (int)(kWinIds / 32);
+  constexpr int kList = 4096;
+  constexpr int kSeg = kList / NW;
+  constexpr int kScores = 4096;
+  constexpr int kMaxChunks = 1536;
+  constexpr uint32_t kSent = 0x7FFFFFFFu;
+  static_assert(kWords == 16 * THREADS, "a thread owns 16 consecutive bitmap words");
+  static_assert(kWinDeg <= THREADS, "thread j owns hyperedge j");
+  static_assert(kWinDeg <= 1024, "a chunk descriptor holds the hyperedge in 10 bits");
+  struct Lds {
+    alignas(16) uint32_t seen[kWords];
+    alignas(16) uint16_t wpre[kWords];   // repeated ids in the words before each word
+    uint32_t lst[kList + kWave];         // repeat visits, wave w's from w * kSeg on
+    uint32_t sc[kScores];                // score of each rank
+    uint2 desc[kMaxChunks + B];          // x: first pin; y: hyperedge | pin count << 10
+    int32_t m_w[kWinDeg];
+    int32_t s_wcnt[NW];
+    int32_t ws[3 * NW];
+    uint64_t red[2 * NW];
+    int32_t s_item;
+    int32_t s_next;
+  };
+  __shared__ Lds S;
+
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int wid = rfl_i32(tid / kWave);
+  int32_t count = a.b.count[bucket];
+  if (count > maxV) {
+    if (tid == 0) atomicOr(a.err, kErrWorkCount);
+    count = (int32_t)maxV;
+  }
+  const int32_t* list = a.b.list + (int64_t)bucket * maxV;
+  const int32_t W = a.n_win;
+  uint4* const seen4 = reinterpret_cast<uint4*>(S.seen);
+  uint4* const wpre4 = reinterpret_cast<uint4*>(S.wpre);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) seen4[4 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
+  int32_t prev_wcnt = 0, prev_nword = -1;
+  uint32_t prev_lw = 0;
+  uint32_t lofs[B];
+#pragma unroll
+  for (int u = 0; u < B; ++u) lofs[u] = (uint32_t)lane * 4u;
+
+  while (true) {
+    __syncthreads();
+    if (tid == 0) S.s_item = atomicAdd(&a.work[bucket], 1);
+    __syncthreads();
+    const int32_t item = S.s_item;
+    if (item >= count) break;
+
+    VertexCtx v;
+    v.n = list[item];
+    v.beg = a.voff[v.n];
+    v.deg = a.voff[v.n + 1] - v.beg;
+    if (v.deg > kWinDeg) {  // block-uniform; the bucket rule excludes it
+      if (tid == 0) atomicOr(a.err, kErrWorkCount);
+      continue;
+    }
+    v.size_n = a.L.size[v.n];
+    v.syn_n = a.L.syn[v.n];
+    v.ax_n = a.L.ax[v.n];
+    v.G = a.gc[a.L.gid ? a.L.gid[v.n] : 0];
+    v.all_valid = (int64_t)v.size_n + v.G.max_size <= v.G.omega &&
+                  (int64_t)v.syn_n + v.G.max_syn <= v.G.phi &&
+                  (int64_t)v.ax_n + v.G.max_ax <= v.G.delta;
+    const uint32_t n = (uint32_t)v.n;
+    const int32_t deg = (int32_t)v.deg;
+    uint64_t best = 0;
+    // thread j owns incident hyperedge j: its pins' base, weight, and the
+    // cursor of the unprocessed part of its slice
+    const bool owner = tid < deg;
+    uint32_t e_j = 0, cur = 0;
+    int32_t w_j = 0;
+    const uint32_t* srow = nullptr;
+    if (owner) {
+      e_j = a.vinc[v.beg + tid] & kIdMask;
+      cur = (uint32_t)a.L.eoff[e_j];
+      w_j = a.L.w[e_j];
+      S.m_w[tid] = w_j;
+      srow = a.splits + (int64_t)e_j * (W + 1);
+    }
+    int passes = 0;
+    bool stop = false;  // a bound was reached: the vertex keeps no candidate
+    for (int32_t wi = 0; wi < W && !stop; ++wi) {  // block-uniform
+      const uint32_t W0 = (uint32_t)wi << kWinAlignBits;
+      uint32_t W1 = W0 + kWinIds;
+      // the slice's end at the aligned window's end
+      uint32_t wend = 0;
+      if (owner) wend = (uint32_t)a.L.eoff[e_j] + srow[wi + 1];
+      uint32_t lo = W0;
+      uint32_t width = kWinIds;
+      while (lo < W1) {  // block-uniform
+        const uint32_t hi = W1 - lo <= width ? W1 : lo + width;
+        const uint32_t lw = lo >> 5;
+        uint32_t* const seenw = S.seen - lw;
+        const uint32_t lane_w = (uint32_t)lane + lw;
+        __syncthreads();  // previous window folded, lists read, descriptors free
+        if (++passes > kMaxPasses) {
+          if (tid == 0) atomicOr(a.err, kErrPassLimit);
+          stop = true;
+          break;
+        }
+        // ---- exact slices and their chunk list
+        uint32_t end = cur;
+        if (owner) {
+          if (hi == W1) {
+            end = wend;
+          } else {
+            uint32_t l = cur, h = wend;
+            while (l < h) {
+              const uint32_t mid = (l + h) >> 1;
+              if ((a.L.pins[mid] & kIdMask) < hi) l = mid + 1;
+              else h = mid;
+            }
+            end = l;
+          }
+        }
+        const int32_t nch = (int32_t)((end - cur + kWave - 1) / kWave);
+        int32_t x3[3] = {nch, 0, 0}, p3[3], t3[3];
+        block_scan3<THREADS>(x3, p3, t3, S.ws);
+        const int32_t T = t3[0];
+        if (T > kMaxChunks) {  // block-uniform
+          width >>= 1;
+          continue;
+        }
+        if (T == 0) {  // no pin of n's hyperedges in this range
+          lo = hi;
+          continue;
+        }
+        for (int32_t c = 0; c < nch; ++c) {
+          const uint32_t first = cur + (uint32_t)c * kWave;
+          const uint32_t left = end - first;
+          S.desc[p3[0] + c] =
+              make_uint2(first, (uint32_t)tid | ((left < (uint32_t)kWave ? left : kWave) << 10));
+        }
+        if (tid < B) S.desc[T + tid] = make_uint2(0u, 0u);
+        if (tid == 0) S.s_next = NW;
+        // the bitmap starts empty: the last window left only its repeated ids
+        for (int o = lane; o < prev_wcnt; o += kWave)
+          S.seen[(S.lst[wid * kSeg + o] >> 5) - prev_lw] = 0;
+        if (tid == 0 && prev_nword >= 0) S.seen[prev_nword] = 0;
+        prev_wcnt = 0;
+        prev_nword = -1;
+        __syncthreads();
+        const int32_t tb = (T + B - 1) / B;  // batches
+
+        // A batch's chunks: descriptors read at a wave-uniform address,
+        // made scalar; lanes past a chunk's pins load its last pin.
+        struct Batch {
+          uint32_t x[B];
+          int32_t cnt[B];
+          int32_t j[B];
+        };
+        int32_t bclaim = wid;
+        auto fetch = [&](Batch& t, uint32_t (&pin)[B], int32_t bno) {
+#pragma unroll
+          for (int u = 0; u < B; ++u) {
+            uint2 d = make_uint2(0u, 0u);
+            if (bno < tb) d = S.desc[bno * B + u];
+            t.x[u] = rfl_u32(d.x);
+            const uint32_t y = rfl_u32(d.y);
+            t.cnt[u] = (int32_t)(y >> 10);
+            t.j[u] = (int32_t)(y & 0x3FFu);
+          }
+#pragma unroll
+          for (int u = 0; u < B; ++u) {
+            const uint32_t last4 = t.cnt[u] > 0 ? (uint32_t)(t.cnt[u] - 1) * 4u : 0u;
+            const char* p = reinterpret_cast<const char*>(a.L.pins + t.x[u]);
+            const uint32_t off = lofs[u] < last4 ? lofs[u] : last4;
+            pin[u] = *reinterpret_cast<const uint32_t*>(p + off);
+          }
+          if (bno < tb) {  // wave-uniform: claim the next batch
+            int32_t c = 0;
+            if (lane == 0) c = atomicAdd(&S.s_next, 1);
+            bclaim = c;
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        };
+
+        // ---- sweep 1
+        bool over = false;
+        int32_t wcnt = 0;
+        auto process1 = [&](const Batch& t, const uint32_t (&pin)[B]) {
+          uint32_t id[B], bit[B], old[B];
+#pragma unroll
+          for (int u = 0; u < B; ++u) {
+            id[u] = pin[u] & kIdMask;
+            const bool act = lofs[u] < (uint32_t)t.cnt[u] * 4u;
+            const uint32_t word = act ? id[u] >> 5 : lane_w;
+            bit[u] = act ? 1u << (id[u] & 31) : 0u;
+            old[u] = atomicOr(&seenw[word], bit[u]);
+          }
+          bool rep[B];
+          uint64_t rb[B];
+          int32_t nr = 0;
+#pragma unroll
+          for (int u = 0; u < B; ++u) {
+            rep[u] = (old[u] & bit[u]) != 0;
+            rb[u] = ballot(rep[u]);
+            nr += (int32_t)__popcll(rb[u]);
+          }
+          if (nr > 0 && !over) {  // wave-uniform
+            if (wcnt + nr > kSeg) {
+              over = true;
+            } else {
+              uint32_t at = (uint32_t)(wid * kSeg + wcnt);
+              wcnt += nr;
+#pragma unroll
+              for (int u = 0; u < B; ++u) {
+                uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(rb[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)rb[u], 0u));
+                asm volatile("" : "+v"(below));
+                S.lst[rep[u] ? at + below : (uint32_t)(kList + lane)] = id[u];
+                at += (uint32_t)__popcll(rb[u]);
+              }
+            }
+          }
+          asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
+        };
+        {
+          Batch ta, tb2;
+          uint32_t pa[B], pb[B];
+          int32_t cur_b = wid;
+          fetch(ta, pa, cur_b);
+          while (cur_b < tb && !over) {
+            const int32_t nb = __builtin_amdgcn_readlane(bclaim, 0);
+            fetch(tb2, pb, nb);
+            process1(ta, pa);
+            cur_b = nb;
+            if (cur_b >= tb || over) break;
+            const int32_t nb2 = __builtin_amdgcn_readlane(bclaim, 0);
+            fetch(ta, pa, nb2);
+            process1(tb2, pb);
+            cur_b = nb2;
+          }
+        }
+        S.s_wcnt[wid] = over ? -1 : wcnt;
+        __syncthreads();
+        const int32_t wc = lane < NW ? S.s_wcnt[lane] : 0;
+        bool any_over = ballot(wc < 0) != 0;
+        const int32_t nrep =
+            __builtin_amdgcn_readlane(wave_incl_scan(wc > 0 ? wc : 0), kWave - 1);
+        any_over |= nrep >= kScores;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) seen4[4 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
+        if (any_over) {  // block-uniform
+          width = width / 2 > 0 ? width / 2 : 1;
+          continue;
+        }
+        __syncthreads();  // bitmap cleared
+        for (int o = lane; o < wcnt; o += kWave) {
+          const uint32_t id = S.lst[wid * kSeg + o];
+          atomicOr(&S.seen[(id >> 5) - lw], 1u << (id & 31));
+        }
+        const bool n_in = n >= lo && n < hi;  // block-uniform
+        if (tid == 0 && n_in) atomicOr(&S.seen[(n >> 5) - lw], 1u << (n & 31));
+        __syncthreads();  // repeated ids marked
+        {
+          uint4 q[4];
+          int32_t x4[3] = {0, 0, 0}, p4[3], t4[3];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            q[i] = seen4[4 * tid + i];
+            x4[0] += __popc(q[i].x) + __popc(q[i].y) + __popc(q[i].z) + __popc(q[i].w);
+          }
+          block_scan3<THREADS>(x4, p4, t4, S.ws);
+          const int32_t nrank = t4[0];
+          uint32_t run = (uint32_t)p4[0], pk[8];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t r0 = run;
+            run += __popc(q[i].x);
+            const uint32_t r1 = run;
+            run += __popc(q[i].y);
+            const uint32_t r2 = run;
+            run += __popc(q[i].z);
+            const uint32_t r3 = run;
+            run += __popc(q[i].w);
+            pk[2 * i] = r0 | (r1 << 16);
+            pk[2 * i + 1] = r2 | (r3 << 16);
+          }
+          if (nrank > 0) {  // block-uniform
+            wpre4[2 * tid] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+            wpre4[2 * tid + 1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+            for (int i = tid; i < nrank; i += THREADS) S.sc[i] = 0;
+          }
+        }
+        if (tid == 0) S.s_next = NW;
+        // ---- singles: the first pin of each slice that is not repeated
+        if (owner) {
+          for (uint32_t pp = cur; pp < end; ++pp) {
+            const uint32_t id = a.L.pins[pp] & kIdMask;
+            const bool rep = (seenw[id >> 5] >> (id & 31)) & 1u;
+            if (!rep && (v.all_valid || merge_valid(a, v, id, 0))) {
+              const uint64_t key = ((uint64_t)(uint32_t)w_j << 32) | (uint64_t)(kSent - id);
+              best = key > best ? key : best;
+              break;
+            }
+          }
+        }
+        __syncthreads();  // ranks, scores and the claim counter ready
+
+        // ---- sweep 2: weights of the repeat visits at their ranks
+        auto process2 = [&](const Batch& t, const uint32_t (&pin)[B]) {
+          uint32_t id[B], wv[B];
+          bool rep[B];
+          bool anyrep = false;
+#pragma unroll
+          for (int u = 0; u < B; ++u) {
+            id[u] = pin[u] & kIdMask;
+            const bool act = lofs[u] < (uint32_t)t.cnt[u] * 4u;
+            wv[u] = seenw[id[u] >> 5];
+            rep[u] = act & (__builtin_amdgcn_ubfe(wv[u], id[u], 1u) != 0);
+            anyrep |= rep[u];
+          }
+          if (ballot(anyrep) != 0) {  // wave-uniform
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+              if (rep[u]) {
+                const uint32_t rank = (uint32_t)S.wpre[(id[u] >> 5) - lw] +
+                                      (uint32_t)__popc(wv[u] & ((1u << (id[u] & 31)) - 1u));
+                atomicAdd(&S.sc[rank], (uint32_t)S.m_w[t.j[u]]);
+              }
+            }
+          }
+          asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
+        };
+        bclaim = wid;
+        {
+          Batch ta, tb2;
+          uint32_t pa[B], pb[B];
+          int32_t cur_b = wid;
+          fetch(ta, pa, cur_b);
+          while (cur_b < tb) {
+            const int32_t nb = __builtin_amdgcn_readlane(bclaim, 0);
+            fetch(tb2, pb, nb);
+            process2(ta, pa);
+            cur_b = nb;
+            if (cur_b >= tb) break;
+            const int32_t nb2 = __builtin_amdgcn_readlane(bclaim, 0);
+            fetch(ta, pa, nb2);
+            process2(tb2, pb);
+            cur_b = nb2;
+          }
+        }
+        __syncthreads();  // scores complete
+        // ---- fold: the repeated ids of the wave's list
+        for (int o = lane; o < wcnt; o += kWave) {
+          const uint32_t id = S.lst[wid * kSeg + o];
+          const uint32_t word = (id >> 5) - lw;
+          const uint32_t w = S.seen[word];
+          const uint32_t rank =
+              (uint32_t)S.wpre[word] + (uint32_t)__popc(w & ((1u << (id & 31)) - 1u));
+          const uint64_t key = ((uint64_t)S.sc[rank] << 32) | (uint64_t)(kSent - id);
+          if (id != n && key > best && (v.all_valid || merge_valid(a, v, id, 0))) best = key;
+        }
+        cur = end;
+        prev_wcnt = wcnt;
+        prev_lw = lw;
+        prev_nword = n_in ? (int32_t)((n >> 5) - lw) : -1;
+        lo = hi;
+        if (nrep < kList / 4 && width < kWinIds) width *= 2;
+      }
+    }
+    if (stop) best = 0;
+    best = block_max_u64<THREADS>(best, S.red);
+    if (tid == 0) {
+      if (best == 0) {
+        a.cand[v.n] = -1;
+        a.cscore[v.n] = 0;
+      } else {
+        a.cand[v.n] = (int32_t)(kSent - (uint32_t)(best & 0xFFFFFFFFull));
+        a.cscore[v.n] = (int32_t)(best >> 32);
+      }
+    }
+  }
+}
+
 __global__ void no_candidate_kernel(const Dims* __restrict__ d, int32_t* __restrict__ cand,
                                     int32_t* __restrict__ cscore, int32_t* __restrict__ work) {
   int64_t V = d->V;
@@ -1358,7 +1794,16 @@ void score_candidates(const ScoreArgs& a, int64_t maxV, int64_t maxP, hipStream_
   }
   k0<<<g[0], 256, 0, s>>>(a, 0, maxV, maxP);
   k1<<<g[1], 512, 0, s>>>(a, 1, maxV, maxP);
-  k2<<<g[2], 1024, 0, s>>>(a, 2, maxV);
+  if (a.n_win > 0 && a.splits) {
+    static int g2[kMaxDevices] = {};
+    auto k2w = score_window2_kernel<1024>;
+    if (!g2[dev]) g2[dev] = persistent_grid(k2w, 1024);
+    window_splits_kernel<<<4096, 256, 0, s>>>(
+        a.L.dims, a.L.eoff, a.L.pins, a.n_win, a.splits);
+    k2w<<<g2[dev], 1024, 0, s>>>(a, 2, maxV);
+  } else {
+    k2<<<g[2], 1024, 0, s>>>(a, 2, maxV);
+  }
   k3<<<g[3], 512, 0, s>>>(a, 3, maxV, maxP);
   k4<<<g[4], 256, 0, s>>>(a, 4, maxV, maxP);
   k5<<<g[5], 512, 0, s>>>(a, 5, maxV, maxP);

@@ -250,3 +250,11 @@ def hub_graph(seed: int, n: int, fan: int, n_hubs: int, hub_p: float, w_max: int
         w[s] = int(rng.integers(1, w_max + 1))
     return Level0(n, np.array(eoff, dtype=np.int64), np.concatenate(pins).astype(np.uint32), w,
                   f"hub{n}f{fan}h{n_hubs}s{seed}")
+
+
+def start_orders(seed: int, n_nodes: int, n_starts: int) -> np.ndarray:
+    """Random initial node orders of the multi-start placement: n_starts
+    seeded permutations of 0..n_nodes-1 (int32 [n_starts, n_nodes])."""
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.permutation(n_nodes) for _ in range(n_starts)]).astype(np.int32) \
+        if n_starts > 0 else np.zeros((0, n_nodes), np.int32)

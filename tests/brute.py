@@ -266,3 +266,159 @@ def refine_round(level_edges, w, part, n_parts, members, orig, lim):
     for _, n, a, p in moves[:best_len]:
         out[n] = p
     return out, [len(moves), best_len, best_cum]
+
+
+def manhattan(a, b, height):
+    return abs(a // height - b // height) + abs(a % height - b % height)
+
+
+def residual_distance(level_edges, w, core, height):
+    """Sum over hyperedges of w(e) times the distances of all unordered pin
+    pairs (the placement objective)."""
+    d = 0
+    for e, pl in enumerate(level_edges):
+        vs = [v for v, _ in pl]
+        s = 0
+        for i in range(len(vs)):
+            for j in range(i + 1, len(vs)):
+                s += manhattan(core[vs[i]], core[vs[j]], height)
+        d += int(w[e]) * s
+    return d
+
+
+def place_refine_round(level_edges, w, core, width, height):
+    """One swap-refinement round (Section 4.2) by enumeration: each tension is
+    the decrease of the residual distance of a swap computed from scratch;
+    the matching is Eq. 13 by literal recursion over cores; each prefix is
+    applied and evaluated from scratch.  Returns (new core, applied)."""
+    V = len(core)
+    C = width * height
+    occ = [-1] * C
+    for p in range(V):
+        occ[core[p]] = p
+    base = residual_distance(level_edges, w, core, height)
+
+    def swapped(cr, oc, a, b):
+        cr = list(cr)
+        pa, pb = oc[a], oc[b]
+        if pa >= 0:
+            cr[pa] = b
+        if pb >= 0:
+            cr[pb] = a
+        return cr
+
+    def tension(a, b):
+        return base - residual_distance(level_edges, w, swapped(core, occ, a, b), height)
+
+    cand, score = [-1] * C, [0] * C
+    for h in range(C):
+        if occ[h] < 0:
+            continue
+        x, y = divmod(h, height)
+        best, bk = 0, -1
+        for nx, ny in ((x - 1, y), (x, y - 1), (x, y + 1), (x + 1, y)):
+            if 0 <= nx < width and 0 <= ny < height:
+                k = nx * height + ny
+                t = tension(h, k)
+                if t > best:
+                    best, bk = t, k
+        cand[h], score[h] = bk, best
+    m = match_eq13_scores(cand, score)
+    swaps = sorted(((tension(h, m[h]), h, m[h]) for h in range(C) if m[h] > h),
+                   key=lambda s: (-s[0], s[1]))
+    cur = list(core)
+    best_cum, best_len = 0, 0
+    for i in range(len(swaps)):
+        trial = list(core)
+        oc = list(occ)
+        for _, a, b in swaps[:i + 1]:
+            trial = swapped(trial, oc, a, b)
+            oc[a], oc[b] = oc[b], oc[a]
+        cum = base - residual_distance(level_edges, w, trial, height)
+        if cum > best_cum:
+            best_cum, best_len = cum, i + 1
+    oc = list(occ)
+    for _, a, b in swaps[:best_len]:
+        cur = swapped(cur, oc, a, b)
+        oc[a], oc[b] = oc[b], oc[a]
+    return cur, best_len, best_cum
+
+
+def match_eq13_scores(cand, score):
+    """Eq. (13) by literal memoised recursion, for given candidates and the
+    score of each candidate arc (best child: largest score, lowest id)."""
+    n_items = len(cand)
+    memo = {}
+
+    def best_child(n):
+        kids = [m for m in range(n_items) if cand[m] == n]
+        if not kids:
+            return -1
+        return min(kids, key=lambda m: (-score[m], m))
+
+    def match(n):
+        if n in memo:
+            return memo[n]
+        c = cand[n]
+        r = c if c >= 0 and (cand[c] == n or match(c) == n) else best_child(n)
+        memo[n] = r
+        return r
+
+    return [match(n) for n in range(n_items)]
+
+
+def initial_placement(level_edges, w, V, hilbert, order0, lp_rounds):
+    """Initial placement (Section 4.2) by enumeration: recursive bisection
+    where each node's gain is the drop of the section's cut recomputed from
+    scratch after moving it alone, label-propagation swaps of the best pairs,
+    then folding by connection weights counted from scratch; the i-th node of
+    the result on core hilbert[i]."""
+    seq = [int(x) for x in order0]
+    pins = [{v for v, _ in pl} for pl in level_edges]
+
+    def cut(A, Bs):
+        return sum(int(w[e]) for e, ps in enumerate(pins) if ps & A and ps & Bs)
+
+    sections = [(0, V)]
+    while sections:
+        nxt = []
+        for st, ln in sections:
+            if ln < 2:
+                continue
+            nl = ln - ln // 2
+            for _ in range(lp_rounds):
+                L, R = set(seq[st:st + nl]), set(seq[st + nl:st + ln])
+                base = cut(L, R)
+                gl = sorted((-(base - cut(L - {u}, R | {u})), u) for u in L)
+                gr = sorted((-(base - cut(L | {u}, R - {u})), u) for u in R)
+                pos = {seq[i]: i for i in range(st, st + ln)}
+                done = 0
+                for (a, u), (b, v) in zip(gl, gr):
+                    if -a - b <= 0:
+                        break
+                    seq[pos[u]], seq[pos[v]] = seq[pos[v]], seq[pos[u]]
+                    done += 1
+                if not done:
+                    break
+            nxt += [(st, nl), (st + nl, ln - nl)]
+        sections = nxt
+
+    def fold(st, ln, side, us, ul):
+        if ln == 1:
+            return [seq[st]]
+        nl = ln - ln // 2
+        c0 = fold(st, nl, 0, st + nl, ln - nl)
+        c1 = fold(st + nl, ln - nl, 1, st, nl)
+        out = c0 + c1
+        if side >= 0:
+            u = set(seq[us:us + ul])
+            k0, k1 = cut(set(seq[st:st + nl]), u), cut(set(seq[st + nl:st + ln]), u)
+            if (side == 0 and k0 > k1) or (side == 1 and k1 > k0):
+                out = out[::-1]
+        return out
+
+    order = fold(0, V, -1, 0, 0) if V else []
+    core = [0] * V
+    for i, v in enumerate(order):
+        core[v] = int(hilbert[i])
+    return core

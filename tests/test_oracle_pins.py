@@ -359,3 +359,75 @@ def test_refinement_never_worsens_and_keeps_limits():
         bad = (rep.size > lim.max_neurons) | (rep.syn > lim.max_synapses) | \
               (rep.ax > lim.max_axons)
         assert np.all(rep.size[bad] <= 1)
+
+
+def test_hilbert_order():
+    """Every core once; on a power-of-two square consecutive cores are
+    neighbours (the curve's locality)."""
+    for w, h in ((1, 1), (2, 2), (8, 8), (64, 64), (5, 3), (6, 11)):
+        hc = oracle.hilbert_cores(w, h)
+        assert sorted(hc.tolist()) == list(range(w * h))
+    hc = oracle.hilbert_cores(16, 16)
+    steps = [brute.manhattan(int(a), int(b), 16) for a, b in zip(hc[:-1], hc[1:])]
+    assert set(steps) == {1}
+    assert oracle.hilbert_cores(2, 2).tolist() == [0, 1, 3, 2]  # (0,0) (0,1) (1,1) (1,0)
+
+
+def _gp(seed, n, lim):
+    """A small partitioned hypergraph G_P (final super-nodes as nodes)."""
+    g = synth.uniform(seed, n, 1, 8)
+    h = oracle.hierarchy(g, lim)
+    return h.levels[-1].level
+
+
+@pytest.mark.parametrize("block", range(3))
+def test_swap_round_vs_brute_force(block):
+    """A swap-refinement round (Eq. 14, 15 and the matching and prefix of
+    Section 4.2) against enumeration, where every tension and every prefix
+    is the decrease of the residual distance recomputed from scratch."""
+    rng = np.random.default_rng(900 + block)
+    applied = 0
+    for it in range(8):
+        L = _gp(int(rng.integers(0, 1 << 20)), int(rng.integers(30, 90)), synth.Limits(6, 60, 20))
+        w, h = (int(x) for x in rng.integers(2, 7, 2))
+        if L.V > w * h:
+            w = h = int(np.ceil(np.sqrt(L.V))) + 1
+        core = rng.permutation(w * h)[:L.V].astype(np.int32)
+        got, info = oracle.place_refine(L, w, h, core, max_rounds=1)
+        exp, n_app, dec = brute.place_refine_round(brute.edges_of(L.eoff, L.pins), L.w,
+                                                   core.tolist(), w, h)
+        assert got.tolist() == exp, it
+        assert (int(info[1]), int(info[2])) == (n_app, dec), it
+        applied += n_app > 0
+    assert applied > 0
+
+
+@pytest.mark.parametrize("block", range(3))
+def test_initial_placement_vs_brute_force(block):
+    """Initial placement (Hilbert order, recursive bisection with label
+    propagation, folding) against enumeration, where every gain is the drop
+    of a section's cut recomputed from scratch and every folding decision
+    compares connection weights counted from scratch."""
+    rng = np.random.default_rng(700 + block)
+    for it in range(6):
+        L = _gp(int(rng.integers(0, 1 << 20)), int(rng.integers(40, 120)), synth.Limits(5, 60, 20))
+        w = h = int(np.ceil(np.sqrt(L.V))) + int(rng.integers(0, 3))
+        order0 = rng.permutation(L.V).astype(np.int32)
+        got = oracle.initial_placement(L, w, h, order0, lp_rounds=3)
+        exp = brute.initial_placement(brute.edges_of(L.eoff, L.pins), L.w, L.V,
+                                      oracle.hilbert_cores(w, h), order0, 3)
+        assert got.tolist() == exp, it
+        assert len(set(got.tolist())) == L.V
+
+
+def test_placement_improves_residual_distance():
+    """Multi-start placement: refinement never raises a start's residual
+    distance, and the chosen start has the least."""
+    L = _gp(3, 400, synth.Limits(8, 100, 30))
+    orders = synth.start_orders(5, L.V, 4)
+    core, best, dists = oracle.place(L, 16, 16, orders)
+    for k, o in enumerate(orders):
+        c0 = oracle.initial_placement(L, 16, 16, o)
+        assert dists[k] <= oracle.residual_distance(L, 16, c0)
+    assert dists[best] == dists.min() and best == int(np.argmin(dists))
+    assert oracle.residual_distance(L, 16, core) == dists[best]
