@@ -598,6 +598,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--start-level", type=int, default=0,
+                    help="level mode: time this level of the hierarchy (the levels before it "
+                         "are coarsened first, untimed)")
     ap.add_argument("--rounds", type=int, default=16,
                     help="partition mode: refinement rounds per level at most")
     ap.add_argument("--mode", default="level",
@@ -662,6 +665,16 @@ def main():
     ctx = hg.Context(0)
     L = ctx.upload(g)
     ctx.sync()
+    for k in range(args.start_level):  # coarser levels of the same hierarchy
+        out = ctx.coarsen_level(L, lim, want_candidates=False)
+        L = ctx.contract(L, out["vmap"], out["n_coarse"])
+        print(f"[bench] level {k + 1}: V={L.V} E={L.E} P={L.P}", file=sys.stderr, flush=True)
+    if args.start_level:
+        V, E, P = L.V, L.E, L.P
+        h = L.to_host()
+        lens = np.diff(h["eoff"]).astype(np.int64)
+        X = int(np.sum(lens * (lens - 1)))
+        del h
     ctx.enable_timing(True)
 
     def step():
@@ -728,7 +741,8 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": wl["desc"], "seed": args.seed, "vertices": V, "hyperedges": E,
+        "config": {"workload": wl["desc"].replace("level 0", f"level {args.start_level}"),
+                   "seed": args.seed, "vertices": V, "hyperedges": E,
                    "pins": P, "neighbour_visits": X, "coarse_vertices": C.V,
                    "coarse_hyperedges": C.E, "coarse_pins": C.P},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -743,7 +757,7 @@ def main():
         "scratch_bytes": ctx.scratch_bytes(),
         "conn_invariant_ok": conn_ok,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.start_level == 0:
         print("[bench] timing the CPU oracle on samples of every step", file=sys.stderr,
               flush=True)
         full = ctx.coarsen_level(L, lim)

@@ -1334,8 +1334,12 @@ __global__ void window_splits_kernel(const Dims* __restrict__ d, const int64_t* 
   }
 }
 
-// Windows with exact slices (large neighbourhoods where the distinct-axon
-// overlap cannot bind, at most kWinDeg incident hyperedges).  The id space
+// Windows with exact slices (large neighbourhoods, at most kWinDeg incident
+// hyperedges).  OV: the distinct-axon bound of Section 3 can bind for the
+// vertex, so the overlap of n and m (the multiplicity of the hyperedges in
+// which both carry the destination flag) enters the validity test: for a
+// single it is the visiting hyperedge's multiplicity when both flags are set;
+// for a repeated id it is summed in sweep 2 next to the score.  The id space
 // is cut into aligned windows of 2^kWinAlignBits ids, and every hyperedge's
 // pins at those boundaries are known from `splits`, so a window's slice of
 // each incident hyperedge is exact and no pin is tested against the window.
@@ -1357,7 +1361,7 @@ __global__ void window_splits_kernel(const Dims* __restrict__ d, const int64_t* 
 // A window whose chunks, repeat visits or repeated ids exceed the LDS room
 // is retried at half the width (slices cut again by binary search), and the
 // width grows back once windows fit.
-template <int THREADS>
+template <int THREADS, bool OV>
 __global__ __launch_bounds__(THREADS) void score_window2_kernel(ScoreArgs a, int bucket,
                                                                int64_t maxV) {
   constexpr int NW = THREADS / kWave;
@@ -1367,7 +1371,7 @@ __global__ __launch_bounds__(THREADS) void score_window2_kernel(ScoreArgs a, int
   constexpr int kList = 4096;
   constexpr int kSeg = kList / NW;
   constexpr int kScores = 4096;
-  constexpr int kMaxChunks = 1536;
+  constexpr int kMaxChunks = OV ? 1024 : 1536;
   constexpr uint32_t kSent = 0x7FFFFFFFu;
   static_assert(kWords == 16 * THREADS, "a thread owns 16 consecutive bitmap words");
   static_assert(kWinDeg <= THREADS, "thread j owns hyperedge j");
@@ -1377,8 +1381,10 @@ __global__ __launch_bounds__(THREADS) void score_window2_kernel(ScoreArgs a, int
     alignas(16) uint16_t wpre[kWords];   // repeated ids in the words before each word
     uint32_t lst[kList + kWave];         // repeat visits, wave w's from w * kSeg on
     uint32_t sc[kScores];                // score of each rank
+    uint32_t ovsc[OV ? kScores : 1];     // overlap of each rank (OV)
     uint2 desc[kMaxChunks + B];          // x: first pin; y: hyperedge | pin count << 10
     int32_t m_w[kWinDeg];
+    int32_t m_mu[OV ? kWinDeg : 1];      // mult of hyperedge j if n has its flag, else 0
     int32_t s_wcnt[NW];
     int32_t ws[3 * NW];
     uint64_t red[2 * NW];
@@ -1435,13 +1441,18 @@ __global__ __launch_bounds__(THREADS) void score_window2_kernel(ScoreArgs a, int
     // cursor of the unprocessed part of its slice
     const bool owner = tid < deg;
     uint32_t e_j = 0, cur = 0;
-    int32_t w_j = 0;
+    int32_t w_j = 0, mu_j = 0;
     const uint32_t* srow = nullptr;
     if (owner) {
-      e_j = a.vinc[v.beg + tid] & kIdMask;
+      const uint32_t ent = a.vinc[v.beg + tid];
+      e_j = ent & kIdMask;
       cur = (uint32_t)a.L.eoff[e_j];
       w_j = a.L.w[e_j];
       S.m_w[tid] = w_j;
+      if (OV) {
+        mu_j = (ent & kDst) ? a.L.mult[e_j] : 0;
+        S.m_mu[tid] = mu_j;
+      }
       srow = a.splits + (int64_t)e_j * (W + 1);
     }
     int passes = 0;
@@ -1647,16 +1658,23 @@ __global__ __launch_bounds__(THREADS) void score_window2_kernel(ScoreArgs a, int
           if (nrank > 0) {  // block-uniform
             wpre4[2 * tid] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
             wpre4[2 * tid + 1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
-            for (int i = tid; i < nrank; i += THREADS) S.sc[i] = 0;
+            for (int i = tid; i < nrank; i += THREADS) {
+              S.sc[i] = 0;
+              if (OV) S.ovsc[i] = 0;
+            }
           }
         }
         if (tid == 0) S.s_next = NW;
-        // ---- singles: the first pin of each slice that is not repeated
+        // ---- singles: the first pin of each slice that is not repeated (a
+        // single shares one hyperedge with n: its overlap is that
+        // hyperedge's multiplicity when both carry the flag)
         if (owner) {
           for (uint32_t pp = cur; pp < end; ++pp) {
-            const uint32_t id = a.L.pins[pp] & kIdMask;
+            const uint32_t pin = a.L.pins[pp];
+            const uint32_t id = pin & kIdMask;
             const bool rep = (seenw[id >> 5] >> (id & 31)) & 1u;
-            if (!rep && (v.all_valid || merge_valid(a, v, id, 0))) {
+            const int64_t ov = (OV && (pin & kDst)) ? mu_j : 0;
+            if (!rep && (v.all_valid || merge_valid(a, v, id, ov))) {
               const uint64_t key = ((uint64_t)(uint32_t)w_j << 32) | (uint64_t)(kSent - id);
               best = key > best ? key : best;
               break;
@@ -1668,6 +1686,7 @@ __global__ __launch_bounds__(THREADS) void score_window2_kernel(ScoreArgs a, int
         // ---- sweep 2: weights of the repeat visits at their ranks
         auto process2 = [&](const Batch& t, const uint32_t (&pin)[B]) {
           uint32_t id[B], wv[B];
+          (void)pin;
           bool rep[B];
           bool anyrep = false;
 #pragma unroll
@@ -1685,6 +1704,10 @@ __global__ __launch_bounds__(THREADS) void score_window2_kernel(ScoreArgs a, int
                 const uint32_t rank = (uint32_t)S.wpre[(id[u] >> 5) - lw] +
                                       (uint32_t)__popc(wv[u] & ((1u << (id[u] & 31)) - 1u));
                 atomicAdd(&S.sc[rank], (uint32_t)S.m_w[t.j[u]]);
+                if (OV) {
+                  const int32_t mu = S.m_mu[t.j[u]];
+                  if (mu && (pin[u] & kDst)) atomicAdd(&S.ovsc[rank], (uint32_t)mu);
+                }
               }
             }
           }
@@ -1717,7 +1740,8 @@ __global__ __launch_bounds__(THREADS) void score_window2_kernel(ScoreArgs a, int
           const uint32_t rank =
               (uint32_t)S.wpre[word] + (uint32_t)__popc(w & ((1u << (id & 31)) - 1u));
           const uint64_t key = ((uint64_t)S.sc[rank] << 32) | (uint64_t)(kSent - id);
-          if (id != n && key > best && (v.all_valid || merge_valid(a, v, id, 0))) best = key;
+          const int64_t ov = OV ? (int64_t)S.ovsc[rank] : 0;
+          if (id != n && key > best && (v.all_valid || merge_valid(a, v, id, ov))) best = key;
         }
         cur = end;
         prev_wcnt = wcnt;
@@ -1794,20 +1818,28 @@ void score_candidates(const ScoreArgs& a, int64_t maxV, int64_t maxP, hipStream_
   }
   k0<<<g[0], 256, 0, s>>>(a, 0, maxV, maxP);
   k1<<<g[1], 512, 0, s>>>(a, 1, maxV, maxP);
-  if (a.n_win > 0 && a.splits) {
-    static int g2[kMaxDevices] = {};
-    auto k2w = score_window2_kernel<1024>;
-    if (!g2[dev]) g2[dev] = persistent_grid(k2w, 1024);
-    window_splits_kernel<<<4096, 256, 0, s>>>(
-        a.L.dims, a.L.eoff, a.L.pins, a.n_win, a.splits);
-    k2w<<<g2[dev], 1024, 0, s>>>(a, 2, maxV);
+  const bool aligned = a.n_win > 0 && a.splits;
+  static int g2[kMaxDevices][2] = {};
+  auto k2w = score_window2_kernel<1024, false>;
+  auto k6w = score_window2_kernel<1024, true>;
+  if (aligned) {
+    if (!g2[dev][0]) {
+      g2[dev][0] = persistent_grid(k2w, 1024);
+      g2[dev][1] = persistent_grid(k6w, 1024);
+    }
+    window_splits_kernel<<<4096, 256, 0, s>>>(a.L.dims, a.L.eoff, a.L.pins, a.n_win,
+                                              a.splits);
+    k2w<<<g2[dev][0], 1024, 0, s>>>(a, 2, maxV);
   } else {
     k2<<<g[2], 1024, 0, s>>>(a, 2, maxV);
   }
   k3<<<g[3], 512, 0, s>>>(a, 3, maxV, maxP);
   k4<<<g[4], 256, 0, s>>>(a, 4, maxV, maxP);
   k5<<<g[5], 512, 0, s>>>(a, 5, maxV, maxP);
-  k6<<<g[6], 1024, 0, s>>>(a, 6, maxV);
+  if (aligned)
+    k6w<<<g2[dev][1], 1024, 0, s>>>(a, 6, maxV);
+  else
+    k6<<<g[6], 1024, 0, s>>>(a, 6, maxV);
   k7<<<g[7], 512, 0, s>>>(a, 7, maxV, maxP);
 }
 
