@@ -59,13 +59,14 @@ WORKLOADS = {
 
 
 # The score kernel of each work list of the library's bucket rule (lists 4-7
-# also count shared inbound axons); list 2 uses the aligned-window variant on
-# levels of at most 16 windows of 2^19 ids.
+# and 9 also count shared inbound axons); lists 2 and 6 use the aligned-window
+# variant on levels of at most 16 windows of 2^19 ids.
 SCORE_KERNELS = (
     "score_block_kernel<256,4096>", "score_block_kernel<512,16384>",
     "score_window_kernel<1024>", "score_block_kernel<512,16384,multipass>",
     "score_block_kernel<256,4096,overlap>", "score_block_kernel<512,8192,overlap>",
     "score_stream_kernel<1024,8192,overlap>", "score_block_kernel<512,8192,multipass,overlap>",
+    "score_dense_kernel<1024>", "score_dense_kernel<1024,overlap>",
 )
 
 
@@ -239,7 +240,7 @@ def run_batch(args):
     _log(f"{args.graphs} graphs: V={V} E={E} P={P} ({time.perf_counter() - t0:.1f} s)")
     sample = sorted(range(len(levels)), key=lambda i: levels[i].P)[:: max(1, len(levels) // 6)]
     tuned = tune.autotune(ctx, [levels[i] for i in sample], [lim] * len(sample), verbose=True)
-    _log(f"tuning: {tuned['single_pass_load16']}/{tuned['pass_fill16']}")
+    _log(f"tuning: {tuned['single_pass_load16']}/{tuned['pass_fill16']}/{tuned['dense_ratio']}")
 
     def plain_level():
         for L in levels:
@@ -340,7 +341,7 @@ def run_batch(args):
                    "unions": len(groups)},
         "plain_pins_per_s": P / t_plain,
         "batched_vs_plain": t_plain / t_batch,
-        "tuning": {k: tuned[k] for k in ("single_pass_load16", "pass_fill16")},
+        "tuning": {k: tuned[k] for k in ("single_pass_load16", "pass_fill16", "dense_ratio")},
         "hierarchies_mid": hier_mid,
         "hierarchies_small": hier_small,
     }
@@ -720,8 +721,8 @@ def main():
     n_by_list, visits_by_list = ctx.score_census()
     top = int(np.argmax(visits_by_list))
     kernel = SCORE_KERNELS[top]
-    if top == 2 and V <= (16 << 19):
-        kernel = "score_window2_kernel<1024>"
+    if top in (2, 6) and V <= (16 << 19):
+        kernel = "score_window2_kernel<1024%s>" % (",overlap" if top == 6 else "")
     value = P / (ms_step / 1000.0)
     b_s2 = s2_bytes(V, E, P, X)
     t_s2 = phases["score"] / 1000.0

@@ -290,16 +290,21 @@ int hg_connectivity_static(hg_ctx* ctx, const hg_level* lvl, const int32_t* part
  * one pass over an on-chip table when its distinct-neighbour bound (its
  * expansion, the sum of the sizes of its incident hyperedges, capped by the
  * vertex count) is at most single_pass_load16/16 of the table's slots.
- * Larger neighbourhoods are scored in windows of neighbour ids with an
- * on-chip bitmap.  Where the distinct-axon overlap of Section 3 can bind, or
- * a vertex has more than 768 incident hyperedges, they are scored in passes
- * over a table, each range aimed at pass_fill16/16 of it.  Results never depend on these values, only the
- * speed does.  Defaults 8 and 5; accepted ranges 1..12 and 1..10
+ * Larger neighbourhoods that visit at least one id in dense_ratio of the
+ * level's ids (dense_ratio * expansion >= V; 0 disables it) are scored in
+ * dense windows of 2^14 ids, one packed (score, overlap) word per id, on
+ * levels of at most 2^21 vertices.  Other large neighbourhoods are scored in
+ * windows of neighbour ids with an on-chip bitmap of seen ids (at most 768
+ * incident hyperedges), else in passes over a table, each range aimed at
+ * pass_fill16/16 of it where the distinct-axon overlap of Section 3 can
+ * bind.  Results never depend on these values, only the speed does.
+ * Defaults 8, 5 and 8; accepted ranges 1..12, 1..10 and 0..64
  * (HG_ERR_INVALID_ARG otherwise).
  */
 typedef struct {
   int32_t single_pass_load16;
   int32_t pass_fill16;
+  int32_t dense_ratio;
 } hg_tuning;
 int hg_set_tuning(hg_ctx* ctx, const hg_tuning* tuning);
 int hg_get_tuning(hg_ctx* ctx, hg_tuning* tuning);
@@ -356,12 +361,17 @@ int hg_batch_sizes(hg_batch* batch, int64_t* sizes);
 /*
  * Census of the score step (Eq. 12) of the most recent hg_coarsen_level on
  * the context (synchronous): out[k] = vertices scored by work list k and
- * out[8 + k] = their neighbour visits (sum over incident hyperedges of the
- * hyperedge's size less one), for the 8 lists of the bucket rule described
- * at hg_tuning: single pass in the small table, single pass in the big
- * table, windows, passes over a table; lists 4-7 the same where the
- * distinct-axon overlap of Section 3 can bind.  `out` is host int64[16].
+ * out[HG_SCORE_LISTS + k] = their neighbour visits (sum over incident
+ * hyperedges of the hyperedge's size less one), for the lists of the bucket
+ * rule described at hg_tuning: 0 single pass in the small table, 1 single
+ * pass in the big table, 2 windows with a bitmap of seen ids, 3 passes over a
+ * table; 4-7 the same where the distinct-axon overlap of Section 3 can bind;
+ * 8 and 9 (without and with the overlap) dense windows, taken by the large
+ * neighbourhoods of lists 2, 3, 6, 7 that visit at least one id in 8 of the
+ * level, on levels of at most 2^21 vertices.  `out` is host
+ * int64[2 * HG_SCORE_LISTS].
  */
+#define HG_SCORE_LISTS 10
 int hg_score_census(hg_ctx* ctx, int64_t* out);
 
 /*

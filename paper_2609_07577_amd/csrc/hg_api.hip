@@ -232,8 +232,11 @@ int hg_set_tuning(hg_ctx* c, const hg_tuning* t) {
                 t->single_pass_load16);
   if (t->pass_fill16 < 1 || t->pass_fill16 > 10)
     return fail(c, HG_ERR_INVALID_ARG, "pass_fill16 %d outside 1..10", t->pass_fill16);
+  if (t->dense_ratio < 0 || t->dense_ratio > 64)
+    return fail(c, HG_ERR_INVALID_ARG, "dense_ratio %d outside 0..64", t->dense_ratio);
   c->tuning.load16 = t->single_pass_load16;
   c->tuning.fill16 = t->pass_fill16;
+  c->tuning.dense_ratio = t->dense_ratio;
   return HG_OK;
 }
 
@@ -241,6 +244,7 @@ int hg_get_tuning(hg_ctx* c, hg_tuning* t) {
   if (!c || !t) return HG_ERR_INVALID_ARG;
   t->single_pass_load16 = c->tuning.load16;
   t->pass_fill16 = c->tuning.fill16;
+  t->dense_ratio = c->tuning.dense_ratio;
   return HG_OK;
 }
 
@@ -321,7 +325,7 @@ int hg_coarsen_level(hg_ctx* c, const hg_level* in, const hg_limits* lim, int32_
   weight_sum_kernel<<<1, 1, 0, s>>>(c->dev_wsum, c->dev_err);
   build_incidence(L, V, E, P, S.vcount, S.voff, S.vinc, S.partials, s);
   Buckets b{S.bcount, S.blist, S.bvisits};
-  expansion_and_buckets(L, S.voff, S.vinc, V, S.xn, S.gc, 1, b, c->tuning, s);
+  expansion_and_buckets(L, S.voff, S.vinc, V, S.xn, S.gc, 1, b, c->tuning, s, S.n_win14);
   census_kernel<<<1, 64, 0, s>>>(S.bcount, S.bvisits, c->dev_census);
   mark(c, 0, 1);
   // S2
@@ -331,6 +335,8 @@ int hg_coarsen_level(hg_ctx* c, const hg_level* in, const hg_limits* lim, int32_
                cs, S.work, b,      c->dev_err, c->tuning.fill16};
   sa.splits = S.splits;
   sa.n_win = S.n_win;
+  sa.splits14 = S.splits14;
+  sa.n_win14 = S.n_win14;
   mark(c, 1, 0);
   score_candidates(sa, V, P, s);
   mark(c, 1, 1);

@@ -154,6 +154,8 @@ struct CoarsenScratch {
   int64_t* partials;
   uint32_t* splits;
   int32_t n_win;
+  uint32_t* splits14;
+  int32_t n_win14;
   void carve(A& a, int64_t V, int64_t E, int64_t P) {
     dims = a.template take<Dims>(1);
     gc = a.template take<GraphConst>(1);
@@ -177,6 +179,9 @@ struct CoarsenScratch {
     const int64_t w = (V + (1ll << kWinAlignBits) - 1) >> kWinAlignBits;
     n_win = (w >= 1 && w <= kMaxAlignedWindows) ? (int32_t)w : 0;
     splits = n_win ? a.template take<uint32_t>(E * (n_win + 1)) : nullptr;
+    const int64_t w14 = (V + (1ll << kDenseBits) - 1) >> kDenseBits;
+    n_win14 = (w14 >= 1 && w14 <= kMaxDenseWindows) ? (int32_t)w14 : 0;
+    splits14 = n_win14 ? a.template take<uint32_t>(E * (n_win14 + 1)) : nullptr;
   }
 };
 

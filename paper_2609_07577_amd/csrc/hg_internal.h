@@ -51,6 +51,7 @@ struct GraphConst {
 struct Tuning {
   int32_t load16 = 8;  // single-pass tables take X_n up to load16/16 of their slots
   int32_t fill16 = 5;  // multipass ranges aim at fill16/16 of the stream table
+  int32_t dense_ratio = 8;  // dense windows for X_n * dense_ratio >= V (0: never)
 };
 
 // Device views of a level.
@@ -127,8 +128,12 @@ void level0_state(const Dims* d, const int64_t* eoff, const uint32_t* pins, int6
 // Buckets 0-3 without, 4-7 with the shared-inbound count: single pass in the
 // small table, single pass in the big table, multipass with the incident
 // hyperedges staged in LDS (degree <= kWinDeg), multipass with them read
-// from global memory.
-constexpr int kNumBuckets = 8;
+// from global memory; 8 without, 9 with it: dense windows (large
+// neighbourhoods that visit at least one id in Tuning::dense_ratio of the
+// level).
+constexpr int kNumBuckets = 10;
+constexpr int kDenseBits = 14;          // ids per dense window: 2^14
+constexpr int kMaxDenseWindows = 128;   // levels of at most 2^21 vertices
 constexpr int kSmallSlots = 4096;
 constexpr int kBigSlots = 16384;
 constexpr int kBigSlotsOv = 8192;
@@ -141,7 +146,7 @@ struct Buckets {
 };
 void expansion_and_buckets(const LevelView& L, const int64_t* voff, const uint32_t* vinc,
                            int64_t maxV, int64_t* xn, GraphConst* gc, int32_t n_graphs,
-                           Buckets b, Tuning t, hipStream_t s);
+                           Buckets b, Tuning t, hipStream_t s, int32_t dense_windows = 0);
 
 // ---- S2 (hg_score.hip) ----------------------------------------------------
 struct ScoreArgs {
@@ -163,6 +168,9 @@ struct ScoreArgs {
   // step are not aligned (the level has too many ids for the array).
   uint32_t* splits = nullptr;
   int32_t n_win = 0;
+  // The same at the dense windows of kDenseBits bits (n_win14 = 0: none).
+  uint32_t* splits14 = nullptr;
+  int32_t n_win14 = 0;
 };
 constexpr int kWinAlignBits = 19;
 constexpr int kMaxAlignedWindows = 16;

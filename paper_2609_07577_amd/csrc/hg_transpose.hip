@@ -136,7 +136,7 @@ __global__ void expansion_kernel(LevelView L, const int64_t* __restrict__ voff,
 __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
                               const int64_t* __restrict__ voff,
                               const GraphConst* __restrict__ gc, Buckets b, int64_t maxV,
-                              int32_t load16) {
+                              int32_t load16, int32_t dense_windows, int32_t dense_ratio) {
   const int64_t V = L.dims->V;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -160,6 +160,10 @@ __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
         else if (dist <= (int64_t)(ov ? kBigSlotsOv : kBigSlots) * load16 / 16) bk = 1;
         else bk = (voff[v + 1] - voff[v] <= kWinDeg) ? 2 : 3;
         if (ov) bk += 4;
+        // dense neighbourhoods (visits at least a kDenseRatio-th of the ids)
+        if ((bk & 3) >= 2 && dense_windows > 0 && dense_ratio > 0 &&
+            x * dense_ratio >= (int64_t)G.nverts)
+          bk = ov ? 9 : 8;
       }
     }
     const int32_t pos = wave_bucket_slot<kNumBuckets>(bk, b.count);
@@ -202,11 +206,12 @@ void level0_state(const Dims* d, const int64_t* eoff, const uint32_t* pins, int6
 
 void expansion_and_buckets(const LevelView& L, const int64_t* voff, const uint32_t* vinc,
                            int64_t maxV, int64_t* xn, GraphConst* gc, int32_t n_graphs,
-                           Buckets b, Tuning t, hipStream_t s) {
+                           Buckets b, Tuning t, hipStream_t s, int32_t dense_windows) {
   reset_maxima_kernel<<<1, 256, 0, s>>>(gc, n_graphs, b.count, b.visits);
   expansion_kernel<<<grid_for(maxV, 4, 16384), 256, 0, s>>>(L, voff, vinc, xn, gc, b, maxV);
   bucket_kernel<<<grid_for(maxV, 256, 16384), 256, 0, s>>>(L, xn, voff, gc, b, maxV,
-                                                          t.load16);
+                                                          t.load16, dense_windows,
+                                                          t.dense_ratio);
 }
 
 }  // namespace hg

@@ -39,6 +39,7 @@ EXPORTED = ("hg_create", "hg_destroy", "hg_set_stream", "hg_last_error", "hg_syn
             "hg_batch_step", "hg_batch_done", "hg_batch_result", "hg_batch_compact",
             "hg_batch_sizes")
 NUM_PHASES = 5
+SCORE_LISTS = 10  # HG_SCORE_LISTS
 PHASES = ("incidence", "score", "match", "contract", "connectivity")
 
 
@@ -54,7 +55,7 @@ class Limits(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     """Score-step tuning (hg_tuning): results never depend on it."""
-    _fields_ = [("single_pass_load16", _i32), ("pass_fill16", _i32)]
+    _fields_ = [("single_pass_load16", _i32), ("pass_fill16", _i32), ("dense_ratio", _i32)]
 
 
 class _Level(ctypes.Structure):
@@ -191,20 +192,23 @@ class Context:
     def scratch_bytes(self) -> int:
         return int(self.lib.hg_scratch_bytes(self.h))
 
-    def set_tuning(self, single_pass_load16: int = 8, pass_fill16: int = 5):
-        t = Tuning(single_pass_load16, pass_fill16)
+    def set_tuning(self, single_pass_load16: int = 8, pass_fill16: int = 5,
+                   dense_ratio: int = 8):
+        t = Tuning(single_pass_load16, pass_fill16, dense_ratio)
         self._check(self.lib.hg_set_tuning(self.h, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
         t = Tuning()
         self._check(self.lib.hg_get_tuning(self.h, ctypes.byref(t)))
-        return dict(single_pass_load16=t.single_pass_load16, pass_fill16=t.pass_fill16)
+        return dict(single_pass_load16=t.single_pass_load16, pass_fill16=t.pass_fill16,
+                    dense_ratio=t.dense_ratio)
 
     def score_census(self) -> tuple[list[int], list[int]]:
         """(vertices, neighbour visits) per score work list of the last level."""
-        buf = (_i64 * 16)()
+        n = SCORE_LISTS
+        buf = (_i64 * (2 * n))()
         self._check(self.lib.hg_score_census(self.h, buf))
-        return [int(buf[k]) for k in range(8)], [int(buf[8 + k]) for k in range(8)]
+        return [int(buf[k]) for k in range(n)], [int(buf[n + k]) for k in range(n)]
 
     def enable_timing(self, on: bool = True):
         self._check(self.lib.hg_enable_timing(self.h, 1 if on else 0))

@@ -2,8 +2,10 @@
 
 The score step (Eq. 12) scores a vertex in one pass over an on-chip table
 when its distinct-neighbour bound is at most ``single_pass_load16``/16 of
-the table, and in windows of neighbour ids otherwise (in passes over a table
-aimed at ``pass_fill16``/16 of it where the distinct-axon overlap can bind).
+the table, in dense windows when its visits cover at least one id in
+``dense_ratio`` of the level, and in windows of neighbour ids otherwise (in
+passes over a table aimed at ``pass_fill16``/16 of it where the
+distinct-axon overlap can bind).
 Results never depend on these settings; the best ones depend on the degree
 and hyperedge-size mix of the workload.
 ``autotune`` times one coarsening level of sample levels under each
@@ -19,6 +21,7 @@ import torch
 
 LOADS = (4, 8, 12)
 FILLS = (3, 5, 8)
+DENSE = (4, 8, 16)
 
 
 def time_levels(ctx, levels, limits, repeats: int = 1) -> float:
@@ -34,21 +37,22 @@ def time_levels(ctx, levels, limits, repeats: int = 1) -> float:
     return best
 
 
-def autotune(ctx, levels, limits, loads=LOADS, fills=FILLS, verbose=False) -> dict:
+def autotune(ctx, levels, limits, loads=LOADS, fills=FILLS, dense=DENSE,
+             verbose=False) -> dict:
     """Set and return the fastest tuning for ``levels`` (device levels with
     state) under ``limits`` (one per level)."""
     results = []
-    for load, fill in itertools.product(loads, fills):
-        ctx.set_tuning(load, fill)
+    for load, fill, dr in itertools.product(loads, fills, dense):
+        ctx.set_tuning(load, fill, dr)
         time_levels(ctx, levels, limits)  # warm-up (first launch, caches)
         t = time_levels(ctx, levels, limits, repeats=2)
-        results.append((t, load, fill))
+        results.append((t, load, fill, dr))
         if verbose:
-            print(f"[tune] load16={load} fill16={fill}: {1e3 * t:.2f} ms", file=sys.stderr,
-                  flush=True)
-    t, load, fill = min(results)
-    ctx.set_tuning(load, fill)
+            print(f"[tune] load16={load} fill16={fill} dense={dr}: {1e3 * t:.2f} ms",
+                  file=sys.stderr, flush=True)
+    t, load, fill, dr = min(results)
+    ctx.set_tuning(load, fill, dr)
     torch.cuda.synchronize()
-    return dict(single_pass_load16=load, pass_fill16=fill, seconds=t,
-                table=[dict(single_pass_load16=l, pass_fill16=f, seconds=s)
-                       for s, l, f in results])
+    return dict(single_pass_load16=load, pass_fill16=fill, dense_ratio=dr, seconds=t,
+                table=[dict(single_pass_load16=l, pass_fill16=f, dense_ratio=d, seconds=s)
+                       for s, l, f, d in results])

@@ -139,7 +139,8 @@ def check_contraction(fine, coarse, vmap):
     assert np.all(np.diff(coarse["eoff"]) >= 2)
 
 
-def score_buckets(level, limits, load16=8, small=4096, big=16384, big_ov=8192, win_deg=768):
+def score_buckets(level, limits, load16=8, small=4096, big=16384, big_ov=8192, win_deg=768,
+                  dense_ratio=8):
     """Work list of every vertex in the score step, by the rule the library
     applies before scoring (a host copy of that rule, used to show which
     scoring kernels an input reaches; results never depend on it).
@@ -149,7 +150,10 @@ def score_buckets(level, limits, load16=8, small=4096, big=16384, big_ov=8192, w
     small table, single pass in the big table, windows (at most ``win_deg``
     incident hyperedges), passes over a table; +4 when the distinct-axon
     bound can bind for the vertex (its ax plus the level's largest ax above
-    the limit), which makes the step also count shared inbound axons."""
+    the limit), which makes the step also count shared inbound axons; 8 or 9
+    (without or with that count) for large neighbourhoods that visit at least
+    one id in ``dense_ratio`` of the level (0: never), on levels of at most
+    2^21 vertices."""
     eoff = np.asarray(level.eoff, dtype=np.int64)
     lens = np.diff(eoff)
     ids = (np.asarray(level.pins) & MASK).astype(np.int64)
@@ -165,4 +169,8 @@ def score_buckets(level, limits, load16=8, small=4096, big=16384, big_ov=8192, w
                  np.where(dist <= np.where(ov, big_ov, big) * load16 // 16, 1,
                           np.where(deg <= win_deg, 2, 3)))
     b = b + 4 * ov
+    # dense windows: large neighbourhoods visiting at least one id in 8, on
+    # levels of at most 2^21 vertices
+    if dense_ratio > 0 and 0 < V <= (1 << 21):
+        b = np.where(((b & 3) >= 2) & (xn * dense_ratio >= V), 8 + ov, b)
     return np.where(xn > 0, b, -1)

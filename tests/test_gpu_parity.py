@@ -56,7 +56,8 @@ def run_hierarchy_parity(ctx, g, lim, max_levels=None, check_conn=True, verbose=
     if verbose:
         print(f"  {g.name}: V={g.n_vertices} P={g.n_pins}, oracle levels={len(oh.levels)}",
               flush=True)
-    load16 = ctx.get_tuning()["single_pass_load16"]
+    tun = ctx.get_tuning()
+    load16, dense_ratio = tun["single_pass_load16"], tun["dense_ratio"]
     L = ctx.upload(g)
     ctx.sync()
     assert_level_equal(L, oh.levels[0].level, "level 0 state")
@@ -67,8 +68,8 @@ def run_hierarchy_parity(ctx, g, lim, max_levels=None, check_conn=True, verbose=
         out = ctx.coarsen_level(L, lim)
         ctx.sync()
         nv, _visits = ctx.score_census()
-        b = hgcheck.score_buckets(r.level, lim, load16=load16)
-        expect = np.bincount(b[b >= 0], minlength=8)
+        b = hgcheck.score_buckets(r.level, lim, load16=load16, dense_ratio=dense_ratio)
+        expect = np.bincount(b[b >= 0], minlength=10)
         assert nv == expect.tolist(), f"score work lists {where}: {nv} vs {expect.tolist()}"
         if census is not None:
             census += expect
@@ -164,45 +165,76 @@ def test_conv_small_hierarchy(ctx):
     print(f"  conv small: {oh.n_levels} contractions to the stop rule", flush=True)
 
 
-def test_overlap_kernels_hub_levels(ctx):
+class _tuned:
+    """Score-step tuning for the duration of a block (restored after)."""
+
+    def __init__(self, ctx, **kw):
+        self.ctx, self.kw = ctx, kw
+
+    def __enter__(self):
+        self.old = self.ctx.get_tuning()
+        t = dict(self.old)
+        t.update(self.kw)
+        self.ctx.set_tuning(**t)
+
+    def __exit__(self, *exc):
+        self.ctx.set_tuning(**self.old)
+
+
+@pytest.mark.parametrize("dense_ratio", [0, 8], ids=["windows", "dense"])
+def test_overlap_kernels_hub_levels(ctx, dense_ratio):
     """Levels where the distinct-axon bound of Section 3 binds with thousands
     of distinct neighbours: 12,000 neurons, each axon reaching 100 random
     neurons, plus 8 hubs that about 900 axons reach; Delta = 1000, so every
-    vertex needs the shared inbound count in its scores, the typical vertex
-    is scored in passes over a table with that count (more than 4,096
-    distinct neighbours, fewer than 769 incident hyperedges) and the hubs
-    in passes with their incident hyperedges read from global memory.  Six
-    levels against the oracle, element by element."""
+    vertex needs the shared inbound count in its scores.  Without dense
+    windows the typical vertex is scored in windows with the overlap counted
+    (more than 4,096 distinct neighbours, fewer than 769 incident hyperedges)
+    and the hubs in passes with their incident hyperedges read from global
+    memory; with them (every neighbourhood here visits more than an eighth
+    of the ids) all are scored in dense windows with the overlap.  Six levels
+    against the oracle, element by element."""
     g = synth.hub_graph(1, 12000, 100, 8, 0.075)
-    census = np.zeros(8, np.int64)
-    run_hierarchy_parity(ctx, g, synth.Limits(512, 65536, 1000), max_levels=6, census=census,
-                         verbose=True)
+    census = np.zeros(10, np.int64)
+    with _tuned(ctx, dense_ratio=dense_ratio):
+        run_hierarchy_parity(ctx, g, synth.Limits(512, 65536, 1000), max_levels=6,
+                             census=census, verbose=True)
     print(f"  census {census.tolist()}", flush=True)
-    assert census[6] >= 20000 and census[7] >= 200
+    if dense_ratio:
+        assert census[9] >= 20000
+    else:
+        assert census[6] >= 20000 and census[7] >= 200
 
 
-def test_passes_without_overlap_hubs(ctx):
+@pytest.mark.parametrize("dense_ratio", [0, 8], ids=["windows", "dense"])
+def test_passes_without_overlap_hubs(ctx, dense_ratio):
     """Hubs with more than 768 incident hyperedges and no binding axon limit
     are scored in passes over a table with the hyperedges read from global
-    memory; six levels against the oracle."""
+    memory, or in dense windows; six levels against the oracle."""
     g = synth.hub_graph(2, 20000, 30, 16, 0.05)
-    census = np.zeros(8, np.int64)
-    run_hierarchy_parity(ctx, g, synth.Limits(512, 65536, 1 << 30), max_levels=6,
-                         census=census)
+    census = np.zeros(10, np.int64)
+    with _tuned(ctx, dense_ratio=dense_ratio):
+        run_hierarchy_parity(ctx, g, synth.Limits(512, 65536, 1 << 30), max_levels=6,
+                             census=census)
     print(f"  census {census.tolist()}", flush=True)
-    assert census[3] >= 16
+    assert census[8 if dense_ratio else 3] >= 16
 
 
-def test_batch_mix_graph_coarse_levels(ctx):
+@pytest.mark.parametrize("dense_ratio", [0, 8], ids=["windows", "dense"])
+def test_batch_mix_graph_coarse_levels(ctx, dense_ratio):
     """A recurrent graph of the batch mix (6,789 neurons, fan-out 16..256)
     under the batch limits: from its fifth level on, super-nodes whose
-    distinct-axon bound binds are scored with the shared inbound count in
-    both multipass kernels; twelve levels against the oracle."""
+    distinct-axon bound binds are scored with the shared inbound count (in
+    both multipass kernels, or in dense windows); twelve levels against the
+    oracle."""
     g = synth.batch_graph(1001, 0, 1000, 8000, 16, 256)
-    census = np.zeros(8, np.int64)
-    run_hierarchy_parity(ctx, g, synth.LIMITS["batch"], max_levels=12, census=census)
+    census = np.zeros(10, np.int64)
+    with _tuned(ctx, dense_ratio=dense_ratio):
+        run_hierarchy_parity(ctx, g, synth.LIMITS["batch"], max_levels=12, census=census)
     print(f"  census {census.tolist()}", flush=True)
-    assert census[5] > 0 and census[6] > 0 and census[7] > 0
+    if dense_ratio:
+        assert census[8] > 0 and census[9] > 0
+    else:
+        assert census[5] > 0 and census[6] > 0 and census[7] > 0
 
 
 def test_uniform_tight_axon_limit(ctx):
@@ -301,7 +333,7 @@ def test_tuning_never_changes_results(ctx):
     plus the median, so that about half of the vertices need the shared
     inbound count: under the settings below vertices move between the
     one-pass tables, the windows and the passes with the overlap table (the
-    only kernel that reads the fill target)."""
+    only kernel that reads the fill target) or the dense windows."""
     from paper_2609_07577_amd import hg
     g = synth.hub_graph(4, 20000, 60, 0, 0.0, skew=0.6)
     OL = oracle.level0(g)
@@ -310,25 +342,28 @@ def test_tuning_never_changes_results(ctx):
     L = ctx.upload(g)
     seen = {}
     try:
-        for load, fill in ((8, 5), (1, 1), (12, 10), (4, 3), (1, 10)):
-            ctx.set_tuning(load, fill)
+        for load, fill, dr in ((8, 5, 0), (1, 1, 0), (12, 10, 4), (4, 3, 16), (1, 10, 0),
+                               (8, 5, 8), (1, 1, 64)):
+            ctx.set_tuning(load, fill, dr)
             out = ctx.coarsen_level(L, lim)
             ctx.sync()
             nv, _ = ctx.score_census()
-            b = hgcheck.score_buckets(OL, lim, load16=load)
-            assert nv == np.bincount(b[b >= 0], minlength=8).tolist(), (load, nv)
-            seen[(load, fill)] = tuple(nv)
+            b = hgcheck.score_buckets(OL, lim, load16=load, dense_ratio=dr)
+            assert nv == np.bincount(b[b >= 0], minlength=10).tolist(), (load, dr, nv)
+            seen[(load, fill, dr)] = tuple(nv)
             for k, ref in (("cand", expect.cand), ("cscore", expect.cscore),
                            ("match", expect.match), ("vmap", expect.vmap)):
-                np.testing.assert_array_equal(_np(out[k]), ref, err_msg=f"{k} tuning {load}/{fill}")
-        for bad in ((0, 5), (13, 5), (8, 0), (8, 11)):
+                np.testing.assert_array_equal(_np(out[k]), ref,
+                                              err_msg=f"{k} tuning {load}/{fill}/{dr}")
+        for bad in ((0, 5, 8), (13, 5, 8), (8, 0, 8), (8, 11, 8), (8, 5, -1), (8, 5, 65)):
             with pytest.raises(hg.HgError):
                 ctx.set_tuning(*bad)
     finally:
-        ctx.set_tuning(8, 5)
+        ctx.set_tuning(8, 5, 8)
     print(f"  census per setting {seen}", flush=True)
-    assert len(set(seen.values())) >= 3, "the settings did not move vertices between lists"
-    assert seen[(1, 1)][2] > 1000 and seen[(1, 1)][6] > 1000  # windows and overlap passes
+    assert len(set(seen.values())) >= 4, "the settings did not move vertices between lists"
+    assert seen[(1, 1, 0)][2] > 1000 and seen[(1, 1, 0)][6] > 1000  # windows, overlap passes
+    assert seen[(1, 1, 64)][8] > 1000 and seen[(1, 1, 64)][9] > 1000  # dense windows
 
 
 def test_out_of_range_maps_are_rejected(ctx):
