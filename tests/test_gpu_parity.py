@@ -232,7 +232,7 @@ def test_batch_mix_graph_coarse_levels(ctx, dense_ratio):
         run_hierarchy_parity(ctx, g, synth.LIMITS["batch"], max_levels=12, census=census)
     print(f"  census {census.tolist()}", flush=True)
     if dense_ratio:
-        assert census[8] > 0 and census[9] > 0
+        assert census[5] > 0 and census[9] > 0
     else:
         assert census[5] > 0 and census[6] > 0 and census[7] > 0
 
