@@ -414,14 +414,22 @@ def test_out_of_range_maps_are_rejected(ctx):
         assert int(ctx.connectivity(L, good).item()) == expect_conn, f"after {what}"
 
 
-def _window_bucket_vertices(g, lim=synth.LIMITS["powerlaw"], load16=8):
+def _window_bucket_vertices(g, lim=synth.LIMITS["powerlaw"], load16=8, dense_ratio=0):
     """Vertices of level 0 that the score step gives to the window kernel
-    (host copy of the bucket rule)."""
-    b = hgcheck.score_buckets(oracle.level0(g), lim, load16=load16)
-    return np.flatnonzero(b == 2)
+    (dense_ratio 0) or to the dense-window kernels (host copy of the bucket
+    rule)."""
+    b = hgcheck.score_buckets(oracle.level0(g), lim, load16=load16, dense_ratio=dense_ratio)
+    return np.flatnonzero(b == 2) if dense_ratio == 0 else np.flatnonzero(b >= 8)
 
 
-def test_window_list_overflow_halves_the_window(ctx):
+# The large-neighbourhood cases run twice: scored in windows of the id range
+# (the dense route off) and in dense windows (every vertex that visits at
+# least one id in 64 of the level).
+ROUTES = pytest.mark.parametrize("dense_ratio", [0, 64], ids=["windows", "dense"])
+
+
+@ROUTES
+def test_window_list_overflow_halves_the_window(ctx, dense_ratio):
     """Every neighbour of the 9000 targets is shared by four hyperedges, so a
     window of the multipass score step holds three repeat visits per id and
     overflows its list of repeat visits until the window is narrowed to a
@@ -429,11 +437,13 @@ def test_window_list_overflow_halves_the_window(ctx):
     nt = 9000
     axons = [(nt + i, list(range(nt)), w) for i, w in enumerate((3, 5, 2, 7))]
     g = synth.from_axons(nt + 4, axons)
-    assert len(_window_bucket_vertices(g)) >= nt
-    run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
+    assert len(_window_bucket_vertices(g, dense_ratio=dense_ratio)) >= nt
+    with _tuned(ctx, dense_ratio=dense_ratio):
+        run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
 
 
-def test_window_slice_runs_past_its_estimate(ctx):
+@ROUTES
+def test_window_slice_runs_past_its_estimate(ctx, dense_ratio):
     """Three hyperedges whose pins are 4000 consecutive low ids plus one id
     near the top of a 600,000-vertex level: the id-density estimate of a
     window's slice falls far short, so the kernel must continue the slice
@@ -443,11 +453,13 @@ def test_window_slice_runs_past_its_estimate(ctx):
     axons = [(n - 10 + i, list(range(4000)), w) for i, w in enumerate((4, 9, 1))]
     axons.append((n - 1, sorted(set(range(0, n - 20, 997)) - {n - 1}), 2))
     g = synth.from_axons(n, axons)
-    assert len(_window_bucket_vertices(g)) >= 4000
-    run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
+    assert len(_window_bucket_vertices(g, dense_ratio=dense_ratio)) >= 4000
+    with _tuned(ctx, dense_ratio=dense_ratio):
+        run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
 
 
-def test_window_degree_limit(ctx):
+@ROUTES
+def test_window_degree_limit(ctx, dense_ratio):
     """Two large neighbourhoods on either side of the window kernel's limit
     on incident hyperedges: vertex 0 is a target of 768 axons (scored in
     windows), vertex 1 of 769 (scored by the global multipass kernel); each
@@ -462,13 +474,18 @@ def test_window_degree_limit(ctx):
             axons.append((src, [target] + sorted(int(x) for x in others), int(rng.integers(1, 100))))
             src += 1
     g = synth.from_axons(n, axons)
-    wb = set(_window_bucket_vertices(g).tolist())
-    assert 0 in wb and 1 not in wb
-    run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
+    wb = set(_window_bucket_vertices(g, dense_ratio=dense_ratio).tolist())
+    if dense_ratio:  # dense windows have no degree limit
+        assert 0 in wb and 1 in wb
+    else:
+        assert 0 in wb and 1 not in wb
+    with _tuned(ctx, dense_ratio=dense_ratio):
+        run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
 
 
+@ROUTES
 @pytest.mark.parametrize("weights", [(1,), (1, 2)], ids=["equal", "two-valued"])
-def test_window_random_neighbourhoods_few_weights(ctx, weights):
+def test_window_random_neighbourhoods_few_weights(ctx, weights, dense_ratio):
     """Large random neighbourhoods whose hyperedges share few weight values:
     1250 axons of 400 random targets over 20,000 neurons (about 25 axons
     reach each neuron, 16,000 of which are scored in windows), weights all 1
@@ -482,8 +499,9 @@ def test_window_random_neighbourhoods_few_weights(ctx, weights):
         t = t + (t >= src)  # any neuron but the source
         axons.append((src, sorted(int(x) for x in t), int(rng.choice(weights))))
     g = synth.from_axons(n, axons)
-    assert len(_window_bucket_vertices(g)) >= 15_000
-    run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=3, verbose=True)
+    assert len(_window_bucket_vertices(g, dense_ratio=dense_ratio)) >= 15_000
+    with _tuned(ctx, dense_ratio=dense_ratio):
+        run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=3, verbose=True)
 
 
 def _disjoint_neighbourhoods(seed, n, hubs, k, fan, heavy):
@@ -518,8 +536,9 @@ def _disjoint_neighbourhoods(seed, n, hubs, k, fan, heavy):
     return synth.from_axons(n, axons), hub_ids
 
 
+@ROUTES
 @pytest.mark.parametrize("heavy", [False, True], ids=["equal", "heavy-late"])
-def test_window_lowest_id_single(ctx, heavy):
+def test_window_lowest_id_single(ctx, heavy, dense_ratio):
     """Hubs scored in windows (600,000 ids, two windows) whose neighbours
     are all singles (disjoint target sets): the candidate is decided by the
     lowest id among the batches of the heaviest weight, spread over many
@@ -530,8 +549,8 @@ def test_window_lowest_id_single(ctx, heavy):
     on other waves).  The levels must be the oracle's."""
     g, hubs = _disjoint_neighbourhoods(5, 600_000, 8, 400, 50, heavy)
     L0 = oracle.level0(g)
-    b = hgcheck.score_buckets(L0, synth.LIMITS["powerlaw"])
-    assert np.all(b[hubs] == 2), "hubs must be scored in windows"
+    b = hgcheck.score_buckets(L0, synth.LIMITS["powerlaw"], dense_ratio=dense_ratio)
+    assert np.all(b[hubs] == (8 if dense_ratio else 2)), "hubs must be scored in windows"
     r0 = oracle.coarsen_level(L0, synth.LIMITS["powerlaw"])
     for h in hubs.tolist():
         # the hub's neighbours and the candidate the definition gives
@@ -544,4 +563,34 @@ def test_window_lowest_id_single(ctx, heavy):
         assert r0.cscore[h] == best_w
         if heavy:
             assert r0.cand[h] > min(v for v, _ in nb)
-    run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
+    with _tuned(ctx, dense_ratio=dense_ratio):
+        run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
+
+
+@pytest.mark.parametrize("delta", [1 << 30, 300], ids=["scores", "overlap"])
+def test_dense_window_rounds(ctx, delta):
+    """Neighbourhoods whose slices in one dense window come to more than the
+    1,024 chunks of 64 pins the dense kernel lists at once: 300 axons each
+    reach 600 of 1,000 neurons, and 10,000 unconnected neurons make the
+    level too large for the single-pass tables (all ids sit in the one
+    window of 2^14), so a target meets about 180 hyperedges of ten chunks
+    each and is scored in two rounds over the same table.  With Delta = 300
+    the distinct-axon bound binds for the targets and the shared inbound
+    count enters the merge test (list 9).  Two levels against the oracle."""
+    rng = np.random.default_rng(21)
+    nt, na = 1000, 300
+    axons = [(nt + i, sorted(rng.choice(nt, size=600, replace=False).tolist()),
+              int(rng.integers(1, 50))) for i in range(na)]
+    g = synth.from_axons(nt + na + 10_000, axons)
+    L0 = oracle.level0(g)
+    lim = synth.Limits(512, 65536, delta)
+    b = hgcheck.score_buckets(L0, lim, dense_ratio=8)
+    chunks = np.zeros(L0.V, np.int64)
+    for e in range(L0.E):
+        ids = L0.pins[L0.eoff[e]:L0.eoff[e + 1]] & 0x7FFFFFFF
+        chunks[ids] += (len(ids) + 63) // 64
+    targets = np.arange(nt)
+    assert np.all(b[targets] == (9 if delta < (1 << 30) else 8))
+    assert chunks[targets].min() > 1024, "every target must need a second round"
+    with _tuned(ctx, dense_ratio=8):
+        run_hierarchy_parity(ctx, g, lim, max_levels=2, verbose=True)
