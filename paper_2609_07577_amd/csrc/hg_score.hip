@@ -1797,44 +1797,34 @@ __global__ void dense_splits_kernel(const Dims* __restrict__ d, const int64_t* _
   }
 }
 
-// Dense windows (neighbourhoods that visit at least one id in dense_ratio
+// Dense windows (neighbourhoods that visit at least one id in kDenseRatio
 // of the level): per window of 2^kDenseBits ids, a packed 64-bit LDS entry
 // per id holds (score << 32 | overlap), and one sweep over the window's
-// slices adds (weight << 32 | overlap share) per visit with one returning
-// 64-bit LDS atomic.  The entry returned plus the visit's share is the id's
-// (score, overlap) so far; every id's last visit sees its totals, and scores
-// and overlaps only grow, so the best valid neighbour is the largest
-// (score, -id) seen at any visit of a valid id, whatever the order of the
-// visits: validity is tested only for keys above the best valid key found
-// so far (kept per lane and for the block in LDS), with the overlap seen by
-// that visit (the test only gets easier as the overlap grows).  OV: the
-// overlap share of a visit is the hyperedge's multiplicity when n and the
-// visited id both carry its flag.
-//
-// The window's slices are cut into chunks of up to 64 pins, listed in LDS
-// (x first pin, y pin count, z weight, w overlap share); waves claim
-// batches of B chunks.  A thread keeps its first incident hyperedge (and
-// the slice bounds of the next windows, loaded ahead) in registers; the
-// chunk list of window w + 1 is built before the sweep of window w, so that
-// each wave loads the pins of its first batch of w + 1 before the barrier
-// and the table clear that separate the two sweeps.  A window of more than
-// kMaxChunks chunks is listed and swept in rounds instead.
+// slices (chunk lists from `splits14`, in rounds of kMaxChunks) adds
+// (weight << 32 | overlap share) per visit with one returning 64-bit LDS
+// atomic.  The entry returned plus the visit's share is the id's (score,
+// overlap) so far; every id's last visit sees its totals, and scores and
+// overlaps only grow, so the best valid neighbour is the largest (score,
+// -id) a lane sees among valid ids: validity is tested only for keys above
+// the lane's best, with the overlap seen by that visit (the test only gets
+// easier as the overlap grows).  OV: the overlap share of a visit is the
+// hyperedge's multiplicity when n and the visited id both carry its flag.
 template <int THREADS, bool OV>
 __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int bucket,
                                                              int64_t maxV) {
   constexpr int NW = THREADS / kWave;
   constexpr int B = 4;
   constexpr int kIds = 1 << kDenseBits;
-  constexpr int kMaxChunks = 768;
+  constexpr int kMaxChunks = 1024;
   constexpr uint32_t kSent = 0x7FFFFFFFu;
   static_assert(kIds * 8 == THREADS * 128, "a thread clears 128 bytes of the table");
   struct Lds {
     uint64_t tab[kIds];
-    uint4 desc[2][kMaxChunks + B];
+    uint4 desc[kMaxChunks + B];  // x first pin, y pin count, z weight, w overlap share
     int32_t ws[3 * NW];
-    uint64_t bbest;
+    uint64_t red[2 * NW];
     int32_t s_item;
-    int32_t s_next[2];
+    int32_t s_next;
   };
   __shared__ Lds S;
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
@@ -1853,24 +1843,10 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
                          ? (int32_t)((Vl + kIds - 1) >> kDenseBits) : W;
   uint4* const tab4 = reinterpret_cast<uint4*>(S.tab);
   const uint32_t lofs = (uint32_t)lane * 4u;
-  auto clear_table = [&]() {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) tab4[8 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
-  };
-  clear_table();  // made visible by the barriers of the first vertex
-
-  struct Batch {
-    uint32_t x[B];
-    int32_t cnt[B];
-    uint32_t wt[B], mu[B];
-  };
 
   while (true) {
     __syncthreads();
-    if (tid == 0) {
-      S.s_item = atomicAdd(&a.work[bucket], 1);
-      S.bbest = 0;
-    }
+    if (tid == 0) S.s_item = atomicAdd(&a.work[bucket], 1);
     __syncthreads();
     const int32_t item = S.s_item;
     if (item >= count) break;
@@ -1888,199 +1864,130 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
     const uint32_t n = (uint32_t)v.n;
     const int64_t deg = v.deg;
     uint64_t best = 0;
-
-    // the thread's first incident hyperedge (j = tid) in registers: its
-    // first pin, weight, overlap share and slice bounds of windows wi
-    // (o_lo, o_hi) and wi + 1 (o_hi, o_pf)
-    const bool own = tid < deg;
-    const uint32_t* o_sr = a.splits14;
-    uint32_t o_first = 0, o_wt = 0, o_mu = 0, o_lo = 0, o_hi = 0, o_pf = 0;
-    if (own) {
-      const uint32_t ent = a.vinc[v.beg + tid];
-      const uint32_t e = ent & kIdMask;
-      o_sr = a.splits14 + (int64_t)e * (W + 1);
-      o_first = (uint32_t)a.L.eoff[e];
-      o_wt = (uint32_t)a.L.w[e];
-      o_mu = (OV && (ent & kDst)) ? (uint32_t)a.L.mult[e] : 0u;
-      o_lo = o_sr[0];
-      o_hi = o_sr[1];
-      if (Wl > 1) o_pf = o_sr[2];
-    }
-    // chunks of window wi owned by this thread (own slice [lo, hi), then
-    // the hyperedges j = tid + THREADS, tid + 2 THREADS, ... from memory)
-    auto count_chunks = [&](int32_t wi, uint32_t lo, uint32_t hi) -> int32_t {
-      int32_t m = (int32_t)((hi - lo + kWave - 1) / kWave);
-      for (int64_t j = tid + THREADS; j < deg; j += THREADS) {
+    for (int32_t wi = 0; wi < Wl; ++wi) {  // block-uniform
+      const uint32_t lo = (uint32_t)wi << kDenseBits;
+      // chunks of this window: thread t owns incident hyperedges t, t + THREADS, ...
+      int32_t mine = 0;
+      for (int64_t j = tid; j < deg; j += THREADS) {
         const uint32_t e = a.vinc[v.beg + j] & kIdMask;
         const uint32_t* sr = a.splits14 + (int64_t)e * (W + 1);
-        m += (int32_t)((sr[wi + 1] - sr[wi] + kWave - 1) / kWave);
+        mine += (int32_t)((sr[wi + 1] - sr[wi] + kWave - 1) / kWave);
       }
-      return m;
-    };
-    // list the chunks c0 .. of window wi that fall in [r0, r0 + Tr)
-    auto list_chunks = [&](uint4* desc, int32_t wi, uint32_t lo, uint32_t hi, int32_t c0,
-                           int32_t r0, int32_t Tr) {
-      int32_t c = c0;
-      auto put = [&](uint32_t first, uint32_t len, uint32_t wt, uint32_t mu) {
-        const int32_t nch = (int32_t)((len + kWave - 1) / kWave);
-        if (c + nch > r0 && c < r0 + Tr) {
-          for (int32_t q = 0; q < nch; ++q) {
-            const int32_t at = c + q - r0;
-            if (at < 0 || at >= Tr) continue;
-            const uint32_t left = len - (uint32_t)q * kWave;
-            desc[at] = make_uint4(first + (uint32_t)q * kWave,
-                                  left < (uint32_t)kWave ? left : (uint32_t)kWave, wt, mu);
-          }
-        }
-        c += nch;
-      };
-      if (own) put(o_first + lo, hi - lo, o_wt, o_mu);
-      for (int64_t j = tid + THREADS; j < deg; j += THREADS) {
-        const uint32_t ent = a.vinc[v.beg + j];
-        const uint32_t e = ent & kIdMask;
-        const uint32_t* sr = a.splits14 + (int64_t)e * (W + 1);
-        put((uint32_t)a.L.eoff[e] + sr[wi], sr[wi + 1] - sr[wi], (uint32_t)a.L.w[e],
-            (OV && (ent & kDst)) ? (uint32_t)a.L.mult[e] : 0u);
-      }
-    };
-    // the scan of window wi's chunk counts; the list is written here when
-    // it fits (else by the rounds of the sweep)
-    struct Win {
-      int32_t T, p;
-      uint32_t lo, hi;
-    };
-    auto prepare = [&](int32_t wi, uint32_t lo, uint32_t hi, uint4* desc, int32_t slot) -> Win {
-      Win w{0, 0, lo, hi};
-      int32_t x3[3] = {count_chunks(wi, lo, hi), 0, 0}, p3[3], t3[3];
+      int32_t x3[3] = {mine, 0, 0}, p3[3], t3[3];
       block_scan3<THREADS>(x3, p3, t3, S.ws);
-      w.T = t3[0];
-      w.p = p3[0];
-      if (w.T > 0 && w.T <= kMaxChunks) {
-        list_chunks(desc, wi, lo, hi, w.p, 0, w.T);
-        if (tid < B) desc[w.T + tid] = make_uint4(0u, 0u, 0u, 0u);
-        if (tid == 0) S.s_next[slot] = NW;
-      }
-      return w;
-    };
-
-    int32_t bclaim = wid;
-    auto fetch = [&](const uint4* desc, int32_t* next, int32_t tb, Batch& t, uint32_t (&pin)[B],
-                     int32_t bno) {
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        uint4 d = make_uint4(0u, 0u, 0u, 0u);
-        if (bno < tb) d = desc[bno * B + u];
-        t.x[u] = rfl_u32(d.x);
-        t.cnt[u] = (int32_t)rfl_u32(d.y);
-        t.wt[u] = rfl_u32(d.z);
-        t.mu[u] = rfl_u32(d.w);
+      const int32_t T = t3[0];
+      if (T == 0) {  // block-uniform; the scan's words are read before the next scan
+        __syncthreads();
+        continue;
       }
 #pragma unroll
-      for (int u = 0; u < B; ++u) {
-        const uint32_t last4 = t.cnt[u] > 0 ? (uint32_t)(t.cnt[u] - 1) * 4u : 0u;
-        const char* p = reinterpret_cast<const char*>(a.L.pins + t.x[u]);
-        const uint32_t off = lofs < last4 ? lofs : last4;
-        pin[u] = *reinterpret_cast<const uint32_t*>(p + off);
-      }
-      if (bno < tb) {  // wave-uniform: claim the next batch
-        int32_t cc = 0;
-        if (lane == 0) cc = atomicAdd(next, 1);
-        bclaim = cc;
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    };
-    auto process = [&](const Batch& t, const uint32_t (&pin)[B]) {
-      const uint64_t thr0 = S.bbest;
-      uint64_t thr = best > thr0 ? best : thr0;
+      for (int i = 0; i < 8; ++i) tab4[8 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
+      for (int32_t r0 = 0; r0 < T; r0 += kMaxChunks) {  // block-uniform
+        const int32_t Tr = T - r0 < kMaxChunks ? T - r0 : kMaxChunks;
+        __syncthreads();  // table clear, previous round's chunks done
+        int32_t c = p3[0];  // this thread's first chunk in the window's list
+        for (int64_t j = tid; j < deg; j += THREADS) {
+          const uint32_t ent = a.vinc[v.beg + j];
+          const uint32_t e = ent & kIdMask;
+          const uint32_t* sr = a.splits14 + (int64_t)e * (W + 1);
+          const uint32_t first = (uint32_t)a.L.eoff[e] + sr[wi];
+          const uint32_t len = sr[wi + 1] - sr[wi];
+          const int32_t nch = (int32_t)((len + kWave - 1) / kWave);
+          if (c + nch > r0 && c < r0 + Tr) {
+            const uint32_t wt = (uint32_t)a.L.w[e];
+            const uint32_t mu = (OV && (ent & kDst)) ? (uint32_t)a.L.mult[e] : 0u;
+            for (int32_t q = 0; q < nch; ++q) {
+              const int32_t at = c + q - r0;
+              if (at < 0 || at >= Tr) continue;
+              const uint32_t left = len - (uint32_t)q * kWave;
+              S.desc[at] = make_uint4(first + (uint32_t)q * kWave,
+                                      left < (uint32_t)kWave ? left : (uint32_t)kWave, wt, mu);
+            }
+          }
+          c += nch;
+        }
+        if (tid < B) S.desc[Tr + tid] = make_uint4(0u, 0u, 0u, 0u);
+        if (tid == 0) S.s_next = NW;
+        __syncthreads();
+        const int32_t tb = (Tr + B - 1) / B;
+        // ---- the sweep
+        struct Batch {
+          uint32_t x[B];
+          int32_t cnt[B];
+          uint32_t wt[B], mu[B];
+        };
+        int32_t bclaim = wid;
+        auto fetch = [&](Batch& t, uint32_t (&pin)[B], int32_t bno) {
 #pragma unroll
-      for (int u = 0; u < B; ++u) {
-        const uint32_t id = pin[u] & kIdMask;
-        const bool act = lofs < (uint32_t)t.cnt[u] * 4u && id != n;
-        if (act) {  // no cross-lane operation inside
-          const uint32_t lo = id & (uint32_t)(kIds - 1);
-          const uint64_t add = ((uint64_t)t.wt[u] << 32) |
-                               (uint64_t)((OV && (pin[u] & kDst)) ? t.mu[u] : 0u);
-          const uint64_t now =
-              atomicAdd((unsigned long long*)&S.tab[lo], (unsigned long long)add) + add;
-          const uint64_t key = (now & 0xFFFFFFFF00000000ull) | (uint64_t)(kSent - id);
-          if (key > thr &&
-              (v.all_valid || merge_valid(a, v, id, OV ? (int64_t)(now & 0xFFFFFFFFull) : 0))) {
-            best = key;
-            thr = key;
-            atomicMax((unsigned long long*)&S.bbest, (unsigned long long)key);
+          for (int u = 0; u < B; ++u) {
+            uint4 d = make_uint4(0u, 0u, 0u, 0u);
+            if (bno < tb) d = S.desc[bno * B + u];
+            t.x[u] = rfl_u32(d.x);
+            t.cnt[u] = (int32_t)rfl_u32(d.y);
+            t.wt[u] = rfl_u32(d.z);
+            t.mu[u] = rfl_u32(d.w);
+          }
+#pragma unroll
+          for (int u = 0; u < B; ++u) {
+            const uint32_t last4 = t.cnt[u] > 0 ? (uint32_t)(t.cnt[u] - 1) * 4u : 0u;
+            const char* p = reinterpret_cast<const char*>(a.L.pins + t.x[u]);
+            const uint32_t off = lofs < last4 ? lofs : last4;
+            pin[u] = *reinterpret_cast<const uint32_t*>(p + off);
+          }
+          if (bno < tb) {  // wave-uniform: claim the next batch
+            int32_t cc = 0;
+            if (lane == 0) cc = atomicAdd(&S.s_next, 1);
+            bclaim = cc;
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        };
+        auto process = [&](const Batch& t, const uint32_t (&pin)[B]) {
+#pragma unroll
+          for (int u = 0; u < B; ++u) {
+            const uint32_t id = pin[u] & kIdMask;
+            const bool act = lofs < (uint32_t)t.cnt[u] * 4u && id != n;
+            if (act) {  // no cross-lane operation inside
+              const uint64_t add = ((uint64_t)t.wt[u] << 32) |
+                                   (uint64_t)((OV && (pin[u] & kDst)) ? t.mu[u] : 0u);
+              const uint64_t now =
+                  atomicAdd((unsigned long long*)&S.tab[id - lo], (unsigned long long)add) +
+                  add;
+              const uint64_t key = (now & 0xFFFFFFFF00000000ull) | (uint64_t)(kSent - id);
+              if (key > best &&
+                  (v.all_valid || merge_valid(a, v, id, OV ? (int64_t)(now & 0xFFFFFFFFull) : 0)))
+                best = key;
+            }
+          }
+          asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
+        };
+        {
+          Batch ta, tb2;
+          uint32_t pa[B], pb[B];
+          int32_t cur_b = wid;
+          fetch(ta, pa, cur_b);
+          while (cur_b < tb) {
+            const int32_t nb = __builtin_amdgcn_readlane(bclaim, 0);
+            fetch(tb2, pb, nb);
+            process(ta, pa);
+            cur_b = nb;
+            if (cur_b >= tb) break;
+            const int32_t nb2 = __builtin_amdgcn_readlane(bclaim, 0);
+            fetch(ta, pa, nb2);
+            process(tb2, pb);
+            cur_b = nb2;
           }
         }
       }
-      asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
-    };
-    // sweep the batches of one list; `ta`/`pa` hold the wave's first batch
-    Batch ta, tb2;
-    uint32_t pa[B], pb[B];
-    auto sweep = [&](const uint4* desc, int32_t* next, int32_t tb) {
-      int32_t cur_b = wid;
-      while (cur_b < tb) {
-        const int32_t nb = __builtin_amdgcn_readlane(bclaim, 0);
-        fetch(desc, next, tb, tb2, pb, nb);
-        process(ta, pa);
-        cur_b = nb;
-        if (cur_b >= tb) break;
-        const int32_t nb2 = __builtin_amdgcn_readlane(bclaim, 0);
-        fetch(desc, next, tb, ta, pa, nb2);
-        process(tb2, pb);
-        cur_b = nb2;
-      }
-    };
-
-    Win cur = prepare(0, o_lo, o_hi, S.desc[0], 0);
-    __syncthreads();  // list 0 written
-    if (cur.T <= kMaxChunks) {
-      bclaim = wid;
-      fetch(S.desc[0], &S.s_next[0], (cur.T + B - 1) / B, ta, pa, wid);
+      __syncthreads();  // the window's sweep done before the table is cleared again
     }
-    for (int32_t wi = 0; wi < Wl; ++wi) {  // block-uniform
-      const int32_t slot = wi & 1;
-      // slice bounds of window wi + 1 and the load of those of wi + 2
-      const uint32_t n_lo = o_hi, n_hi = o_pf;
-      o_hi = o_pf;
-      if (own && wi + 2 < Wl) o_pf = o_sr[wi + 3];
-      Win nxt{0, 0, n_lo, n_hi};
-      if (wi + 1 < Wl) nxt = prepare(wi + 1, n_lo, n_hi, S.desc[slot ^ 1], slot ^ 1);
-      __syncthreads();  // list wi + 1 written; the table clear before it seen
-      if (cur.T > kMaxChunks) {
-        // rounds: list and sweep kMaxChunks chunks at a time in this slot
-        for (int32_t r0 = 0; r0 < cur.T; r0 += kMaxChunks) {  // block-uniform
-          const int32_t Tr = cur.T - r0 < kMaxChunks ? cur.T - r0 : kMaxChunks;
-          if (r0 > 0) __syncthreads();  // the previous round's sweep done
-          list_chunks(S.desc[slot], wi, cur.lo, cur.hi, cur.p, r0, Tr);
-          if (tid < B) S.desc[slot][Tr + tid] = make_uint4(0u, 0u, 0u, 0u);
-          if (tid == 0) S.s_next[slot] = NW;
-          __syncthreads();
-          const int32_t tb = (Tr + B - 1) / B;
-          bclaim = wid;
-          fetch(S.desc[slot], &S.s_next[slot], tb, ta, pa, wid);
-          sweep(S.desc[slot], &S.s_next[slot], tb);
-        }
-      } else if (cur.T > 0) {
-        sweep(S.desc[slot], &S.s_next[slot], (cur.T + B - 1) / B);
-      }
-      // the first batch of window wi + 1, loaded before the barrier
-      if (wi + 1 < Wl && nxt.T <= kMaxChunks) {
-        bclaim = wid;
-        fetch(S.desc[slot ^ 1], &S.s_next[slot ^ 1], (nxt.T + B - 1) / B, ta, pa, wid);
-      }
-      __syncthreads();  // the sweep of wi done
-      if (cur.T > 0) clear_table();
-      cur = nxt;
-    }
-    __syncthreads();  // every lane's best in bbest
+    best = block_max_u64<THREADS>(best, S.red);
     if (tid == 0) {
-      const uint64_t b = S.bbest;
-      if (b == 0) {
+      if (best == 0) {
         a.cand[v.n] = -1;
         a.cscore[v.n] = 0;
       } else {
-        a.cand[v.n] = (int32_t)(kSent - (uint32_t)(b & 0xFFFFFFFFull));
-        a.cscore[v.n] = (int32_t)(b >> 32);
+        a.cand[v.n] = (int32_t)(kSent - (uint32_t)(best & 0xFFFFFFFFull));
+        a.cscore[v.n] = (int32_t)(best >> 32);
       }
     }
   }
