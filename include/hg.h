@@ -367,12 +367,70 @@ int hg_batch_sizes(hg_batch* batch, int64_t* sizes);
  * pass in the big table, 2 windows with a bitmap of seen ids, 3 passes over a
  * table; 4-7 the same where the distinct-axon overlap of Section 3 can bind;
  * 8 and 9 (without and with the overlap) dense windows, taken by the large
- * neighbourhoods of lists 2, 3, 6, 7 that visit at least one id in 8 of the
- * level, on levels of at most 2^21 vertices.  `out` is host
+ * neighbourhoods of lists 2, 3, 6, 7 that visit at least one id in
+ * dense_ratio (hg_tuning, default 8) of the level, on levels of at most 2^21
+ * vertices.  `out` is host
  * int64[2 * HG_SCORE_LISTS].
  */
 #define HG_SCORE_LISTS 10
 int hg_score_census(hg_ctx* ctx, int64_t* out);
+
+/*
+ * Placement of a partitioned hypergraph G_P on the cores of a lattice
+ * (Section 4.2).  `gp` is the level whose vertices are the parts (nodes):
+ * hg_contract of the level-0 hypergraph with the partition as its vertex
+ * map gives it; only edge_offsets, pins (flags ignored) and edge_weight (the
+ * spike rates eta) are read.  The lattice has width x height cores, 1 <=
+ * width, height <= 64; core c sits at (x, y) = (c / height, c % height) and
+ * distances are Manhattan (Section 2).  1 <= V <= width * height.
+ *
+ * Every call runs n_starts >= 1 placements together (the multi-start of
+ * Section 4.2); per-start device arrays are start-major: core_of[s * V + p]
+ * is the core of node p in start s.  All pointers are device memory owned
+ * by the caller; the calls are asynchronous; an order that is not a
+ * permutation, or a placement with a core outside the lattice or held by two
+ * nodes, is reported by the next hg_sync (HG_ERR_INVALID_ARG) and leaves the
+ * outputs undefined.
+ *
+ * hg_place_initial ("Initial Placement"): start s lays the nodes in the
+ * order orders[s * V .. s * V + V) (a permutation of 0..V-1, the random
+ * initial order), bisects the sequence recursively (a section of len nodes
+ * into its first ceil(len/2) and last floor(len/2) positions) with up to
+ * lp_rounds label-propagation rounds per section (gains of crossing to the
+ * other half over the hyperedges cut inside the section, both halves sorted
+ * by gain descending then node id, i-th pairs swapped while their gains sum
+ * above 0, a section stopping after a round without swaps), folds the tree
+ * (a non-root section flips, reversing its order, when its child facing
+ * away from its sibling is the more connected one to that sibling; ties
+ * keep the order) and places the i-th node of the result on the i-th core
+ * of the lattice's Hilbert order (the curve of the smallest power-of-two
+ * square holding the lattice, cores outside skipped).  Writes core_of.
+ *
+ * hg_place_refine ("Swap Proposals", "Placement Refinement"): rounds of
+ * forces (Eq. 14) and tensions (Eq. 15) towards the four neighbour cores;
+ * every occupied core proposes the neighbour of largest positive tension
+ * (lowest core id on ties); proposals are matched by the rule of Eq. 13
+ * over cores; the matched swaps are ordered by tension descending, then
+ * lower core id; their tensions are recomputed as if the swaps before them
+ * were applied, and the prefix of largest positive cumulative tension (the
+ * shortest on ties) is applied.  A start stops after a round that applies
+ * nothing, all after max_rounds.  core_of is updated in place (synchronous:
+ * the host reads one counter per round); info (device int64[3 * n_starts])
+ * = per start [rounds run, swaps applied, decrease of the residual distance].
+ *
+ * hg_place_residual: dist[s] (device int64[n_starts]) = sum over hyperedges
+ * of eta times the Manhattan distances of all unordered pairs of their pins'
+ * cores, the quantity each applied swap decreases by its recomputed tension;
+ * best (device int32[1], may be NULL) = the start of least dist, lowest
+ * index on ties (the multi-start choice of Section 4.2).
+ */
+int hg_place_initial(hg_ctx* ctx, const hg_level* gp, int32_t width, int32_t height,
+                     int32_t n_starts, const int32_t* orders, int32_t lp_rounds,
+                     int32_t* core_of);
+int hg_place_refine(hg_ctx* ctx, const hg_level* gp, int32_t width, int32_t height,
+                    int32_t n_starts, int32_t* core_of, int32_t max_rounds, int64_t* info);
+int hg_place_residual(hg_ctx* ctx, const hg_level* gp, int32_t width, int32_t height,
+                      int32_t n_starts, const int32_t* core_of, int64_t* dist, int32_t* best);
 
 /*
  * Synchronous structural check of a level: offsets non-decreasing and within

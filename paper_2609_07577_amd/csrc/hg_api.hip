@@ -205,6 +205,12 @@ int hg_sync(hg_ctx* c) {
                   "a vmap or part value, or n_coarse, was outside its range; the outputs of "
                   "that call are undefined (flags 0x%x)",
                   flags);
+    if (flags & kErrPlacement)
+      return fail(c, HG_ERR_INVALID_ARG,
+                  "a starting order that is not a permutation of the nodes, or a placement "
+                  "that is not one node per core of the lattice; the outputs of that call are "
+                  "undefined (flags 0x%x)",
+                  flags);
     if (flags & kErrWeight)
       return fail(c, HG_ERR_INVALID_LEVEL,
                   "a hyperedge weight below 1; the outputs of that call are undefined "

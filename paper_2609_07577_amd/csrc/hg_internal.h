@@ -25,6 +25,7 @@ enum : int32_t {
   kErrMapRange = 64,    // a caller's vmap / part value (or n_coarse) out of range
   kErrWeight = 128,     // a hyperedge weight below 1
   kErrWeightSum = 256,  // the weights of a level sum to 2^31 or more
+  kErrPlacement = 512,  // a starting order or a placement that is not one node per core
 };
 
 // Level sizes kept in device memory so that a chain of kernels can run

@@ -35,6 +35,7 @@ EXPORTED = ("hg_create", "hg_destroy", "hg_set_stream", "hg_last_error", "hg_syn
             "hg_coarsen_level", "hg_contract", "hg_connectivity", "hg_validate_level",
             "hg_set_tuning", "hg_get_tuning", "hg_score_census", "hg_connectivity_static",
             "hg_project", "hg_partition_report", "hg_refine",
+            "hg_place_initial", "hg_place_refine", "hg_place_residual",
             "hg_batch_create", "hg_batch_destroy", "hg_batch_bytes", "hg_batch_add_graph",
             "hg_batch_step", "hg_batch_done", "hg_batch_result", "hg_batch_compact",
             "hg_batch_sizes")
@@ -98,6 +99,10 @@ def load_library(path: str = LIB_PATH):
     lib.hg_project.argtypes = [_P, _i32, _P, _P, _P, _P]
     lib.hg_refine.argtypes = [_P, ctypes.POINTER(_Level), _P, _i32, ctypes.POINTER(Limits),
                               _i32, ctypes.POINTER(_i64)]
+    lib.hg_place_initial.argtypes = [_P, ctypes.POINTER(_Level), _i32, _i32, _i32, _P, _i32,
+                                     _P]
+    lib.hg_place_refine.argtypes = [_P, ctypes.POINTER(_Level), _i32, _i32, _i32, _P, _i32, _P]
+    lib.hg_place_residual.argtypes = [_P, ctypes.POINTER(_Level), _i32, _i32, _i32, _P, _P, _P]
     lib.hg_partition_report.argtypes = [_P, ctypes.POINTER(_Level), _P, _P,
                                         ctypes.POINTER(Limits), _P, _P, _P, _P]
     lib.hg_validate_level.argtypes = [_P, ctypes.POINTER(_Level)]
@@ -367,6 +372,60 @@ class Context:
             self._check(self.lib.hg_refine(self.h, ctypes.byref(lv), _ptr(part), int(n_parts),
                                            ctypes.byref(lim), int(max_rounds), info))
         return [int(info[i]) for i in range(4)]
+
+    def place_initial(self, gp: DeviceLevel, width: int, height: int, orders: torch.Tensor,
+                      lp_rounds: int = 4) -> torch.Tensor:
+        """Initial placements of G_P (hg_place_initial), one per row of the
+        device int32 ``orders`` [starts, V]; returns core_of [starts, V]."""
+        assert orders.dtype == torch.int32 and orders.is_contiguous() and orders.dim() == 2
+        S = int(orders.shape[0])
+        lv = gp.c_struct()
+        with torch.cuda.stream(self.stream):
+            core = torch.empty((S, max(gp.V, 1)), dtype=torch.int32, device=self.device)
+            self._check(self.lib.hg_place_initial(self.h, ctypes.byref(lv), int(width),
+                                                  int(height), S, _ptr(orders), int(lp_rounds),
+                                                  _ptr(core)))
+        return core
+
+    def place_refine(self, gp: DeviceLevel, width: int, height: int, core_of: torch.Tensor,
+                     max_rounds: int = 1000) -> torch.Tensor:
+        """Swap refinement of every start (hg_place_refine); ``core_of``
+        [starts, V] is updated in place.  Returns the device int64 info
+        [starts, 3]: rounds, swaps applied, decrease of the residual."""
+        assert core_of.dtype == torch.int32 and core_of.is_contiguous() and core_of.dim() == 2
+        S = int(core_of.shape[0])
+        lv = gp.c_struct()
+        with torch.cuda.stream(self.stream):
+            info = torch.zeros((S, 3), dtype=torch.int64, device=self.device)
+            self._check(self.lib.hg_place_refine(self.h, ctypes.byref(lv), int(width),
+                                                 int(height), S, _ptr(core_of), int(max_rounds),
+                                                 _ptr(info)))
+        return info
+
+    def place_residual(self, gp: DeviceLevel, width: int, height: int,
+                       core_of: torch.Tensor):
+        """Residual distance of every start and the best start
+        (hg_place_residual): (device int64 [starts], device int32 [1])."""
+        assert core_of.dtype == torch.int32 and core_of.is_contiguous() and core_of.dim() == 2
+        S = int(core_of.shape[0])
+        lv = gp.c_struct()
+        with torch.cuda.stream(self.stream):
+            dist = torch.empty(S, dtype=torch.int64, device=self.device)
+            best = torch.empty(1, dtype=torch.int32, device=self.device)
+            self._check(self.lib.hg_place_residual(self.h, ctypes.byref(lv), int(width),
+                                                   int(height), S, _ptr(core_of), _ptr(dist),
+                                                   _ptr(best)))
+        return dist, best
+
+    def place(self, gp: DeviceLevel, width: int, height: int, orders: torch.Tensor,
+              lp_rounds: int = 4, max_rounds: int = 1000):
+        """Multi-start placement (Section 4.2): initial placements, swap
+        refinement, residual distances and the best start.  Returns
+        (core_of [starts, V], info [starts, 3], dist [starts], best [1])."""
+        core = self.place_initial(gp, width, height, orders, lp_rounds)
+        info = self.place_refine(gp, width, height, core, max_rounds)
+        dist, best = self.place_residual(gp, width, height, core)
+        return core, info, dist, best
 
     def validate(self, L: DeviceLevel):
         lv = L.c_struct()

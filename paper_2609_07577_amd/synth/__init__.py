@@ -258,3 +258,37 @@ def start_orders(seed: int, n_nodes: int, n_starts: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.stack([rng.permutation(n_nodes) for _ in range(n_starts)]).astype(np.int32) \
         if n_starts > 0 else np.zeros((0, n_nodes), np.int32)
+
+
+def gp_graph(seed: int, n_nodes: int, n_edges: int, fan_min: int = 2, fan_max: int = 24,
+             w_max: int = 100, local: float = 0.7, span: int = 32) -> Level0:
+    """A partitioned hypergraph G_P for placement: n_nodes parts, n_edges
+    hyperedges, each from a uniform source part to fan targets (fan uniform
+    in [fan_min, fan_max], capped at n_nodes - 1), a target within ``span``
+    ids of the source with probability ``local`` (the id locality of parts
+    cut from layered networks) and uniform otherwise; distinct pins;
+    weights (spike rates) uniform in [1, w_max]."""
+    rng = np.random.default_rng(seed)
+    eoff = [0]
+    pins: list[np.ndarray] = []
+    w = rng.integers(1, w_max + 1, size=n_edges).astype(np.int32)
+    for _ in range(n_edges):
+        src = int(rng.integers(0, n_nodes))
+        fan = int(rng.integers(fan_min, fan_max + 1))
+        fan = max(0, min(fan, n_nodes - 1))
+        tg: set[int] = set()
+        while len(tg) < fan:
+            if rng.random() < local:
+                t = src + int(rng.integers(-span, span + 1))
+                if t < 0 or t >= n_nodes:
+                    continue
+            else:
+                t = int(rng.integers(0, n_nodes))
+            if t != src:
+                tg.add(t)
+        ids = np.array(sorted(tg | {src}), dtype=np.int64)
+        flags = (ids != src).astype(np.int64) << 31
+        pins.append((ids | flags).astype(np.uint32))
+        eoff.append(eoff[-1] + len(ids))
+    P = np.concatenate(pins) if pins else np.zeros(0, np.uint32)
+    return Level0(n_nodes, np.array(eoff, dtype=np.int64), P, w, f"gp{n_nodes}s{seed}")
