@@ -33,6 +33,7 @@ CFLAGS = [
 # wave-wide reduction.
 EXTRA = {
     "hg_score.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+    "hg_score_dense.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
 }
 
 

@@ -176,6 +176,9 @@ struct ScoreArgs {
 constexpr int kWinAlignBits = 19;
 constexpr int kMaxAlignedWindows = 16;
 void score_candidates(const ScoreArgs& a, int64_t maxV, int64_t maxP, hipStream_t s);
+// Dense-window scoring of work lists 8 and 9 (hg_score_dense.hip); called by
+// score_candidates, a no-op on levels without dense windows.
+void score_dense(const ScoreArgs& a, int64_t maxV, hipStream_t s);
 
 // ---- S3-S5 (hg_match.hip) ---------------------------------------------------
 struct MatchArgs {

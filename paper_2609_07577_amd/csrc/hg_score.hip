@@ -24,6 +24,7 @@
 // hyperedges.
 #include <type_traits>
 #include "hg_internal.h"
+#include "hg_score_common.h"
 
 namespace hg {
 
@@ -69,34 +70,6 @@ __device__ inline uint32_t table_add(uint64_t* table, uint32_t mask, int shift, 
 
 __device__ inline int log2_pow2(uint32_t c) { return 31 - __clz(c); }
 
-// A value that is the same in every lane (e.g. read from LDS at a
-// wave-uniform address), moved to a scalar register so that the control flow
-// depending on it stays scalar.
-// The lane mask of a predicate (HIP's __ballot takes an int, which costs a
-// select and a compare per call to turn the predicate back into a mask).
-__device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
-__device__ inline int32_t rfl_i32(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ inline uint32_t rfl_u32(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)x);
-}
-
-struct VertexCtx {
-  int32_t n;
-  int64_t beg, deg;
-  int32_t size_n, syn_n, ax_n;
-  GraphConst G;
-  bool all_valid;
-};
-
-// Section 3 limits on the union of n and m; `ov` is the number of original
-// axons with a destination in both (0 when the distinct-axon bound cannot
-// bind for this vertex).
-__device__ inline bool merge_valid(const ScoreArgs& a, const VertexCtx& v, uint32_t m,
-                                   int64_t ov) {
-  if ((int64_t)v.size_n + a.L.size[m] > v.G.omega) return false;
-  if ((int64_t)v.syn_n + a.L.syn[m] > v.G.phi) return false;
-  return (int64_t)v.ax_n + a.L.ax[m] - ov <= v.G.delta;
-}
 
 // Scans the first `cap` slots: folds entries into `best`, empties them.
 template <bool OV>
@@ -119,23 +92,6 @@ __device__ inline void drain_table(uint64_t* table, uint32_t* ovtab, int cap,
   }
 }
 
-template <int THREADS>
-__device__ inline uint64_t block_max_u64(uint64_t x, uint64_t* red) {
-  constexpr int NW = THREADS / kWave;
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    uint64_t o = __shfl_xor(x, d, kWave);
-    x = o > x ? o : x;
-  }
-  int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  if (lane == 0) red[wid] = x;
-  __syncthreads();
-  uint64_t r = red[0];
-#pragma unroll
-  for (int k = 1; k < NW; ++k) r = red[k] > r ? red[k] : r;
-  __syncthreads();
-  return r;
-}
 
 template <int THREADS>
 __device__ inline void block_min_max_i64(int64_t& mn, int64_t& mx, int64_t* red) {
@@ -624,50 +580,6 @@ __global__ __launch_bounds__(THREADS) void score_stream_kernel(ScoreArgs a, int 
   }
 }
 
-// Inclusive prefix sum over the 64 lanes of a wave with the DPP unit: four
-// shifts within rows of 16 lanes, then the row totals carried into the later
-// rows with the row broadcasts (lanes shifted in from outside a row, and
-// rows a step leaves out, add 0).
-__device__ inline int32_t wave_incl_scan(int32_t x) {
-  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
-  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
-  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
-  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
-  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 to rows 1, 3
-  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 to rows 2, 3
-  return x;
-}
-
-// Exclusive block-wide prefix sums of three per-thread values (in thread
-// order) and their totals.  One barrier: the caller synchronises again
-// before ws (3 * NW entries) is written by another scan.
-template <int THREADS>
-__device__ inline void block_scan3(const int32_t (&x)[3], int32_t (&px)[3], int32_t (&tx)[3],
-                                   int32_t* ws) {
-  constexpr int NW = THREADS / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  int32_t ix[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    ix[c] = wave_incl_scan(x[c]);
-    if (lane == kWave - 1) ws[c * NW + wid] = ix[c];
-  }
-  __syncthreads();
-  // the wave totals, one per lane, scanned again; a wave takes the sum of
-  // the waves before it and the total with readlane
-  static_assert(NW <= kWave, "one lane per wave");
-  int32_t wt[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) wt[c] = lane < NW ? ws[c * NW + lane] : 0;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const int32_t inc = wave_incl_scan(wt[c]);
-    const int32_t before = wid > 0 ? __builtin_amdgcn_readlane(inc, wid - 1) : 0;
-    px[c] = before + ix[c] - x[c];
-    tx[c] = __builtin_amdgcn_readlane(inc, NW - 1);
-  }
-}
 
 // Multipass over windows of neighbour ids for vertices whose incident
 // hyperedges fit in LDS (no distinct-axon overlap needed).  In a large
@@ -1765,234 +1677,6 @@ __global__ __launch_bounds__(THREADS) void score_window2_kernel(ScoreArgs a, int
   }
 }
 
-// Slices of every hyperedge at the dense windows of 2^kDenseBits ids: a wave
-// per hyperedge walks its ascending pins 64 at a time; where the window of
-// consecutive pins changes, the windows passed over get the pin's position.
-__global__ void dense_splits_kernel(const Dims* __restrict__ d, const int64_t* __restrict__ eoff,
-                                    const uint32_t* __restrict__ pins, int32_t W,
-                                    uint32_t* __restrict__ splits) {
-  const int64_t E = d->E;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
-  for (int64_t e = wave; e < E; e += nw) {
-    const int64_t s0 = eoff[e];
-    const int32_t len = (int32_t)(eoff[e + 1] - s0);
-    uint32_t* out = splits + e * (int64_t)(W + 1);
-    int32_t prev_w = -1;  // window of the pin before the chunk (-1: before the first)
-    for (int32_t c = 0; c < len; c += kWave) {  // wave-uniform
-      const int32_t i = c + lane;
-      const int32_t w = i < len ? (int32_t)((pins[s0 + i] & kIdMask) >> kDenseBits) : W;
-      int32_t before = __shfl_up(w, 1, kWave);
-      if (lane == 0) before = prev_w;
-      // windows (before, w] start at pin i (pins of window w begin here)
-      if (i < len)
-        for (int32_t x = before + 1; x <= w && x <= W; ++x) out[x] = (uint32_t)i;
-      prev_w = __shfl(w, kWave - 1, kWave);
-      if (prev_w >= W) break;
-    }
-    // windows after the last pin's window end at the hyperedge's end
-    const int32_t last = len > 0 ? (int32_t)((pins[s0 + len - 1] & kIdMask) >> kDenseBits) : -1;
-    for (int32_t x = last + 1 + lane; x <= W; x += kWave) out[x] = (uint32_t)len;
-  }
-}
-
-// Dense windows (neighbourhoods that visit at least one id in kDenseRatio
-// of the level): per window of 2^kDenseBits ids, a packed 64-bit LDS entry
-// per id holds (score << 32 | overlap), and one sweep over the window's
-// slices (chunk lists from `splits14`, in rounds of kMaxChunks) adds
-// (weight << 32 | overlap share) per visit with one returning 64-bit LDS
-// atomic.  The entry returned plus the visit's share is the id's (score,
-// overlap) so far; every id's last visit sees its totals, and scores and
-// overlaps only grow, so the best valid neighbour is the largest (score,
-// -id) a lane sees among valid ids: validity is tested only for keys above
-// the lane's best, with the overlap seen by that visit (the test only gets
-// easier as the overlap grows).  OV: the overlap share of a visit is the
-// hyperedge's multiplicity when n and the visited id both carry its flag.
-template <int THREADS, bool OV>
-__global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int bucket,
-                                                             int64_t maxV) {
-  constexpr int NW = THREADS / kWave;
-  constexpr int B = 4;
-  constexpr int kIds = 1 << kDenseBits;
-  constexpr int kMaxChunks = 1024;
-  constexpr uint32_t kSent = 0x7FFFFFFFu;
-  static_assert(kIds * 8 == THREADS * 128, "a thread clears 128 bytes of the table");
-  struct Lds {
-    uint64_t tab[kIds];
-    uint4 desc[kMaxChunks + B];  // x first pin, y pin count, z weight, w overlap share
-    int32_t ws[3 * NW];
-    uint64_t red[2 * NW];
-    int32_t s_item;
-    int32_t s_next;
-  };
-  __shared__ Lds S;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1);
-  const int wid = rfl_i32(tid / kWave);
-  int32_t count = a.b.count[bucket];
-  if (count > maxV) {
-    if (tid == 0) atomicOr(a.err, kErrWorkCount);
-    count = (int32_t)maxV;
-  }
-  const int32_t* list = a.b.list + (int64_t)bucket * maxV;
-  // splits14 rows hold n_win14 + 1 entries (the windows of the largest
-  // level); the windows past this level's ids are empty and skipped
-  const int32_t W = a.n_win14;
-  const int64_t Vl = a.L.dims->V;
-  const int32_t Wl = (int32_t)((Vl + kIds - 1) >> kDenseBits) < W
-                         ? (int32_t)((Vl + kIds - 1) >> kDenseBits) : W;
-  uint4* const tab4 = reinterpret_cast<uint4*>(S.tab);
-  const uint32_t lofs = (uint32_t)lane * 4u;
-
-  while (true) {
-    __syncthreads();
-    if (tid == 0) S.s_item = atomicAdd(&a.work[bucket], 1);
-    __syncthreads();
-    const int32_t item = S.s_item;
-    if (item >= count) break;
-    VertexCtx v;
-    v.n = list[item];
-    v.beg = a.voff[v.n];
-    v.deg = a.voff[v.n + 1] - v.beg;
-    v.size_n = a.L.size[v.n];
-    v.syn_n = a.L.syn[v.n];
-    v.ax_n = a.L.ax[v.n];
-    v.G = a.gc[a.L.gid ? a.L.gid[v.n] : 0];
-    v.all_valid = (int64_t)v.size_n + v.G.max_size <= v.G.omega &&
-                  (int64_t)v.syn_n + v.G.max_syn <= v.G.phi &&
-                  (int64_t)v.ax_n + v.G.max_ax <= v.G.delta;
-    const uint32_t n = (uint32_t)v.n;
-    const int64_t deg = v.deg;
-    uint64_t best = 0;
-    for (int32_t wi = 0; wi < Wl; ++wi) {  // block-uniform
-      const uint32_t lo = (uint32_t)wi << kDenseBits;
-      // chunks of this window: thread t owns incident hyperedges t, t + THREADS, ...
-      int32_t mine = 0;
-      for (int64_t j = tid; j < deg; j += THREADS) {
-        const uint32_t e = a.vinc[v.beg + j] & kIdMask;
-        const uint32_t* sr = a.splits14 + (int64_t)e * (W + 1);
-        mine += (int32_t)((sr[wi + 1] - sr[wi] + kWave - 1) / kWave);
-      }
-      int32_t x3[3] = {mine, 0, 0}, p3[3], t3[3];
-      block_scan3<THREADS>(x3, p3, t3, S.ws);
-      const int32_t T = t3[0];
-      if (T == 0) {  // block-uniform; the scan's words are read before the next scan
-        __syncthreads();
-        continue;
-      }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) tab4[8 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
-      for (int32_t r0 = 0; r0 < T; r0 += kMaxChunks) {  // block-uniform
-        const int32_t Tr = T - r0 < kMaxChunks ? T - r0 : kMaxChunks;
-        __syncthreads();  // table clear, previous round's chunks done
-        int32_t c = p3[0];  // this thread's first chunk in the window's list
-        for (int64_t j = tid; j < deg; j += THREADS) {
-          const uint32_t ent = a.vinc[v.beg + j];
-          const uint32_t e = ent & kIdMask;
-          const uint32_t* sr = a.splits14 + (int64_t)e * (W + 1);
-          const uint32_t first = (uint32_t)a.L.eoff[e] + sr[wi];
-          const uint32_t len = sr[wi + 1] - sr[wi];
-          const int32_t nch = (int32_t)((len + kWave - 1) / kWave);
-          if (c + nch > r0 && c < r0 + Tr) {
-            const uint32_t wt = (uint32_t)a.L.w[e];
-            const uint32_t mu = (OV && (ent & kDst)) ? (uint32_t)a.L.mult[e] : 0u;
-            for (int32_t q = 0; q < nch; ++q) {
-              const int32_t at = c + q - r0;
-              if (at < 0 || at >= Tr) continue;
-              const uint32_t left = len - (uint32_t)q * kWave;
-              S.desc[at] = make_uint4(first + (uint32_t)q * kWave,
-                                      left < (uint32_t)kWave ? left : (uint32_t)kWave, wt, mu);
-            }
-          }
-          c += nch;
-        }
-        if (tid < B) S.desc[Tr + tid] = make_uint4(0u, 0u, 0u, 0u);
-        if (tid == 0) S.s_next = NW;
-        __syncthreads();
-        const int32_t tb = (Tr + B - 1) / B;
-        // ---- the sweep
-        struct Batch {
-          uint32_t x[B];
-          int32_t cnt[B];
-          uint32_t wt[B], mu[B];
-        };
-        int32_t bclaim = wid;
-        auto fetch = [&](Batch& t, uint32_t (&pin)[B], int32_t bno) {
-#pragma unroll
-          for (int u = 0; u < B; ++u) {
-            uint4 d = make_uint4(0u, 0u, 0u, 0u);
-            if (bno < tb) d = S.desc[bno * B + u];
-            t.x[u] = rfl_u32(d.x);
-            t.cnt[u] = (int32_t)rfl_u32(d.y);
-            t.wt[u] = rfl_u32(d.z);
-            t.mu[u] = rfl_u32(d.w);
-          }
-#pragma unroll
-          for (int u = 0; u < B; ++u) {
-            const uint32_t last4 = t.cnt[u] > 0 ? (uint32_t)(t.cnt[u] - 1) * 4u : 0u;
-            const char* p = reinterpret_cast<const char*>(a.L.pins + t.x[u]);
-            const uint32_t off = lofs < last4 ? lofs : last4;
-            pin[u] = *reinterpret_cast<const uint32_t*>(p + off);
-          }
-          if (bno < tb) {  // wave-uniform: claim the next batch
-            int32_t cc = 0;
-            if (lane == 0) cc = atomicAdd(&S.s_next, 1);
-            bclaim = cc;
-          }
-          __builtin_amdgcn_sched_barrier(0);
-        };
-        auto process = [&](const Batch& t, const uint32_t (&pin)[B]) {
-#pragma unroll
-          for (int u = 0; u < B; ++u) {
-            const uint32_t id = pin[u] & kIdMask;
-            const bool act = lofs < (uint32_t)t.cnt[u] * 4u && id != n;
-            if (act) {  // no cross-lane operation inside
-              const uint64_t add = ((uint64_t)t.wt[u] << 32) |
-                                   (uint64_t)((OV && (pin[u] & kDst)) ? t.mu[u] : 0u);
-              const uint64_t now =
-                  atomicAdd((unsigned long long*)&S.tab[id - lo], (unsigned long long)add) +
-                  add;
-              const uint64_t key = (now & 0xFFFFFFFF00000000ull) | (uint64_t)(kSent - id);
-              if (key > best &&
-                  (v.all_valid || merge_valid(a, v, id, OV ? (int64_t)(now & 0xFFFFFFFFull) : 0)))
-                best = key;
-            }
-          }
-          asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
-        };
-        {
-          Batch ta, tb2;
-          uint32_t pa[B], pb[B];
-          int32_t cur_b = wid;
-          fetch(ta, pa, cur_b);
-          while (cur_b < tb) {
-            const int32_t nb = __builtin_amdgcn_readlane(bclaim, 0);
-            fetch(tb2, pb, nb);
-            process(ta, pa);
-            cur_b = nb;
-            if (cur_b >= tb) break;
-            const int32_t nb2 = __builtin_amdgcn_readlane(bclaim, 0);
-            fetch(ta, pa, nb2);
-            process(tb2, pb);
-            cur_b = nb2;
-          }
-        }
-      }
-      __syncthreads();  // the window's sweep done before the table is cleared again
-    }
-    best = block_max_u64<THREADS>(best, S.red);
-    if (tid == 0) {
-      if (best == 0) {
-        a.cand[v.n] = -1;
-        a.cscore[v.n] = 0;
-      } else {
-        a.cand[v.n] = (int32_t)(kSent - (uint32_t)(best & 0xFFFFFFFFull));
-        a.cscore[v.n] = (int32_t)(best >> 32);
-      }
-    }
-  }
-}
-
 __global__ void no_candidate_kernel(const Dims* __restrict__ d, int32_t* __restrict__ cand,
                                     int32_t* __restrict__ cscore, int32_t* __restrict__ work) {
   int64_t V = d->V;
@@ -2005,14 +1689,6 @@ __global__ void no_candidate_kernel(const Dims* __restrict__ d, int32_t* __restr
   }
 }
 
-template <typename K>
-int persistent_grid(K kernel, int threads) {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  return per_cu * device_cu_count();
-}
 
 }  // namespace
 
@@ -2068,19 +1744,7 @@ void score_candidates(const ScoreArgs& a, int64_t maxV, int64_t maxP, hipStream_
     k6w<<<g2[dev][1], 1024, 0, s>>>(a, 6, maxV);
   else
     k6<<<g[6], 1024, 0, s>>>(a, 6, maxV);
-  if (a.n_win14 > 0 && a.splits14) {
-    static int g3[kMaxDevices][2] = {};
-    auto k8 = score_dense_kernel<1024, false>;
-    auto k9 = score_dense_kernel<1024, true>;
-    if (!g3[dev][0]) {
-      g3[dev][0] = persistent_grid(k8, 1024);
-      g3[dev][1] = persistent_grid(k9, 1024);
-    }
-    dense_splits_kernel<<<4096, 256, 0, s>>>(a.L.dims, a.L.eoff, a.L.pins, a.n_win14,
-                                             a.splits14);
-    k8<<<g3[dev][0], 1024, 0, s>>>(a, 8, maxV);
-    k9<<<g3[dev][1], 1024, 0, s>>>(a, 9, maxV);
-  }
+  score_dense(a, maxV, s);
   k7<<<g[7], 512, 0, s>>>(a, 7, maxV, maxP);
 }
 
