@@ -2,6 +2,8 @@
 // vertices whose neighbour visits reach a large share of the level's ids
 // (work lists 8 and 9 of the bucket rule), scored in windows of 2^14 ids
 // with one packed LDS entry per id.
+#include <type_traits>
+
 #include "hg_internal.h"
 #include "hg_score_common.h"
 
@@ -41,18 +43,28 @@ __global__ void dense_splits_kernel(const Dims* __restrict__ d, const int64_t* _
   }
 }
 
-// Dense windows (neighbourhoods that visit at least one id in kDenseRatio
-// of the level): per window of 2^kDenseBits ids, a packed 64-bit LDS entry
-// per id holds (score << 32 | overlap), and one sweep over the window's
-// slices (chunk lists from `splits14`, in rounds of kMaxChunks) adds
-// (weight << 32 | overlap share) per visit with one returning 64-bit LDS
-// atomic.  The entry returned plus the visit's share is the id's (score,
-// overlap) so far; every id's last visit sees its totals, and scores and
-// overlaps only grow, so the best valid neighbour is the largest (score,
-// -id) a lane sees among valid ids: validity is tested only for keys above
-// the lane's best, with the overlap seen by that visit (the test only gets
-// easier as the overlap grows).  OV: the overlap share of a visit is the
-// hyperedge's multiplicity when n and the visited id both carry its flag.
+// Dense windows (neighbourhoods that visit at least one id in dense_ratio
+// of the level): per window of ids, one packed LDS entry per id holds the
+// id's (score, overlap) so far, and one sweep over the window's slices adds
+// the visit's (weight, overlap share) with one returning LDS atomic.  The
+// entry returned plus the visit's share is the id's (score, overlap) so
+// far; every id's last visit sees its totals, and scores and overlaps only
+// grow, so the best valid neighbour is the largest (score, -id) a lane sees
+// among valid ids, whatever the order of the visits: validity is tested
+// only for keys above the lane's best, with the overlap seen by that visit
+// (the test only gets easier as the overlap grows).  OV: the overlap share
+// of a visit is the hyperedge's multiplicity when n and the visited id both
+// carry its flag.
+//
+// Entry width per vertex: a score is at most S_n (the weight of n's
+// incident hyperedges) and an overlap at most M_n (their multiplicity where
+// n carries the flag).  When both fit in 32 bits together (always without
+// OV), entries are 32-bit, score << b | overlap with b the bits of M_n, and a
+// window spans 2^(kDenseBits + 1) ids (two windows of the split table);
+// otherwise entries are 64-bit, score << 32 | overlap, over 2^kDenseBits
+// ids.  The window's slices (from `splits14`) are cut into chunks of up to
+// 64 pins listed in LDS and claimed by the waves in batches of B; a window
+// of more than kMaxChunks chunks is swept in rounds.
 template <int THREADS, bool OV>
 __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int bucket,
                                                              int64_t maxV) {
@@ -63,7 +75,7 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
   constexpr uint32_t kSent = 0x7FFFFFFFu;
   static_assert(kIds * 8 == THREADS * 128, "a thread clears 128 bytes of the table");
   struct Lds {
-    uint64_t tab[kIds];
+    uint64_t tab[kIds];          // 2^14 64-bit entries or 2^15 32-bit ones
     uint4 desc[kMaxChunks + B];  // x first pin, y pin count, z weight, w overlap share
     int32_t ws[3 * NW];
     uint64_t red[2 * NW];
@@ -86,6 +98,7 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
   const int32_t Wl = (int32_t)((Vl + kIds - 1) >> kDenseBits) < W
                          ? (int32_t)((Vl + kIds - 1) >> kDenseBits) : W;
   uint4* const tab4 = reinterpret_cast<uint4*>(S.tab);
+  uint32_t* const tab32 = reinterpret_cast<uint32_t*>(S.tab);
   const uint32_t lofs = (uint32_t)lane * 4u;
 
   while (true) {
@@ -108,122 +121,173 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
     const uint32_t n = (uint32_t)v.n;
     const int64_t deg = v.deg;
     uint64_t best = 0;
-    for (int32_t wi = 0; wi < Wl; ++wi) {  // block-uniform
-      const uint32_t lo = (uint32_t)wi << kDenseBits;
-      // chunks of this window: thread t owns incident hyperedges t, t + THREADS, ...
-      int32_t mine = 0;
+    // bounds of a score (S_n) and of an overlap (M_n), for the entry width
+    int32_t ob = 0;  // overlap bits of a compact entry
+    bool compact = true;
+    if (OV) {
+      // both sums stay below 2^31: the weights of a level sum below 2^31 and
+      // the multiplicities below the number of original axons
+      int32_t sw = 0, sm = 0;
       for (int64_t j = tid; j < deg; j += THREADS) {
-        const uint32_t e = a.vinc[v.beg + j] & kIdMask;
-        const uint32_t* sr = a.splits14 + (int64_t)e * (W + 1);
-        mine += (int32_t)((sr[wi + 1] - sr[wi] + kWave - 1) / kWave);
+        const uint32_t ent = a.vinc[v.beg + j];
+        const uint32_t e = ent & kIdMask;
+        sw += a.L.w[e];
+        if (ent & kDst) sm += a.L.mult[e];
       }
-      int32_t x3[3] = {mine, 0, 0}, p3[3], t3[3];
+      int32_t x3[3] = {sw, sm, 0}, p3[3], t3[3];
       block_scan3<THREADS>(x3, p3, t3, S.ws);
-      const int32_t T = t3[0];
-      if (T == 0) {  // block-uniform; the scan's words are read before the next scan
-        __syncthreads();
-        continue;
-      }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) tab4[8 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
-      for (int32_t r0 = 0; r0 < T; r0 += kMaxChunks) {  // block-uniform
-        const int32_t Tr = T - r0 < kMaxChunks ? T - r0 : kMaxChunks;
-        __syncthreads();  // table clear, previous round's chunks done
-        int32_t c = p3[0];  // this thread's first chunk in the window's list
-        for (int64_t j = tid; j < deg; j += THREADS) {
-          const uint32_t ent = a.vinc[v.beg + j];
-          const uint32_t e = ent & kIdMask;
-          const uint32_t* sr = a.splits14 + (int64_t)e * (W + 1);
-          const uint32_t first = (uint32_t)a.L.eoff[e] + sr[wi];
-          const uint32_t len = sr[wi + 1] - sr[wi];
-          const int32_t nch = (int32_t)((len + kWave - 1) / kWave);
-          if (c + nch > r0 && c < r0 + Tr) {
-            const uint32_t wt = (uint32_t)a.L.w[e];
-            const uint32_t mu = (OV && (ent & kDst)) ? (uint32_t)a.L.mult[e] : 0u;
-            for (int32_t q = 0; q < nch; ++q) {
-              const int32_t at = c + q - r0;
-              if (at < 0 || at >= Tr) continue;
-              const uint32_t left = len - (uint32_t)q * kWave;
-              S.desc[at] = make_uint4(first + (uint32_t)q * kWave,
-                                      left < (uint32_t)kWave ? left : (uint32_t)kWave, wt, mu);
-            }
-          }
-          c += nch;
-        }
-        if (tid < B) S.desc[Tr + tid] = make_uint4(0u, 0u, 0u, 0u);
-        if (tid == 0) S.s_next = NW;
-        __syncthreads();
-        const int32_t tb = (Tr + B - 1) / B;
-        // ---- the sweep
-        struct Batch {
-          uint32_t x[B];
-          int32_t cnt[B];
-          uint32_t wt[B], mu[B];
-        };
-        int32_t bclaim = wid;
-        auto fetch = [&](Batch& t, uint32_t (&pin)[B], int32_t bno) {
-#pragma unroll
-          for (int u = 0; u < B; ++u) {
-            uint4 d = make_uint4(0u, 0u, 0u, 0u);
-            if (bno < tb) d = S.desc[bno * B + u];
-            t.x[u] = rfl_u32(d.x);
-            t.cnt[u] = (int32_t)rfl_u32(d.y);
-            t.wt[u] = rfl_u32(d.z);
-            t.mu[u] = rfl_u32(d.w);
-          }
-#pragma unroll
-          for (int u = 0; u < B; ++u) {
-            const uint32_t last4 = t.cnt[u] > 0 ? (uint32_t)(t.cnt[u] - 1) * 4u : 0u;
-            const char* p = reinterpret_cast<const char*>(a.L.pins + t.x[u]);
-            const uint32_t off = lofs < last4 ? lofs : last4;
-            pin[u] = *reinterpret_cast<const uint32_t*>(p + off);
-          }
-          if (bno < tb) {  // wave-uniform: claim the next batch
-            int32_t cc = 0;
-            if (lane == 0) cc = atomicAdd(&S.s_next, 1);
-            bclaim = cc;
-          }
-          __builtin_amdgcn_sched_barrier(0);
-        };
-        auto process = [&](const Batch& t, const uint32_t (&pin)[B]) {
-#pragma unroll
-          for (int u = 0; u < B; ++u) {
-            const uint32_t id = pin[u] & kIdMask;
-            const bool act = lofs < (uint32_t)t.cnt[u] * 4u && id != n;
-            if (act) {  // no cross-lane operation inside
-              const uint64_t add = ((uint64_t)t.wt[u] << 32) |
-                                   (uint64_t)((OV && (pin[u] & kDst)) ? t.mu[u] : 0u);
-              const uint64_t now =
-                  atomicAdd((unsigned long long*)&S.tab[id - lo], (unsigned long long)add) +
-                  add;
-              const uint64_t key = (now & 0xFFFFFFFF00000000ull) | (uint64_t)(kSent - id);
-              if (key > best &&
-                  (v.all_valid || merge_valid(a, v, id, OV ? (int64_t)(now & 0xFFFFFFFFull) : 0)))
-                best = key;
-            }
-          }
-          asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
-        };
-        {
-          Batch ta, tb2;
-          uint32_t pa[B], pb[B];
-          int32_t cur_b = wid;
-          fetch(ta, pa, cur_b);
-          while (cur_b < tb) {
-            const int32_t nb = __builtin_amdgcn_readlane(bclaim, 0);
-            fetch(tb2, pb, nb);
-            process(ta, pa);
-            cur_b = nb;
-            if (cur_b >= tb) break;
-            const int32_t nb2 = __builtin_amdgcn_readlane(bclaim, 0);
-            fetch(ta, pa, nb2);
-            process(tb2, pb);
-            cur_b = nb2;
-          }
-        }
-      }
-      __syncthreads();  // the window's sweep done before the table is cleared again
+      const uint32_t S_n = (uint32_t)t3[0], M_n = (uint32_t)t3[1];
+      const int sb = S_n ? 32 - __clz(S_n) : 0;
+      ob = M_n ? 32 - __clz(M_n) : 0;
+      compact = sb + ob <= 32;
+      __syncthreads();  // the scan words are read before the windows' scans
     }
+    auto windows = [&](auto compact_tag) {
+      constexpr bool C = decltype(compact_tag)::value;
+      constexpr int kBits = C ? kDenseBits + 1 : kDenseBits;
+      const int32_t nw = C ? (Wl + 1) / 2 : Wl;
+      const uint32_t omask = C ? ((1u << ob) - 1u) : 0xFFFFFFFFu;
+      // split-table bounds of window wi (two 2^14 windows when compact)
+      auto bounds = [&](const uint32_t* sr, int32_t wi, uint32_t& b0, uint32_t& b1) {
+        if (C) {
+          b0 = sr[2 * wi];
+          b1 = sr[2 * wi + 2 <= W ? 2 * wi + 2 : W];
+        } else {
+          b0 = sr[wi];
+          b1 = sr[wi + 1];
+        }
+      };
+      for (int32_t wi = 0; wi < nw; ++wi) {  // block-uniform
+        const uint32_t lo = (uint32_t)wi << kBits;
+        // chunks of this window: thread t owns incident hyperedges t, t + THREADS, ...
+        int32_t mine = 0;
+        for (int64_t j = tid; j < deg; j += THREADS) {
+          const uint32_t e = a.vinc[v.beg + j] & kIdMask;
+          uint32_t b0, b1;
+          bounds(a.splits14 + (int64_t)e * (W + 1), wi, b0, b1);
+          mine += (int32_t)((b1 - b0 + kWave - 1) / kWave);
+        }
+        int32_t x3[3] = {mine, 0, 0}, p3[3], t3[3];
+        block_scan3<THREADS>(x3, p3, t3, S.ws);
+        const int32_t T = t3[0];
+        if (T == 0) {  // block-uniform; the scan's words are read before the next scan
+          __syncthreads();
+          continue;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) tab4[8 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
+        for (int32_t r0 = 0; r0 < T; r0 += kMaxChunks) {  // block-uniform
+          const int32_t Tr = T - r0 < kMaxChunks ? T - r0 : kMaxChunks;
+          __syncthreads();  // table clear, previous round's chunks done
+          int32_t c = p3[0];  // this thread's first chunk in the window's list
+          for (int64_t j = tid; j < deg; j += THREADS) {
+            const uint32_t ent = a.vinc[v.beg + j];
+            const uint32_t e = ent & kIdMask;
+            uint32_t b0, b1;
+            bounds(a.splits14 + (int64_t)e * (W + 1), wi, b0, b1);
+            const uint32_t first = (uint32_t)a.L.eoff[e] + b0;
+            const uint32_t len = b1 - b0;
+            const int32_t nch = (int32_t)((len + kWave - 1) / kWave);
+            if (c + nch > r0 && c < r0 + Tr) {
+              const uint32_t wt = (uint32_t)a.L.w[e];
+              const uint32_t mu = (OV && (ent & kDst)) ? (uint32_t)a.L.mult[e] : 0u;
+              for (int32_t q = 0; q < nch; ++q) {
+                const int32_t at = c + q - r0;
+                if (at < 0 || at >= Tr) continue;
+                const uint32_t left = len - (uint32_t)q * kWave;
+                S.desc[at] = make_uint4(first + (uint32_t)q * kWave,
+                                        left < (uint32_t)kWave ? left : (uint32_t)kWave, wt, mu);
+              }
+            }
+            c += nch;
+          }
+          if (tid < B) S.desc[Tr + tid] = make_uint4(0u, 0u, 0u, 0u);
+          if (tid == 0) S.s_next = NW;
+          __syncthreads();
+          const int32_t tb = (Tr + B - 1) / B;
+          // ---- the sweep
+          struct Batch {
+            uint32_t x[B];
+            int32_t cnt[B];
+            uint32_t wt[B], mu[B];
+          };
+          int32_t bclaim = wid;
+          auto fetch = [&](Batch& t, uint32_t (&pin)[B], int32_t bno) {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+              uint4 d = make_uint4(0u, 0u, 0u, 0u);
+              if (bno < tb) d = S.desc[bno * B + u];
+              t.x[u] = rfl_u32(d.x);
+              t.cnt[u] = (int32_t)rfl_u32(d.y);
+              t.wt[u] = rfl_u32(d.z);
+              t.mu[u] = rfl_u32(d.w);
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+              const uint32_t last4 = t.cnt[u] > 0 ? (uint32_t)(t.cnt[u] - 1) * 4u : 0u;
+              const char* p = reinterpret_cast<const char*>(a.L.pins + t.x[u]);
+              const uint32_t off = lofs < last4 ? lofs : last4;
+              pin[u] = *reinterpret_cast<const uint32_t*>(p + off);
+            }
+            if (bno < tb) {  // wave-uniform: claim the next batch
+              int32_t cc = 0;
+              if (lane == 0) cc = atomicAdd(&S.s_next, 1);
+              bclaim = cc;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          };
+          auto process = [&](const Batch& t, const uint32_t (&pin)[B]) {
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+              const uint32_t id = pin[u] & kIdMask;
+              const bool act = lofs < (uint32_t)t.cnt[u] * 4u && id != n;
+              if (act) {  // no cross-lane operation inside
+                const uint32_t share = (OV && (pin[u] & kDst)) ? t.mu[u] : 0u;
+                uint64_t sc;
+                uint32_t ov;
+                if (C) {
+                  const uint32_t add = (t.wt[u] << ob) | share;
+                  const uint32_t now = atomicAdd(&tab32[id - lo], add) + add;
+                  sc = now >> ob;
+                  ov = now & omask;
+                } else {
+                  const uint64_t add = ((uint64_t)t.wt[u] << 32) | (uint64_t)share;
+                  const uint64_t now =
+                      atomicAdd((unsigned long long*)&S.tab[id - lo], (unsigned long long)add) +
+                      add;
+                  sc = now >> 32;
+                  ov = (uint32_t)now;
+                }
+                const uint64_t key = (sc << 32) | (uint64_t)(kSent - id);
+                if (key > best && (v.all_valid || merge_valid(a, v, id, OV ? (int64_t)ov : 0)))
+                  best = key;
+              }
+            }
+            asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
+          };
+          {
+            Batch ta, tb2;
+            uint32_t pa[B], pb[B];
+            int32_t cur_b = wid;
+            fetch(ta, pa, cur_b);
+            while (cur_b < tb) {
+              const int32_t nb = __builtin_amdgcn_readlane(bclaim, 0);
+              fetch(tb2, pb, nb);
+              process(ta, pa);
+              cur_b = nb;
+              if (cur_b >= tb) break;
+              const int32_t nb2 = __builtin_amdgcn_readlane(bclaim, 0);
+              fetch(ta, pa, nb2);
+              process(tb2, pb);
+              cur_b = nb2;
+            }
+          }
+        }
+        __syncthreads();  // the window's sweep done before the table is cleared again
+      }
+    };
+    if (compact) windows(std::integral_constant<bool, true>{});
+    else windows(std::integral_constant<bool, false>{});
     best = block_max_u64<THREADS>(best, S.red);
     if (tid == 0) {
       if (best == 0) {

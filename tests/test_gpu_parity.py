@@ -594,3 +594,28 @@ def test_dense_window_rounds(ctx, delta):
     assert chunks[targets].min() > 1024, "every target must need a second round"
     with _tuned(ctx, dense_ratio=8):
         run_hierarchy_parity(ctx, g, lim, max_levels=2, verbose=True)
+
+
+def test_dense_entry_widths(ctx):
+    """Heavy weights (uniform up to 150,000) on the hub graph of the overlap
+    test: a typical vertex's score and overlap bounds fit one 32-bit dense
+    entry together, a hub's (about 900 incident hyperedges) do not, so both
+    entry widths of the dense kernel decide candidates on level 0; three
+    levels against the oracle."""
+    g = synth.hub_graph(1, 12000, 100, 8, 0.075, w_max=150000)
+    L0 = oracle.level0(g)
+    lim = synth.Limits(512, 65536, 1000)
+    lens = np.diff(L0.eoff)
+    ids = (L0.pins & 0x7FFFFFFF).astype(np.int64)
+    dst = (L0.pins >> 31).astype(np.int64)
+    e_of = np.repeat(np.arange(L0.E), lens)
+    S = np.bincount(ids, weights=L0.w[e_of].astype(np.float64), minlength=L0.V).astype(np.int64)
+    M = np.bincount(ids, weights=(dst * L0.mult[e_of]).astype(np.float64),
+                    minlength=L0.V).astype(np.int64)
+    bits = np.array([int(x).bit_length() for x in S]) + np.array([int(x).bit_length() for x in M])
+    b = hgcheck.score_buckets(L0, lim, dense_ratio=8)
+    assert ((b == 9) & (bits > 32)).sum() >= 8 and ((b == 9) & (bits <= 32)).sum() >= 10000
+    census = np.zeros(10, np.int64)
+    with _tuned(ctx, dense_ratio=8):
+        run_hierarchy_parity(ctx, g, lim, max_levels=3, census=census, verbose=True)
+    assert census[9] >= 12000
