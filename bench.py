@@ -371,6 +371,8 @@ def run_hierarchy(args):
     L = L0
     part = torch.arange(g.n_vertices, dtype=torch.int32, device="cuda")
     rows, t_total, pins_total, all_equal = [], 0.0, 0, True
+    t_start = time.perf_counter()
+    anyc = 1
     while True:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -396,8 +398,12 @@ def run_hierarchy(args):
                  f"conn={row.get('conn')} equal={row.get('conn_equal')}")
         if not anyc:
             break
+        if args.time_limit and time.perf_counter() - t_start > args.time_limit:
+            _log(f"time limit reached after {len(rows)} levels; reporting them")
+            break
         L = C
-    n_contract = len(rows) - 1
+    finished = not anyc
+    n_contract = len(rows) - 1 if finished else len(rows)
     result = {
         "metric": METRIC,
         "value": pins_total / t_total,
@@ -410,6 +416,7 @@ def run_hierarchy(args):
                    "seed": args.seed, "vertices": g.n_vertices, "hyperedges": g.n_edges,
                    "pins": g.n_pins},
         "contractions": n_contract,
+        "finished": finished,
         "levels_per_s": len(rows) / t_total,
         "hierarchy_s": t_total,
         "final_parts": rows[-1]["V"],
@@ -683,6 +690,9 @@ def main():
     ap.add_argument("--start-level", type=int, default=0,
                     help="level mode: time this level of the hierarchy (the levels before it "
                          "are coarsened first, untimed)")
+    ap.add_argument("--time-limit", type=float, default=0.0,
+                    help="hierarchy mode: stop after this many seconds and report the levels "
+                         "done (0: run to the stop rule)")
     ap.add_argument("--rounds", type=int, default=16,
                     help="partition mode: refinement rounds per level at most")
     ap.add_argument("--mode", default="level",
