@@ -276,8 +276,8 @@ int hg_refine(hg_ctx* ctx, const hg_level* lvl, int32_t* part, int32_t n_parts,
  * that forbid allocation in their loop).  Same arguments, result and checks
  * as hg_connectivity; its kernels use a fixed device array of the library
  * (64 MiB per GPU, held until the process ends) instead of the context's
- * arena.  A level needing more than that (about 12 bytes per vertex plus 12
- * per hyperedge, e.g. 2.7M of each) fails with HG_ERR_CAPACITY before any
+ * arena.  A level needing more than that (about 12 bytes per vertex plus 16
+ * per hyperedge, e.g. 2.3M of each) fails with HG_ERR_CAPACITY before any
  * work.  All calls on one GPU share the array: calls that overlap on one GPU
  * (other streams or host threads) race, and the caller must serialise them.
  * With HG_VALIDATE=1 the level check also uses the fixed array.

@@ -329,7 +329,7 @@ int hg_coarsen_level(hg_ctx* c, const hg_level* in, const hg_limits* lim, int32_
   weight_check_kernel<<<grid_for(E, 256 * 8, 1024), 256, 0, s>>>(S.dims, in->edge_weight,
                                                                   c->dev_wsum, c->dev_err);
   weight_sum_kernel<<<1, 1, 0, s>>>(c->dev_wsum, c->dev_err);
-  build_incidence(L, V, E, P, S.vcount, S.voff, S.vinc, S.partials, s);
+  build_incidence(L, V, E, P, S.vcount, S.voff, S.vinc, S.partials, s, S.inc);
   Buckets b{S.bcount, S.blist, S.bvisits};
   expansion_and_buckets(L, S.voff, S.vinc, V, S.xn, S.gc, 1, b, c->tuning, s, S.n_win14);
   census_kernel<<<1, 64, 0, s>>>(S.bcount, S.bvisits, c->dev_census);

@@ -430,7 +430,7 @@ void level_step(hg_batch* b, int from, int to) {
   const int64_t V = b->capV, E = b->capE, P = b->capP;
   auto& S = b->cs;
   LevelView L{F.dims, F.eoff, F.pins, F.w, F.mult, F.size, F.syn, F.ax, F.gid};
-  build_incidence(L, V, E, P, S.vcount, S.voff, S.vinc, S.partials, s);
+  build_incidence(L, V, E, P, S.vcount, S.voff, S.vinc, S.partials, s, S.inc);
   Buckets bk{S.bcount, S.blist, S.bvisits};
   expansion_and_buckets(L, S.voff, S.vinc, V, S.xn, b->gc, b->max_graphs, bk, c->tuning, s);
   ScoreArgs sa{L,  S.voff, S.vinc, S.xn,      b->gc, S.cursor,         b->cand,

@@ -1,9 +1,11 @@
 // S8: connectivity (paper, Section 3, Eq. 1):
 //   Conn = sum over hyperedges e of w(e) * (lambda(e) - 1),
 //   lambda(e) = number of distinct part[v] over the pins v of e.
-// Three size classes: a wave with one pin per lane sorts the block ids by
+// Four size classes: a wave with one pin per lane sorts the block ids by
 // shuffles (<= 64 pins); a work-group counts distinct ids in an LDS hash set
-// (<= 16384 pins); larger hyperedges use a bitmap over the block-id range.
+// of 4096 slots (<= 2048 pins, many work-groups per CU to hide the latency
+// of the part lookups) or of 32768 slots (<= 16384 pins); larger hyperedges
+// use a bitmap over the block-id range.
 // Sums are int64 and combined with integer atomics, so the result does not
 // depend on scheduling.
 #include "hg_internal.h"
@@ -13,9 +15,9 @@ namespace hg {
 namespace {
 
 constexpr int kSmallMax = 64;
+constexpr int kMediumMax = 2048;
 constexpr int kBlockMax = 16384;
 constexpr int kThreads = 256;
-constexpr int kSetSlots = 2 * kBlockMax;
 constexpr uint32_t kEmptySlot = 0xFFFFFFFFu;
 
 __global__ void conn_classify_kernel(const Dims* __restrict__ d, const int64_t* __restrict__ eoff,
@@ -34,9 +36,9 @@ __global__ void conn_classify_kernel(const Dims* __restrict__ d, const int64_t* 
     if (i < E) {
       const int64_t s = eoff[i + 1] - eoff[i];
       // lambda <= 1 contributes nothing
-      if (s >= 2) b = s <= kSmallMax ? 0 : (s <= kBlockMax ? 1 : 2);
+      if (s >= 2) b = s <= kSmallMax ? 0 : (s <= kMediumMax ? 1 : (s <= kBlockMax ? 2 : 3));
     }
-    const int32_t pos = wave_bucket_slot<3>(b, count);
+    const int32_t pos = wave_bucket_slot<4>(b, count);
     if (b >= 0) list[(int64_t)b * maxE + pos] = (int32_t)i;
   }
 }
@@ -87,22 +89,24 @@ __global__ void conn_small_kernel(ConnArgs a) {
   if (lane == 0 && acc) atomicAdd((unsigned long long*)a.conn, (unsigned long long)acc);
 }
 
+// Hyperedges of class CLS (at most SLOTS / 2 pins): one work-group each.
+template <int SLOTS, int CLS>
 __global__ __launch_bounds__(kThreads) void conn_block_kernel(ConnArgs a) {
-  __shared__ uint32_t set[kSetSlots];
+  __shared__ uint32_t set[SLOTS];
   __shared__ int32_t s_item;
   __shared__ int32_t s_new;
   const int tid = threadIdx.x;
-  int32_t cnt = a.count[1];
+  int32_t cnt = a.count[CLS];
   if (cnt > a.max_items) {
     if (tid == 0) atomicOr(a.err, kErrWorkCount);
     cnt = (int32_t)a.max_items;
   }
-  for (int i = tid; i < kSetSlots; i += kThreads) set[i] = kEmptySlot;
+  for (int i = tid; i < SLOTS; i += kThreads) set[i] = kEmptySlot;
   int64_t acc = 0;
   while (true) {
     __syncthreads();
     if (tid == 0) {
-      s_item = atomicAdd(&a.work[1], 1);
+      s_item = atomicAdd(&a.work[CLS], 1);
       s_new = 0;
     }
     __syncthreads();
@@ -111,7 +115,7 @@ __global__ __launch_bounds__(kThreads) void conn_block_kernel(ConnArgs a) {
     const int64_t e = a.list[item];
     const int64_t s0 = a.L.eoff[e], s1 = a.L.eoff[e + 1];
     uint32_t cap = 128;
-    while (cap < 2 * (uint64_t)(s1 - s0) && cap < (uint32_t)kSetSlots) cap <<= 1;
+    while (cap < 2 * (uint64_t)(s1 - s0) && cap < (uint32_t)SLOTS) cap <<= 1;
     const uint32_t mask = cap - 1;
     int mine = 0;
     for (int64_t k = s0 + tid; k < s1; k += kThreads) {
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(kThreads) void conn_huge_kernel(ConnArgs a) {
   __shared__ int32_t s_item;
   __shared__ int32_t s_new;
   const int tid = threadIdx.x;
-  int32_t cnt = a.count[2];
+  int32_t cnt = a.count[3];
   if (cnt > a.max_items) {
     if (tid == 0) atomicOr(a.err, kErrWorkCount);
     cnt = (int32_t)a.max_items;
@@ -152,7 +156,7 @@ __global__ __launch_bounds__(kThreads) void conn_huge_kernel(ConnArgs a) {
   while (true) {
     __syncthreads();
     if (tid == 0) {
-      s_item = atomicAdd(&a.work[2], 1);
+      s_item = atomicAdd(&a.work[3], 1);
       s_new = 0;
     }
     __syncthreads();
@@ -190,8 +194,10 @@ void connectivity(const LevelView& L, int64_t maxE, int64_t part_range, const in
              (part_range + 31) / 32, cs.err, maxE};
   conn_small_kernel<<<grid_for(maxE, 4, 16384), 256, 0, s>>>(a);
   a.list = cs.ebucket + maxE;
-  conn_block_kernel<<<device_cu_count(), kThreads, 0, s>>>(a);
+  conn_block_kernel<2 * kMediumMax, 1><<<device_cu_count() * 8, kThreads, 0, s>>>(a);
   a.list = cs.ebucket + 2 * maxE;
+  conn_block_kernel<2 * kBlockMax, 2><<<device_cu_count(), kThreads, 0, s>>>(a);
+  a.list = cs.ebucket + 3 * maxE;
   conn_huge_kernel<<<kHugeWG, kThreads, 0, s>>>(a);
 }
 

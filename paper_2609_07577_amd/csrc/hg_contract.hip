@@ -28,6 +28,7 @@ namespace hg {
 namespace {
 
 constexpr int kSmallMax = 64;
+constexpr int kMediumMax = 2048;
 constexpr int kBlockMax = 16384;
 constexpr int kBlockThreads = 256;
 constexpr uint32_t kPad = 0xFFFFFFFFu;
@@ -97,9 +98,9 @@ __global__ void classify_edges_kernel(const Dims* __restrict__ d, const int64_t*
     int b = -1;
     if (i < E) {
       const int64_t s = eoff[i + 1] - eoff[i];
-      b = s <= kSmallMax ? 0 : (s <= kBlockMax ? 1 : 2);
+      b = s <= kSmallMax ? 0 : (s <= kMediumMax ? 1 : (s <= kBlockMax ? 2 : 3));
     }
-    const int32_t pos = wave_bucket_slot<3>(b, count);
+    const int32_t pos = wave_bucket_slot<4>(b, count);
     if (b >= 0) list[(int64_t)b * maxE + pos] = (int32_t)i;
   }
 }
@@ -210,21 +211,24 @@ __device__ inline uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
   return r;
 }
 
-// 65..16384 pins: one work-group, bitonic sort in LDS.
+// Hyperedges of class CLS (at most MAXN pins): one work-group, bitonic sort
+// in LDS (the medium class keeps its keys small enough for many work-groups
+// per CU, which hide the latency of the vertex-map lookups).
+template <int MAXN, int CLS>
 __global__ __launch_bounds__(kBlockThreads) void s6_block_kernel(S6Args a) {
-  __shared__ uint32_t keys[kBlockMax];
+  __shared__ uint32_t keys[MAXN];
   __shared__ int32_t wsum[kBlockThreads / kWave];
   __shared__ uint64_t red[kBlockThreads / kWave];
   __shared__ int32_t s_item;
   const int tid = threadIdx.x;
-  int32_t cnt = a.count[1];
+  int32_t cnt = a.count[CLS];
   if (cnt > a.max_items) {
     if (tid == 0) atomicOr(a.err, kErrWorkCount);
     cnt = (int32_t)a.max_items;
   }
   while (true) {
     __syncthreads();
-    if (tid == 0) s_item = atomicAdd(&a.work[1], 1);
+    if (tid == 0) s_item = atomicAdd(&a.work[CLS], 1);
     __syncthreads();
     const int32_t item = s_item;
     if (item >= cnt) break;
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(kBlockThreads) void s6_block_kernel(S6Args a) {
     const int64_t s0 = a.L.eoff[e];
     const int len = (int)(a.L.eoff[e + 1] - s0);
     int N = 128;
-    while (N < len && N < kBlockMax) N <<= 1;
+    while (N < len && N < MAXN) N <<= 1;
     for (int i = tid; i < N; i += kBlockThreads) {
       uint32_t key = kPad;
       if (i < len) {
@@ -289,7 +293,7 @@ __global__ __launch_bounds__(kBlockThreads) void s6_huge_kernel(S6Args a) {
   __shared__ uint64_t red[kBlockThreads / kWave];
   __shared__ int32_t s_item;
   const int tid = threadIdx.x;
-  int32_t cnt = a.count[2];
+  int32_t cnt = a.count[3];
   if (cnt > a.max_items) {
     if (tid == 0) atomicOr(a.err, kErrWorkCount);
     cnt = (int32_t)a.max_items;
@@ -303,7 +307,7 @@ __global__ __launch_bounds__(kBlockThreads) void s6_huge_kernel(S6Args a) {
   }
   while (true) {
     __syncthreads();
-    if (tid == 0) s_item = atomicAdd(&a.work[2], 1);
+    if (tid == 0) s_item = atomicAdd(&a.work[3], 1);
     __syncthreads();
     const int32_t item = s_item;
     if (item >= cnt) break;
@@ -550,8 +554,10 @@ int contract_level(const LevelView& L, int64_t maxV, int64_t maxE, int64_t maxP,
   a6.count = cs.ecount;
   s6_small_kernel<<<gridEw, 256, 0, s>>>(a6);
   a6.list = cs.ebucket + maxE;
-  s6_block_kernel<<<device_cu_count() * 4, kBlockThreads, 0, s>>>(a6);
+  s6_block_kernel<kMediumMax, 1><<<device_cu_count() * 8, kBlockThreads, 0, s>>>(a6);
   a6.list = cs.ebucket + 2 * maxE;
+  s6_block_kernel<kBlockMax, 2><<<device_cu_count() * 2, kBlockThreads, 0, s>>>(a6);
+  a6.list = cs.ebucket + 3 * maxE;
   s6_huge_kernel<<<kHugeWG, kBlockThreads, 0, s>>>(a6);
 
   // S7

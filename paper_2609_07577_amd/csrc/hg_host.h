@@ -156,6 +156,7 @@ struct CoarsenScratch {
   int32_t n_win;
   uint32_t* splits14;
   int32_t n_win14;
+  IncScratch inc;  // its pairs alias `cursor`, which the score step uses later
   void carve(A& a, int64_t V, int64_t E, int64_t P) {
     dims = a.template take<Dims>(1);
     gc = a.template take<GraphConst>(1);
@@ -168,6 +169,7 @@ struct CoarsenScratch {
     bvisits = a.template take<int64_t>(kNumBuckets);
     work = a.template take<int32_t>(kNumBuckets);
     cursor = a.template take<int32_t>(2 * P);
+    inc = incidence_scratch_carve(a, V, reinterpret_cast<uint64_t*>(cursor));
     cand = a.template take<int32_t>(V);
     cscore = a.template take<int32_t>(V);
     bkey = a.template take<uint64_t>(V);
@@ -202,7 +204,7 @@ struct ContractLayout {
     cs.tpin = a.template take<uint32_t>(P);
     cs.tlen = a.template take<int32_t>(E);
     cs.fp = a.template take<uint64_t>(E);
-    cs.ebucket = a.template take<int32_t>(3 * E);
+    cs.ebucket = a.template take<int32_t>(4 * E);
     cs.ecount = a.template take<int32_t>(8);
     cs.work = a.template take<int32_t>(4);
     cs.htab_cap = pow2_at_least(2 * E);
@@ -227,7 +229,7 @@ struct ConnLayout {
   ConnScratch cs;
   void carve(A& a, int64_t V, int64_t E) {
     dims = a.template take<Dims>(1);
-    cs.ebucket = a.template take<int32_t>(3 * E);
+    cs.ebucket = a.template take<int32_t>(4 * E);
     cs.ecount = a.template take<int32_t>(4);
     cs.work = a.template take<int32_t>(4);
     cs.bitmap_words = (V + 31) / 32 + 1;

@@ -117,9 +117,40 @@ void exclusive_scan_i64(const int64_t* in, int64_t* out, const int64_t* count,
 
 // ---- S0/S1 (hg_transpose.hip) ----------------------------------------------
 // Incidence lists: voff [V+1], vinc [P] = edge | flag << 31.
+//
+// Levels of at most kIncBuckets * 2^kIncBits vertices are transposed without
+// global atomics, in buckets of 2^kIncBits consecutive vertices: per-work-
+// group bucket counts of an even share of the pins, one scan, a scatter of
+// (vertex, entry) pairs into the buckets, then one work-group per bucket
+// counting, scanning and placing its vertices' entries in LDS.  That needs
+// an IncScratch (carve it with incidence_scratch_carve); without one, or on
+// larger levels, the lists are built with global atomic counters.
+constexpr int kIncBits = 13;
+constexpr int kIncBuckets = 4096;
+constexpr int kIncBlocks = 1024;
+struct IncScratch {
+  uint64_t* pairs = nullptr;  // [P] (vertex << 32 | entry); may alias other scratch
+  int64_t* boff = nullptr;    // [kIncBuckets' * kIncBlocks + 1]
+  int32_t* bcnt = nullptr;    // [buckets * kIncBlocks]
+  int64_t* n = nullptr;       // [1]
+};
+inline int64_t incidence_buckets(int64_t maxV) {
+  return (maxV + (1ll << kIncBits) - 1) >> kIncBits;
+}
+template <typename A>
+IncScratch incidence_scratch_carve(A& a, int64_t maxV, uint64_t* pairs) {
+  IncScratch s;
+  const int64_t nb = incidence_buckets(maxV);
+  if (nb < 1 || nb > kIncBuckets) return s;
+  s.pairs = pairs;
+  s.boff = a.template take<int64_t>(nb * kIncBlocks + 1);
+  s.bcnt = a.template take<int32_t>(nb * kIncBlocks);
+  s.n = a.template take<int64_t>(1);
+  return s;
+}
 void build_incidence(const LevelView& L, int64_t maxV, int64_t maxE, int64_t maxP,
                      int32_t* vcount, int64_t* voff, uint32_t* vinc, int64_t* partials,
-                     hipStream_t s);
+                     hipStream_t s, const IncScratch& inc = IncScratch());
 void level0_state(const Dims* d, const int64_t* eoff, const uint32_t* pins, int64_t maxV,
                   int64_t maxE, int32_t* size, int32_t* syn, int32_t* ax, int32_t* mult,
                   hipStream_t s);
@@ -205,7 +236,7 @@ struct ContractScratch {
   uint32_t* tpin;       // [P]
   int32_t* tlen;        // [E]
   uint64_t* fp;         // [E]
-  int32_t* ebucket;     // [3 * E] size-bucket lists
+  int32_t* ebucket;     // [4 * E] size-bucket lists
   int32_t* ecount;      // [4] counters
   int32_t* work;        // [4] work counters
   uint64_t* htab_key;   // [T]
@@ -231,7 +262,7 @@ int contract_level(const LevelView& L, int64_t maxV, int64_t maxE, int64_t maxP,
 
 // ---- S8 (hg_conn.hip) -----------------------------------------------------
 struct ConnScratch {
-  int32_t* ebucket;     // [3 * E]
+  int32_t* ebucket;     // [4 * E]
   int32_t* ecount;      // [4]
   int32_t* work;        // [4]
   uint32_t* bitmap;

@@ -59,7 +59,7 @@ int hg_connectivity_static(hg_ctx* c, const hg_level* lvl, const int32_t* part, 
   if (need > kStaticScratchBytes)
     return fail(c, HG_ERR_CAPACITY,
                 "hg_connectivity_static: the level needs %zu bytes of scratch, above the fixed "
-                "maximum of %zu (12 bytes per vertex and per hyperedge); use hg_connectivity",
+                "maximum of %zu (12 bytes per vertex and 16 per hyperedge); use hg_connectivity",
                 need, kStaticScratchBytes);
   char* base = nullptr;
   {

@@ -1,6 +1,8 @@
-// S0: incidence lists I(n) (paper, Section 2: in(n) U out(n)) by counting
-// and atomic scatter; order inside a list is not fixed and does not matter
-// to any result (all later uses are integer sums or set tests).
+// S0: incidence lists I(n) (paper, Section 2: in(n) U out(n)); order inside a
+// list is not fixed and does not matter to any result (all later uses are
+// integer sums or set tests).  Levels of up to 2^25 vertices are transposed
+// through buckets of 8192 consecutive vertices with LDS counters only;
+// larger ones by global atomic counters.
 // S1: expansion sizes X_n = sum over I(n) of |e|, level maxima of the
 // super-node state, and the work lists of the scoring kernels.
 // Level-0 state (Section 2 model; Section 3 constraint quantities).
@@ -37,6 +39,137 @@ __global__ void scatter_incidence_kernel(const Dims* __restrict__ d,
       int32_t pos = atomicAdd(&cursor[v], 1);
       vinc[voff[v] + pos] = (uint32_t)e | (p & kDst);
     }
+  }
+}
+
+// ---- bucketed transpose --------------------------------------------------
+// Work-group g takes the pins [P g / G, P (g + 1) / G).
+
+__device__ inline void pin_share(int64_t P, int64_t& p0, int64_t& p1) {
+  p0 = P * (int64_t)blockIdx.x / gridDim.x;
+  p1 = P * (int64_t)(blockIdx.x + 1) / gridDim.x;
+}
+
+// Pins of the work-group's share per bucket: bcnt[b * G + g].
+__global__ __launch_bounds__(256) void inc_count_kernel(const Dims* __restrict__ d,
+                                                        const uint32_t* __restrict__ pins,
+                                                        int32_t* __restrict__ bcnt,
+                                                        int64_t* __restrict__ n_out) {
+  __shared__ int32_t h[kIncBuckets];
+  const int64_t V = d->V, P = d->P;
+  const int32_t nb = (int32_t)((V + (1 << kIncBits) - 1) >> kIncBits);
+  for (int32_t i = threadIdx.x; i < nb; i += 256) h[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = (int64_t)nb * gridDim.x;
+  __syncthreads();
+  int64_t p0, p1;
+  pin_share(P, p0, p1);
+  for (int64_t k = p0 + threadIdx.x; k < p1; k += 256)
+    atomicAdd(&h[(pins[k] & kIdMask) >> kIncBits], 1);
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i < nb; i += 256)
+    bcnt[(int64_t)i * gridDim.x + blockIdx.x] = h[i];
+}
+
+// The work-group's pins as (vertex << 32 | edge | flag) pairs at its slots of
+// each bucket (boff = exclusive scan of bcnt, bucket-major).  Waves walk the
+// hyperedges that meet the share, from the one holding its first pin.
+__global__ __launch_bounds__(256) void inc_scatter_kernel(const Dims* __restrict__ d,
+                                                          const int64_t* __restrict__ eoff,
+                                                          const uint32_t* __restrict__ pins,
+                                                          const int64_t* __restrict__ boff,
+                                                          uint64_t* __restrict__ pairs) {
+  __shared__ int32_t cur[kIncBuckets];
+  __shared__ int64_t s_e0;
+  const int64_t V = d->V, E = d->E, P = d->P;
+  const int32_t nb = (int32_t)((V + (1 << kIncBits) - 1) >> kIncBits);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  constexpr int NW = 256 / kWave;
+  for (int32_t i = threadIdx.x; i < nb; i += 256) cur[i] = 0;
+  int64_t p0, p1;
+  pin_share(P, p0, p1);
+  if (threadIdx.x == 0) {
+    // the last hyperedge starting at or before p0 (eoff[0] = 0 <= p0)
+    int64_t lo = 0, hi = E;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (eoff[mid] <= p0) lo = mid;
+      else hi = mid - 1;
+    }
+    s_e0 = lo;
+  }
+  __syncthreads();
+  if (p0 >= p1) return;  // block-uniform, after the last barrier
+  const int64_t G = gridDim.x;
+  for (int64_t e = s_e0 + wid; e < E; e += NW) {
+    const int64_t a0 = eoff[e], a1 = eoff[e + 1];
+    if (a0 >= p1) break;  // wave-uniform
+    const int64_t lo = a0 > p0 ? a0 : p0, hi = a1 < p1 ? a1 : p1;
+    for (int64_t k = lo + lane; k < hi; k += kWave) {
+      const uint32_t p = pins[k];
+      const uint32_t v = p & kIdMask;
+      const int32_t b = (int32_t)(v >> kIncBits);
+      const int32_t at = atomicAdd(&cur[b], 1);
+      pairs[boff[(int64_t)b * G + blockIdx.x] + at] =
+          ((uint64_t)v << 32) | (uint64_t)((uint32_t)e | (p & kDst));
+    }
+  }
+}
+
+// One work-group per bucket: its vertices' list lengths (LDS counters), their
+// offsets (bucket start + an LDS scan) into voff, and the entries placed.
+__global__ __launch_bounds__(1024) void inc_finish_kernel(const Dims* __restrict__ d,
+                                                          const int64_t* __restrict__ boff,
+                                                          int32_t G,
+                                                          const uint64_t* __restrict__ pairs,
+                                                          int64_t* __restrict__ voff,
+                                                          uint32_t* __restrict__ vinc) {
+  constexpr int kIds = 1 << kIncBits;
+  constexpr int kPer = kIds / 1024;
+  __shared__ int32_t cnt[kIds];
+  __shared__ int32_t ws[1024 / kWave];
+  const int64_t V = d->V, P = d->P;
+  const int32_t nb = (int32_t)((V + kIds - 1) >> kIncBits);
+  const int32_t b = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  if (b == 0 && tid == 0) voff[V] = P;
+  if (b >= nb) return;  // block-uniform, before any barrier
+  const int64_t start = boff[(int64_t)b * G];
+  const int64_t end = b + 1 < nb ? boff[(int64_t)(b + 1) * G] : P;
+  const int64_t base = (int64_t)b << kIncBits;
+  for (int i = tid; i < kIds; i += 1024) cnt[i] = 0;
+  __syncthreads();
+  for (int64_t k = start + tid; k < end; k += 1024)
+    atomicAdd(&cnt[(int32_t)((pairs[k] >> 32) - base)], 1);
+  __syncthreads();
+  // exclusive scan: thread t owns ids [kPer t, kPer t + kPer)
+  int32_t loc[kPer], sum = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    loc[i] = sum;
+    sum += cnt[kPer * tid + i];
+  }
+  int32_t inc = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) ws[wid] = inc;
+  __syncthreads();
+  int32_t before = 0;
+  for (int w = 0; w < wid; ++w) before += ws[w];
+  const int32_t first = before + inc - sum;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int64_t v = base + kPer * tid + i;
+    cnt[kPer * tid + i] = first + loc[i];
+    if (v < V) voff[v] = start + first + loc[i];
+  }
+  __syncthreads();
+  for (int64_t k = start + tid; k < end; k += 1024) {
+    const uint64_t pr = pairs[k];
+    const int32_t at = atomicAdd(&cnt[(int32_t)((pr >> 32) - base)], 1);
+    vinc[start + at] = (uint32_t)pr;
   }
 }
 
@@ -185,7 +318,16 @@ __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
 
 void build_incidence(const LevelView& L, int64_t maxV, int64_t maxE, int64_t maxP,
                      int32_t* vcount, int64_t* voff, uint32_t* vinc, int64_t* partials,
-                     hipStream_t s) {
+                     hipStream_t s, const IncScratch& inc) {
+  const int64_t nb = incidence_buckets(maxV);
+  if (inc.pairs && inc.boff && nb >= 1 && nb <= kIncBuckets) {
+    inc_count_kernel<<<kIncBlocks, 256, 0, s>>>(L.dims, L.pins, inc.bcnt, inc.n);
+    exclusive_scan_i32(inc.bcnt, inc.boff, inc.n, nb * kIncBlocks, partials, s);
+    inc_scatter_kernel<<<kIncBlocks, 256, 0, s>>>(L.dims, L.eoff, L.pins, inc.boff, inc.pairs);
+    inc_finish_kernel<<<(int)nb, 1024, 0, s>>>(L.dims, inc.boff, kIncBlocks, inc.pairs, voff,
+                                               vinc);
+    return;
+  }
   fill_i32(vcount, 0, maxV, s);
   count_pins_kernel<<<grid_for(maxP, 256 * 8, 8192), 256, 0, s>>>(L.dims, L.pins, vcount);
   exclusive_scan_i32(vcount, voff, &L.dims->V, maxV, partials, s);
