@@ -216,9 +216,10 @@ def run_batch(args):
     (b) whole hierarchies of two size-scaled copies of the distribution
     (neurons in [1k, 20k) with the full fan-out range, and [500, 5000) with
     fan-out 8..32), batched with the level step replayed from a HIP graph vs
-    plain level-by-level runs, with every partition compared.  Whole
-    hierarchies at full size are out of reach of one run: a graph of the mix
-    needs 100-260 contractions, each costing about as much as its level 0."""
+    plain level-by-level runs, with every partition compared; (c) with
+    --full-hier-graphs N, the same for N graphs of the mix at full size (a
+    graph needs 100-260 contractions, so the whole batch of 256 is out of
+    reach of one run)."""
     import torch
     from paper_2609_07577_amd import hg, hierarchy, synth, tune
 
@@ -227,8 +228,13 @@ def run_batch(args):
     # ---- (a) full size, one level -------------------------------------------
     t0 = time.perf_counter()
     levels = []
+    X_total = 0
+    bytes_level = 0
     for k in range(args.graphs):
         g = synth.batch_graph(args.seed, k)
+        xg = int(expansion_stats(g))
+        X_total += xg
+        bytes_level += level_bytes(g.n_vertices, g.n_edges, g.n_pins, xg)
         levels.append(ctx.upload(g))
         if k % 32 == 31:
             ctx.sync()
@@ -320,6 +326,12 @@ def run_batch(args):
 
     hier_mid = hierarchies("mid", 1000, 20000, 16, 256, args.seed + 1000)
     hier_small = hierarchies("small", 500, 5000, 8, 32, args.seed + 1100)
+    hier_full = None
+    if args.full_hier_graphs:
+        saved = args.hier_graphs
+        args.hier_graphs = args.full_hier_graphs
+        hier_full = hierarchies("full", 10000, 500000, 16, 256, args.seed + 1200)
+        args.hier_graphs = saved
     result = {
         "metric": METRIC,
         "value": P / t_batch,
@@ -341,9 +353,14 @@ def run_batch(args):
                    "unions": len(groups)},
         "plain_pins_per_s": P / t_plain,
         "batched_vs_plain": t_plain / t_batch,
+        "neighbour_visits": X_total,
+        "level_algorithmic_bytes": bytes_level,
+        "level_hbm_frac_batched": bytes_level / t_batch / 1e9 / HBM_PEAK_GBS,
+        "level_hbm_frac_plain": bytes_level / t_plain / 1e9 / HBM_PEAK_GBS,
         "tuning": {k: tuned[k] for k in ("single_pass_load16", "pass_fill16", "dense_ratio")},
         "hierarchies_mid": hier_mid,
         "hierarchies_small": hier_small,
+        "hierarchies_full_size": hier_full,
     }
     ctx.sync()
     print(json.dumps(result), flush=True)
@@ -572,7 +589,10 @@ def run_serve(args):
     seconds.  A request is one SNN hypergraph to coarsen to the end, drawn
     from a pool of 1024 graphs of the batch mix scaled down to neurons in
     [500, 5000) and fan-out 8..32 (98%) plus 2% such graphs of 20,000
-    neurons, all resident on the device.  (A request of the full-size mix
+    neurons, all resident on the device; with --mix full, from 64 graphs of
+    the full-size mix (neurons in [10k, 500k), fan-out 16..256) plus 2%
+    graphs of 2,000,000 neurons, served until --serve-wall seconds at most,
+    the backlog then reported.  (A request of the full-size mix
     costs 0.3-40 GPU-seconds, so a 200/s stream of them cannot be served by
     one GPU; the scaled mix keeps the offered load below capacity.)  Requests are admitted by footprint into one
     batch (continuous batching) and stepped 4 levels per union step from a
@@ -585,13 +605,22 @@ def run_serve(args):
     ctx = hg.Context(0)
     rng = np.random.default_rng(args.seed)
     pool, lims = [], []
-    for k in range(1024):
-        g = synth.batch_graph(args.seed + 2000, k, n_min=500, n_max=5000, fan_min=8, fan_max=32)
+    full = args.mix == "full"
+    n_small, n_big = (64, 2) if full else (1024, 8)
+    for k in range(n_small):
+        if full:
+            g = synth.batch_graph(args.seed + 2000, k)
+        else:
+            g = synth.batch_graph(args.seed + 2000, k, n_min=500, n_max=5000, fan_min=8,
+                                  fan_max=32)
         pool.append(ctx.upload(g))
         lims.append(synth.LIMITS["batch"])
-    for k in range(8):
-        g = synth.batch_graph(args.seed + 3000, k, n_min=20000, n_max=20001, fan_min=8,
-                              fan_max=32)
+    for k in range(n_big):
+        if full:
+            g = synth.batch_graph(args.seed + 3000, k, n_min=2_000_000, n_max=2_000_001)
+        else:
+            g = synth.batch_graph(args.seed + 3000, k, n_min=20000, n_max=20001, fan_min=8,
+                                  fan_max=32)
         pool.append(ctx.upload(g))
         lims.append(synth.LIMITS["batch"])
     ctx.sync()
@@ -599,9 +628,14 @@ def run_serve(args):
     n_req = int(rng.poisson(args.rate * args.duration))
     arrivals = np.sort(rng.uniform(0.0, args.duration, n_req))
     big = rng.random(n_req) < 0.02
-    which = np.where(big, 1024 + rng.integers(0, 8, n_req), rng.integers(0, 1024, n_req))
-    srv = serve.Server(ctx, max_graphs=1024, cap_vertices=2_000_000, cap_edges=2_000_000,
-                       cap_pins=64_000_000, levels_per_step=4, use_graph=True)
+    which = np.where(big, n_small + rng.integers(0, n_big, n_req),
+                     rng.integers(0, n_small, n_req))
+    if full:
+        srv = serve.Server(ctx, max_graphs=256, cap_vertices=4_000_000, cap_edges=4_000_000,
+                           cap_pins=640_000_000, levels_per_step=4, use_graph=True)
+    else:
+        srv = serve.Server(ctx, max_graphs=1024, cap_vertices=2_000_000, cap_edges=2_000_000,
+                           cap_pins=64_000_000, levels_per_step=4, use_graph=True)
     # warm-up: capture and first launches
     srv.submit(-1, pool[0], lims[0], time.perf_counter())
     while not srv.idle():
@@ -612,8 +646,14 @@ def run_serve(args):
     t0 = time.perf_counter()
     nxt = 0
     last_log = t0
+    stopped = False
     while nxt < n_req or not srv.idle():
         now = time.perf_counter() - t0
+        if args.serve_wall and now > args.serve_wall:
+            stopped = True
+            _log(f"wall limit: {len(lat)} served, {n_req - nxt} not yet arrived, "
+                 f"{len(srv.queue)} queued, {len(srv.running)} running")
+            break
         while nxt < n_req and arrivals[nxt] <= now:
             srv.submit(nxt, pool[which[nxt]], lims[which[nxt]], t0 + arrivals[nxt])
             nxt += 1
@@ -629,6 +669,8 @@ def run_serve(args):
             _log(f"t={last_log - t0:.0f} s: {len(lat)} served, {len(srv.queue)} queued, "
                  f"{len(srv.running)} running")
     wall = time.perf_counter() - t0
+    backlog = {"not_arrived": int(n_req - nxt), "queued": len(srv.queue),
+               "running": len(srv.running)}
     ctx.sync()
     # the same graphs alone, plain
     equal = True
@@ -637,8 +679,11 @@ def run_serve(args):
         vmaps, nlev, last = hierarchy.plain_hierarchy(ctx, L, lims[which[rid]])
         ref = hierarchy.compose(vmaps, L.V, ctx.device)
         equal &= bool(torch.equal(ref, part)) and nlev == n_levels and last.V == n_parts
-    # plain service capacity on a sample of the stream
-    sample = [int(x) for x in rng.choice(n_req, size=min(24, n_req), replace=False)]
+    # plain service capacity on a sample of the stream (small requests only
+    # for the full mix: one 2M-neuron request alone takes minutes)
+    cand = np.flatnonzero(~big) if full else np.arange(n_req)
+    sample = [int(x) for x in rng.choice(cand, size=min(24 if not full else 8, len(cand)),
+                                         replace=False)]
     ctx.sync()
     t1 = time.perf_counter()
     for r in sample:
@@ -661,19 +706,27 @@ def run_serve(args):
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": ("served mapping requests, Poisson %.0f/s for %.0f s: 98%% batch-mix "
-                                "graphs with neurons log-uniform in [500, 5000) and fan-out "
-                                "U{8..32}, 2%% such graphs of 20,000 neurons; limits "
-                                "512/32768/2048; each coarsened to the end"
-                                % (args.rate, args.duration)),
+        "config": {"workload": (("served mapping requests, Poisson %g/s for %.0f s: 98%% "
+                                 "batch-mix graphs with neurons log-uniform in [10k, 500k) and "
+                                 "fan-out U{16..256}, 2%% such graphs of 2,000,000 neurons; "
+                                 "limits 512/32768/2048; each coarsened to the end"
+                                 % (args.rate, args.duration)) if full else
+                                ("served mapping requests, Poisson %g/s for %.0f s: 98%% "
+                                 "batch-mix graphs with neurons log-uniform in [500, 5000) and "
+                                 "fan-out U{8..32}, 2%% such graphs of 20,000 neurons; limits "
+                                 "512/32768/2048; each coarsened to the end"
+                                 % (args.rate, args.duration))),
                    "requests": n_req, "seed": args.seed, "batch_bytes": batch_bytes},
-        "p50_ms": float(np.percentile(lat_ms, 50)),
-        "p99_ms": float(np.percentile(lat_ms, 99)),
+        "p50_ms": float(np.percentile(lat_ms, 50)) if len(lat_ms) else None,
+        "p99_ms": float(np.percentile(lat_ms, 99)) if len(lat_ms) else None,
         "served_per_s": len(lat) / wall,
         "plain_mean_service_ms": 1000.0 * t_plain_req,
         "plain_capacity_per_s": 1.0 / t_plain_req,
         "served_equal_to_alone": equal,
         "checked": len(served),
+        "stopped_at_wall_limit": stopped,
+        "backlog_at_end": backlog,
+        "big_requests": int(big.sum()),
     }
     print(json.dumps(result), flush=True)
 
@@ -713,7 +766,16 @@ def main():
     ap.add_argument("--graphs", type=int, default=256, help="batch mode: graphs at full size")
     ap.add_argument("--hier-graphs", type=int, default=64,
                     help="batch mode: graphs of the size-scaled full-hierarchy comparison")
+    ap.add_argument("--full-hier-graphs", type=int, default=0,
+                    help="batch mode: graphs of the mix at full size coarsened to the end, "
+                         "batched vs plain (0: skipped)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve mode: requests per second")
+    ap.add_argument("--mix", default="scaled", choices=("scaled", "full"),
+                    help="serve mode: request sizes (scaled-down mix, or the full-size mix "
+                         "with 2%% of 2M-neuron graphs)")
+    ap.add_argument("--serve-wall", type=float, default=0.0,
+                    help="serve mode: stop serving after this many seconds and report the "
+                         "backlog (0: serve every request)")
     ap.add_argument("--duration", type=float, default=60.0, help="serve mode: seconds of arrivals")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times), the "
