@@ -50,24 +50,10 @@ __device__ inline T wave_sum(T v) {
 }
 
 // ---------------------------------------------------------------------------
-// Fine-level pass: per-vertex sum of mult over hyperedges where the vertex
-// holds the destination flag.  One wave per hyperedge.
-__global__ void dstmult_kernel(const Dims* __restrict__ d, const int64_t* __restrict__ eoff,
-                               const uint32_t* __restrict__ pins, const int32_t* __restrict__ mult,
-                               int32_t* __restrict__ dstmult) {
-  int64_t E = d->E;
-  int lane = threadIdx.x & (kWave - 1);
-  int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
-  for (int64_t e = wave; e < E; e += nw) {
-    int32_t m = mult[e];
-    for (int64_t k = eoff[e] + lane; k < eoff[e + 1]; k += kWave) {
-      uint32_t p = pins[k];
-      if (p & kDst) atomicAdd(&dstmult[p & kIdMask], m);
-    }
-  }
-}
-
+// Coarse vertex state from the fine vertices: sizes and synapses summed; the
+// axons start from each member's internal ones (its axons less the
+// multiplicity of the hyperedges where it holds the destination flag, which
+// scatter_add_flagged summed into dstmult).
 __global__ void vertex_state_kernel(LevelView L, const int32_t* __restrict__ vmap,
                                     const int32_t* __restrict__ dstmult, int32_t* __restrict__ osize,
                                     int32_t* __restrict__ osyn, int32_t* __restrict__ oax) {
@@ -123,10 +109,12 @@ struct S6Args {
   uint64_t fp_mask;  // fingerprint bits kept (all of them outside tests)
 };
 
+// The coarse pins of fine hyperedge e (their flagged multiplicities are added
+// to the coarse vertices' axons after S6, by scatter_add_flagged).
 __device__ inline void emit_pin(const S6Args& a, int64_t e, int64_t pos, uint32_t pin,
                                 int32_t m) {
+  (void)m;
   a.tpin[a.L.eoff[e] + pos] = pin;
-  if (pin & kDst) atomicAdd(&a.oax[pin & kIdMask], m);
 }
 
 // Up to 64 pins: one key per lane, bitonic sort by shuffles.
@@ -537,7 +525,8 @@ int contract_level(const LevelView& L, int64_t maxV, int64_t maxE, int64_t maxP,
 
   // state
   fill_i32(cs.dstmult, 0, maxV, s);
-  dstmult_kernel<<<gridEw, 256, 0, s>>>(L.dims, L.eoff, L.pins, L.mult, cs.dstmult);
+  scatter_add_flagged(L.dims, L.eoff, nullptr, L.pins, L.mult, &L.dims->V, nullptr, maxV, maxE,
+                      cs.dstmult, cs.inc, cs.partials, s);
   fill_i32(out->v_size, 0, capV, s);
   fill_i32(out->v_syn, 0, capV, s);
   fill_i32(out->v_axons, 0, capV, s);
@@ -559,6 +548,10 @@ int contract_level(const LevelView& L, int64_t maxV, int64_t maxE, int64_t maxP,
   s6_block_kernel<kBlockMax, 2><<<device_cu_count() * 2, kBlockThreads, 0, s>>>(a6);
   a6.list = cs.ebucket + 3 * maxE;
   s6_huge_kernel<<<kHugeWG, kBlockThreads, 0, s>>>(a6);
+  // the axons of the coarse vertices: + mult of every coarse hyperedge copy
+  // (per fine hyperedge) where the vertex holds a destination
+  scatter_add_flagged(L.dims, L.eoff, cs.tlen, cs.tpin, L.mult, nullptr, n_coarse, maxV, maxE,
+                      out->v_axons, cs.inc, cs.partials, s);
 
   // S7
   fill_u64(cs.htab_key, 0, cs.htab_cap, s);

@@ -220,6 +220,8 @@ struct ContractLayout {
     cs.partials = a.template take<int64_t>(scan_partials_size());
     cs.bitmap_words = (V + 31) / 32 + 1;
     cs.bitmap = a.template take<uint32_t>((int64_t)kHugeWG * 2 * cs.bitmap_words);
+    uint64_t* pairs = a.template take<uint64_t>(P);
+    cs.inc = incidence_scratch_carve(a, V, pairs);
   }
 };
 

@@ -133,6 +133,7 @@ struct IncScratch {
   int64_t* boff = nullptr;    // [kIncBuckets' * kIncBlocks + 1]
   int32_t* bcnt = nullptr;    // [buckets * kIncBlocks]
   int64_t* n = nullptr;       // [1]
+  int64_t nb_cap = 0;         // buckets the arrays were carved for
 };
 inline int64_t incidence_buckets(int64_t maxV) {
   return (maxV + (1ll << kIncBits) - 1) >> kIncBits;
@@ -146,11 +147,21 @@ IncScratch incidence_scratch_carve(A& a, int64_t maxV, uint64_t* pairs) {
   s.boff = a.template take<int64_t>(nb * kIncBlocks + 1);
   s.bcnt = a.template take<int32_t>(nb * kIncBlocks);
   s.n = a.template take<int64_t>(1);
+  s.nb_cap = nb;
   return s;
 }
 void build_incidence(const LevelView& L, int64_t maxV, int64_t maxE, int64_t maxP,
                      int32_t* vcount, int64_t* voff, uint32_t* vinc, int64_t* partials,
                      hipStream_t s, const IncScratch& inc = IncScratch());
+// acc[v] += val[e] for every flagged pin v of every hyperedge e, the pins of
+// e being pins[eoff[e] .. eoff[e] + (len ? len[e] : eoff[e+1] - eoff[e])),
+// E and P from `d`; v < *nv32 (or *nv64); at most maxNV.  Through the same
+// buckets as build_incidence (no global atomics) when `inc` allows maxNV,
+// else with global atomics.
+void scatter_add_flagged(const Dims* d, const int64_t* eoff, const int32_t* len,
+                         const uint32_t* pins, const int32_t* val, const int64_t* nv64,
+                         const int32_t* nv32, int64_t maxNV, int64_t maxE, int32_t* acc,
+                         const IncScratch& inc, int64_t* partials, hipStream_t s);
 void level0_state(const Dims* d, const int64_t* eoff, const uint32_t* pins, int64_t maxV,
                   int64_t maxE, int32_t* size, int32_t* syn, int32_t* ax, int32_t* mult,
                   hipStream_t s);
@@ -253,6 +264,7 @@ struct ContractScratch {
   uint32_t* bitmap;     // huge-hyperedge fallback [n_wg * words]
   int64_t bitmap_words; // per work-group
   Dims* out_dims;       // device Dims of the output level
+  IncScratch inc;       // buckets of the flagged-multiplicity sums
   int32_t* err;
   uint64_t fp_mask = ~0ull;  // bits of the S7 fingerprints kept (all but in tests)
 };

@@ -173,6 +173,114 @@ __global__ __launch_bounds__(1024) void inc_finish_kernel(const Dims* __restrict
   }
 }
 
+// ---- bucketed sums of flagged pins ------------------------------------------
+// The same buckets, over the live pins of each hyperedge (pins[eoff[e] ..
+// eoff[e] + len[e]) when `len` is given); only flagged pins take part.
+
+__device__ inline int64_t edge_of_pin(const int64_t* eoff, int64_t E, int64_t p0) {
+  int64_t lo = 0, hi = E;  // the last hyperedge starting at or before p0
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (eoff[mid] <= p0) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline int64_t acc_vertices(const int64_t* nv64, const int32_t* nv32) {
+  return nv64 ? *nv64 : (int64_t)*nv32;
+}
+
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void flagged_bucket_kernel(
+    const Dims* __restrict__ d, const int64_t* __restrict__ eoff, const int32_t* __restrict__ len,
+    const uint32_t* __restrict__ pins, const int32_t* __restrict__ val,
+    const int64_t* __restrict__ nv64, const int32_t* __restrict__ nv32,
+    int32_t* __restrict__ bcnt, int64_t* __restrict__ n_out, const int64_t* __restrict__ boff,
+    uint64_t* __restrict__ pairs) {
+  __shared__ int32_t h[kIncBuckets];
+  __shared__ int64_t s_e0;
+  const int64_t E = d->E, P = d->P, NV = acc_vertices(nv64, nv32);
+  const int32_t nb = (int32_t)((NV + (1 << kIncBits) - 1) >> kIncBits);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  constexpr int NW = 256 / kWave;
+  for (int32_t i = threadIdx.x; i < nb; i += 256) h[i] = 0;
+  if (!SCATTER && blockIdx.x == 0 && threadIdx.x == 0) *n_out = (int64_t)nb * gridDim.x;
+  int64_t p0, p1;
+  pin_share(P, p0, p1);
+  if (threadIdx.x == 0) s_e0 = edge_of_pin(eoff, E, p0);
+  __syncthreads();
+  const int64_t G = gridDim.x;
+  if (p0 < p1) {  // block-uniform
+    for (int64_t e = s_e0 + wid; e < E; e += NW) {
+      const int64_t a0 = eoff[e];
+      if (a0 >= p1) break;  // wave-uniform
+      const int64_t a1 = len ? a0 + len[e] : eoff[e + 1];
+      const int64_t lo = a0 > p0 ? a0 : p0, hi = a1 < p1 ? a1 : p1;
+      const int32_t m = val[e];
+      for (int64_t k = lo + lane; k < hi; k += kWave) {
+        const uint32_t p = pins[k];
+        if (!(p & kDst)) continue;
+        const uint32_t v = p & kIdMask;
+        const int32_t b = (int32_t)(v >> kIncBits);
+        if (!SCATTER) {
+          atomicAdd(&h[b], 1);
+        } else {
+          const int32_t at = atomicAdd(&h[b], 1);
+          pairs[boff[(int64_t)b * G + blockIdx.x] + at] = ((uint64_t)v << 32) | (uint32_t)m;
+        }
+      }
+    }
+  }
+  if (!SCATTER) {
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < nb; i += 256) bcnt[(int64_t)i * G + blockIdx.x] = h[i];
+  }
+}
+
+// One work-group per bucket: LDS sums of its pairs added to acc.
+__global__ __launch_bounds__(1024) void flagged_sum_kernel(
+    const int64_t* __restrict__ nv64, const int32_t* __restrict__ nv32,
+    const int64_t* __restrict__ boff, int32_t G, const int64_t* __restrict__ n_pairs_at,
+    const uint64_t* __restrict__ pairs, int32_t* __restrict__ acc) {
+  constexpr int kIds = 1 << kIncBits;
+  __shared__ int32_t sum[kIds];
+  const int64_t NV = acc_vertices(nv64, nv32);
+  const int32_t nb = (int32_t)((NV + kIds - 1) >> kIncBits);
+  const int32_t b = blockIdx.x;
+  if (b >= nb) return;  // block-uniform
+  const int64_t start = boff[(int64_t)b * G];
+  const int64_t end = b + 1 < nb ? boff[(int64_t)(b + 1) * G] : boff[*n_pairs_at];
+  const int64_t base = (int64_t)b << kIncBits;
+  for (int i = threadIdx.x; i < kIds; i += 1024) sum[i] = 0;
+  __syncthreads();
+  for (int64_t k = start + threadIdx.x; k < end; k += 1024) {
+    const uint64_t pr = pairs[k];
+    atomicAdd(&sum[(int32_t)((pr >> 32) - base)], (int32_t)(uint32_t)pr);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kIds; i += 1024)
+    if (base + i < NV && sum[i]) acc[base + i] += sum[i];
+}
+
+__global__ void flagged_atomic_kernel(const Dims* __restrict__ d, const int64_t* __restrict__ eoff,
+                                      const int32_t* __restrict__ len,
+                                      const uint32_t* __restrict__ pins,
+                                      const int32_t* __restrict__ val, int32_t* __restrict__ acc) {
+  const int64_t E = d->E;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t e = wave; e < E; e += nw) {
+    const int64_t a0 = eoff[e], a1 = len ? a0 + len[e] : eoff[e + 1];
+    const int32_t m = val[e];
+    for (int64_t k = a0 + lane; k < a1; k += kWave) {
+      const uint32_t p = pins[k];
+      if (p & kDst) atomicAdd(&acc[p & kIdMask], m);
+    }
+  }
+}
+
 __global__ void level0_flags_kernel(const Dims* __restrict__ d, const uint32_t* __restrict__ pins,
                                     int32_t* __restrict__ syn) {
   int64_t P = d->P;
@@ -320,7 +428,7 @@ void build_incidence(const LevelView& L, int64_t maxV, int64_t maxE, int64_t max
                      int32_t* vcount, int64_t* voff, uint32_t* vinc, int64_t* partials,
                      hipStream_t s, const IncScratch& inc) {
   const int64_t nb = incidence_buckets(maxV);
-  if (inc.pairs && inc.boff && nb >= 1 && nb <= kIncBuckets) {
+  if (inc.pairs && inc.boff && nb >= 1 && nb <= inc.nb_cap) {
     inc_count_kernel<<<kIncBlocks, 256, 0, s>>>(L.dims, L.pins, inc.bcnt, inc.n);
     exclusive_scan_i32(inc.bcnt, inc.boff, inc.n, nb * kIncBlocks, partials, s);
     inc_scatter_kernel<<<kIncBlocks, 256, 0, s>>>(L.dims, L.eoff, L.pins, inc.boff, inc.pairs);
@@ -334,6 +442,24 @@ void build_incidence(const LevelView& L, int64_t maxV, int64_t maxE, int64_t max
   fill_i32(vcount, 0, maxV, s);
   scatter_incidence_kernel<<<grid_for(maxE, 4, 16384), 256, 0, s>>>(L.dims, L.eoff, L.pins,
                                                                      voff, vcount, vinc);
+}
+
+void scatter_add_flagged(const Dims* d, const int64_t* eoff, const int32_t* len,
+                         const uint32_t* pins, const int32_t* val, const int64_t* nv64,
+                         const int32_t* nv32, int64_t maxNV, int64_t maxE, int32_t* acc,
+                         const IncScratch& inc, int64_t* partials, hipStream_t s) {
+  const int64_t nb = incidence_buckets(maxNV);
+  if (inc.pairs && inc.boff && nb >= 1 && nb <= inc.nb_cap) {
+    flagged_bucket_kernel<false><<<kIncBlocks, 256, 0, s>>>(d, eoff, len, pins, val, nv64, nv32,
+                                                           inc.bcnt, inc.n, nullptr, nullptr);
+    exclusive_scan_i32(inc.bcnt, inc.boff, inc.n, nb * kIncBlocks, partials, s);
+    flagged_bucket_kernel<true><<<kIncBlocks, 256, 0, s>>>(d, eoff, len, pins, val, nv64, nv32,
+                                                          nullptr, nullptr, inc.boff, inc.pairs);
+    flagged_sum_kernel<<<(int)nb, 1024, 0, s>>>(nv64, nv32, inc.boff, kIncBlocks, inc.n,
+                                               inc.pairs, acc);
+    return;
+  }
+  flagged_atomic_kernel<<<grid_for(maxE, 4, 16384), 256, 0, s>>>(d, eoff, len, pins, val, acc);
 }
 
 void level0_state(const Dims* d, const int64_t* eoff, const uint32_t* pins, int64_t maxV,
