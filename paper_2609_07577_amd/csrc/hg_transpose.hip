@@ -43,6 +43,7 @@ __global__ void scatter_incidence_kernel(const Dims* __restrict__ d,
 }
 
 // ---- bucketed transpose --------------------------------------------------
+constexpr int kIncScatterThreads = 512;
 // Work-group g takes the pins [P g / G, P (g + 1) / G).
 
 __device__ inline void pin_share(int64_t P, int64_t& p0, int64_t& p1) {
@@ -73,18 +74,19 @@ __global__ __launch_bounds__(256) void inc_count_kernel(const Dims* __restrict__
 // The work-group's pins as (vertex << 32 | edge | flag) pairs at its slots of
 // each bucket (boff = exclusive scan of bcnt, bucket-major).  Waves walk the
 // hyperedges that meet the share, from the one holding its first pin.
-__global__ __launch_bounds__(256) void inc_scatter_kernel(const Dims* __restrict__ d,
-                                                          const int64_t* __restrict__ eoff,
-                                                          const uint32_t* __restrict__ pins,
-                                                          const int64_t* __restrict__ boff,
-                                                          uint64_t* __restrict__ pairs) {
-  __shared__ int32_t cur[kIncBuckets];
+__global__ __launch_bounds__(kIncScatterThreads) void inc_scatter_kernel(
+    const Dims* __restrict__ d, const int64_t* __restrict__ eoff,
+    const uint32_t* __restrict__ pins, const int64_t* __restrict__ boff,
+    uint64_t* __restrict__ pairs) {
+  __shared__ int32_t cur[kIncBuckets];  // next slot of each bucket (P < 2^31)
   __shared__ int64_t s_e0;
   const int64_t V = d->V, E = d->E, P = d->P;
   const int32_t nb = (int32_t)((V + (1 << kIncBits) - 1) >> kIncBits);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  constexpr int NW = 256 / kWave;
-  for (int32_t i = threadIdx.x; i < nb; i += 256) cur[i] = 0;
+  constexpr int NW = kIncScatterThreads / kWave;
+  const int64_t G = gridDim.x;
+  for (int32_t i = threadIdx.x; i < nb; i += kIncScatterThreads)
+    cur[i] = (int32_t)boff[(int64_t)i * G + blockIdx.x];
   int64_t p0, p1;
   pin_share(P, p0, p1);
   if (threadIdx.x == 0) {
@@ -99,7 +101,6 @@ __global__ __launch_bounds__(256) void inc_scatter_kernel(const Dims* __restrict
   }
   __syncthreads();
   if (p0 >= p1) return;  // block-uniform, after the last barrier
-  const int64_t G = gridDim.x;
   for (int64_t e = s_e0 + wid; e < E; e += NW) {
     const int64_t a0 = eoff[e], a1 = eoff[e + 1];
     if (a0 >= p1) break;  // wave-uniform
@@ -107,10 +108,8 @@ __global__ __launch_bounds__(256) void inc_scatter_kernel(const Dims* __restrict
     for (int64_t k = lo + lane; k < hi; k += kWave) {
       const uint32_t p = pins[k];
       const uint32_t v = p & kIdMask;
-      const int32_t b = (int32_t)(v >> kIncBits);
-      const int32_t at = atomicAdd(&cur[b], 1);
-      pairs[boff[(int64_t)b * G + blockIdx.x] + at] =
-          ((uint64_t)v << 32) | (uint64_t)((uint32_t)e | (p & kDst));
+      const int32_t at = atomicAdd(&cur[v >> kIncBits], 1);
+      pairs[at] = ((uint64_t)v << 32) | (uint64_t)((uint32_t)e | (p & kDst));
     }
   }
 }
@@ -138,8 +137,18 @@ __global__ __launch_bounds__(1024) void inc_finish_kernel(const Dims* __restrict
   const int64_t base = (int64_t)b << kIncBits;
   for (int i = tid; i < kIds; i += 1024) cnt[i] = 0;
   __syncthreads();
-  for (int64_t k = start + tid; k < end; k += 1024)
-    atomicAdd(&cnt[(int32_t)((pairs[k] >> 32) - base)], 1);
+  // four loads in flight per thread before their LDS updates
+  for (int64_t k0 = start + tid; k0 < end; k0 += 4 * 1024) {
+    uint64_t pr[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + u * 1024;
+      pr[u] = k < end ? pairs[k] : ((uint64_t)base << 32);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + u * 1024 < end) atomicAdd(&cnt[(int32_t)((pr[u] >> 32) - base)], 1);
+  }
   __syncthreads();
   // exclusive scan: thread t owns ids [kPer t, kPer t + kPer)
   int32_t loc[kPer], sum = 0;
@@ -166,10 +175,20 @@ __global__ __launch_bounds__(1024) void inc_finish_kernel(const Dims* __restrict
     if (v < V) voff[v] = start + first + loc[i];
   }
   __syncthreads();
-  for (int64_t k = start + tid; k < end; k += 1024) {
-    const uint64_t pr = pairs[k];
-    const int32_t at = atomicAdd(&cnt[(int32_t)((pr >> 32) - base)], 1);
-    vinc[start + at] = (uint32_t)pr;
+  for (int64_t k0 = start + tid; k0 < end; k0 += 4 * 1024) {
+    uint64_t pr[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + u * 1024;
+      pr[u] = k < end ? pairs[k] : ((uint64_t)base << 32);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (k0 + u * 1024 < end) {
+        const int32_t at = atomicAdd(&cnt[(int32_t)((pr[u] >> 32) - base)], 1);
+        vinc[start + at] = (uint32_t)pr[u];
+      }
+    }
   }
 }
 
@@ -192,7 +211,7 @@ __device__ inline int64_t acc_vertices(const int64_t* nv64, const int32_t* nv32)
 }
 
 template <bool SCATTER>
-__global__ __launch_bounds__(256) void flagged_bucket_kernel(
+__global__ __launch_bounds__(kIncScatterThreads) void flagged_bucket_kernel(
     const Dims* __restrict__ d, const int64_t* __restrict__ eoff, const int32_t* __restrict__ len,
     const uint32_t* __restrict__ pins, const int32_t* __restrict__ val,
     const int64_t* __restrict__ nv64, const int32_t* __restrict__ nv32,
@@ -203,14 +222,16 @@ __global__ __launch_bounds__(256) void flagged_bucket_kernel(
   const int64_t E = d->E, P = d->P, NV = acc_vertices(nv64, nv32);
   const int32_t nb = (int32_t)((NV + (1 << kIncBits) - 1) >> kIncBits);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  constexpr int NW = 256 / kWave;
-  for (int32_t i = threadIdx.x; i < nb; i += 256) h[i] = 0;
+  constexpr int NW = kIncScatterThreads / kWave;
+  const int64_t G = gridDim.x;
+  // counts, or (scatter) the next slot of each bucket (P < 2^31)
+  for (int32_t i = threadIdx.x; i < nb; i += kIncScatterThreads)
+    h[i] = SCATTER ? (int32_t)boff[(int64_t)i * G + blockIdx.x] : 0;
   if (!SCATTER && blockIdx.x == 0 && threadIdx.x == 0) *n_out = (int64_t)nb * gridDim.x;
   int64_t p0, p1;
   pin_share(P, p0, p1);
   if (threadIdx.x == 0) s_e0 = edge_of_pin(eoff, E, p0);
   __syncthreads();
-  const int64_t G = gridDim.x;
   if (p0 < p1) {  // block-uniform
     for (int64_t e = s_e0 + wid; e < E; e += NW) {
       const int64_t a0 = eoff[e];
@@ -222,19 +243,15 @@ __global__ __launch_bounds__(256) void flagged_bucket_kernel(
         const uint32_t p = pins[k];
         if (!(p & kDst)) continue;
         const uint32_t v = p & kIdMask;
-        const int32_t b = (int32_t)(v >> kIncBits);
-        if (!SCATTER) {
-          atomicAdd(&h[b], 1);
-        } else {
-          const int32_t at = atomicAdd(&h[b], 1);
-          pairs[boff[(int64_t)b * G + blockIdx.x] + at] = ((uint64_t)v << 32) | (uint32_t)m;
-        }
+        const int32_t at = atomicAdd(&h[v >> kIncBits], 1);
+        if (SCATTER) pairs[at] = ((uint64_t)v << 32) | (uint32_t)m;
       }
     }
   }
   if (!SCATTER) {
     __syncthreads();
-    for (int32_t i = threadIdx.x; i < nb; i += 256) bcnt[(int64_t)i * G + blockIdx.x] = h[i];
+    for (int32_t i = threadIdx.x; i < nb; i += kIncScatterThreads)
+      bcnt[(int64_t)i * G + blockIdx.x] = h[i];
   }
 }
 
@@ -431,7 +448,8 @@ void build_incidence(const LevelView& L, int64_t maxV, int64_t maxE, int64_t max
   if (inc.pairs && inc.boff && nb >= 1 && nb <= inc.nb_cap) {
     inc_count_kernel<<<kIncBlocks, 256, 0, s>>>(L.dims, L.pins, inc.bcnt, inc.n);
     exclusive_scan_i32(inc.bcnt, inc.boff, inc.n, nb * kIncBlocks, partials, s);
-    inc_scatter_kernel<<<kIncBlocks, 256, 0, s>>>(L.dims, L.eoff, L.pins, inc.boff, inc.pairs);
+    inc_scatter_kernel<<<kIncBlocks, kIncScatterThreads, 0, s>>>(L.dims, L.eoff, L.pins,
+                                                                 inc.boff, inc.pairs);
     inc_finish_kernel<<<(int)nb, 1024, 0, s>>>(L.dims, inc.boff, kIncBlocks, inc.pairs, voff,
                                                vinc);
     return;
@@ -450,11 +468,11 @@ void scatter_add_flagged(const Dims* d, const int64_t* eoff, const int32_t* len,
                          const IncScratch& inc, int64_t* partials, hipStream_t s) {
   const int64_t nb = incidence_buckets(maxNV);
   if (inc.pairs && inc.boff && nb >= 1 && nb <= inc.nb_cap) {
-    flagged_bucket_kernel<false><<<kIncBlocks, 256, 0, s>>>(d, eoff, len, pins, val, nv64, nv32,
-                                                           inc.bcnt, inc.n, nullptr, nullptr);
+    flagged_bucket_kernel<false><<<kIncBlocks, kIncScatterThreads, 0, s>>>(
+        d, eoff, len, pins, val, nv64, nv32, inc.bcnt, inc.n, nullptr, nullptr);
     exclusive_scan_i32(inc.bcnt, inc.boff, inc.n, nb * kIncBlocks, partials, s);
-    flagged_bucket_kernel<true><<<kIncBlocks, 256, 0, s>>>(d, eoff, len, pins, val, nv64, nv32,
-                                                          nullptr, nullptr, inc.boff, inc.pairs);
+    flagged_bucket_kernel<true><<<kIncBlocks, kIncScatterThreads, 0, s>>>(
+        d, eoff, len, pins, val, nv64, nv32, nullptr, nullptr, inc.boff, inc.pairs);
     flagged_sum_kernel<<<(int)nb, 1024, 0, s>>>(nv64, nv32, inc.boff, kIncBlocks, inc.n,
                                                inc.pairs, acc);
     return;
