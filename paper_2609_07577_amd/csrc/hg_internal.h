@@ -119,24 +119,35 @@ void exclusive_scan_i64(const int64_t* in, int64_t* out, const int64_t* count,
 // Incidence lists: voff [V+1], vinc [P] = edge | flag << 31.
 //
 // Levels of at most kIncBuckets * 2^kIncBits vertices are transposed without
-// global atomics, in buckets of 2^kIncBits consecutive vertices: per-work-
+// global atomics, in buckets of 2^b consecutive vertices (b the smallest
+// width giving at most kIncMinBuckets buckets, at most kIncBits): per-work-
 // group bucket counts of an even share of the pins, one scan, a scatter of
 // (vertex, entry) pairs into the buckets, then one work-group per bucket
-// counting, scanning and placing its vertices' entries in LDS.  That needs
-// an IncScratch (carve it with incidence_scratch_carve); without one, or on
-// larger levels, the lists are built with global atomic counters.
+// counting, scanning and placing its vertices' entries in LDS.  (Narrow
+// buckets keep every CU busy on coarse levels with few vertices and many
+// pins.)  That needs an IncScratch (carve it with incidence_scratch_carve);
+// without one, or on larger levels, the lists are built with global atomic
+// counters.
 constexpr int kIncBits = 13;
 constexpr int kIncBuckets = 4096;
+constexpr int kIncMinBuckets = 256;
 constexpr int kIncBlocks = 1024;
 struct IncScratch {
   uint64_t* pairs = nullptr;  // [P] (vertex << 32 | entry); may alias other scratch
-  int64_t* boff = nullptr;    // [kIncBuckets' * kIncBlocks + 1]
-  int32_t* bcnt = nullptr;    // [buckets * kIncBlocks]
+  int64_t* boff = nullptr;    // [nb_cap * kIncBlocks + 1]
+  int32_t* bcnt = nullptr;    // [nb_cap * kIncBlocks]
   int64_t* n = nullptr;       // [1]
   int64_t nb_cap = 0;         // buckets the arrays were carved for
 };
+__host__ __device__ inline int incidence_bits(int64_t V) {
+  int b = 0;
+  while (b < kIncBits && ((V + (1ll << b) - 1) >> b) > kIncMinBuckets) ++b;
+  return b;
+}
+// the most buckets a level of at most maxV vertices can use
 inline int64_t incidence_buckets(int64_t maxV) {
-  return (maxV + (1ll << kIncBits) - 1) >> kIncBits;
+  const int64_t wide = (maxV + (1ll << kIncBits) - 1) >> kIncBits;
+  return wide > kIncMinBuckets ? wide : (maxV > 0 ? kIncMinBuckets : 0);
 }
 template <typename A>
 IncScratch incidence_scratch_carve(A& a, int64_t maxV, uint64_t* pairs) {

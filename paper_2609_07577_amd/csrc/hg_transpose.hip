@@ -58,14 +58,15 @@ __global__ __launch_bounds__(256) void inc_count_kernel(const Dims* __restrict__
                                                         int64_t* __restrict__ n_out) {
   __shared__ int32_t h[kIncBuckets];
   const int64_t V = d->V, P = d->P;
-  const int32_t nb = (int32_t)((V + (1 << kIncBits) - 1) >> kIncBits);
+  const int bits = incidence_bits(V);
+  const int32_t nb = (int32_t)((V + (1ll << bits) - 1) >> bits);
   for (int32_t i = threadIdx.x; i < nb; i += 256) h[i] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = (int64_t)nb * gridDim.x;
   __syncthreads();
   int64_t p0, p1;
   pin_share(P, p0, p1);
   for (int64_t k = p0 + threadIdx.x; k < p1; k += 256)
-    atomicAdd(&h[(pins[k] & kIdMask) >> kIncBits], 1);
+    atomicAdd(&h[(pins[k] & kIdMask) >> bits], 1);
   __syncthreads();
   for (int32_t i = threadIdx.x; i < nb; i += 256)
     bcnt[(int64_t)i * gridDim.x + blockIdx.x] = h[i];
@@ -81,7 +82,8 @@ __global__ __launch_bounds__(kIncScatterThreads) void inc_scatter_kernel(
   __shared__ int32_t cur[kIncBuckets];  // next slot of each bucket (P < 2^31)
   __shared__ int64_t s_e0;
   const int64_t V = d->V, E = d->E, P = d->P;
-  const int32_t nb = (int32_t)((V + (1 << kIncBits) - 1) >> kIncBits);
+  const int bits = incidence_bits(V);
+  const int32_t nb = (int32_t)((V + (1ll << bits) - 1) >> bits);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   constexpr int NW = kIncScatterThreads / kWave;
   const int64_t G = gridDim.x;
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(kIncScatterThreads) void inc_scatter_kernel(
     for (int64_t k = lo + lane; k < hi; k += kWave) {
       const uint32_t p = pins[k];
       const uint32_t v = p & kIdMask;
-      const int32_t at = atomicAdd(&cur[v >> kIncBits], 1);
+      const int32_t at = atomicAdd(&cur[v >> bits], 1);
       pairs[at] = ((uint64_t)v << 32) | (uint64_t)((uint32_t)e | (p & kDst));
     }
   }
@@ -127,14 +129,16 @@ __global__ __launch_bounds__(1024) void inc_finish_kernel(const Dims* __restrict
   __shared__ int32_t cnt[kIds];
   __shared__ int32_t ws[1024 / kWave];
   const int64_t V = d->V, P = d->P;
-  const int32_t nb = (int32_t)((V + kIds - 1) >> kIncBits);
+  const int bits = incidence_bits(V);
+  const int32_t ids = 1 << bits;  // vertices of a bucket (<= kIds)
+  const int32_t nb = (int32_t)((V + ids - 1) >> bits);
   const int32_t b = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   if (b == 0 && tid == 0) voff[V] = P;
   if (b >= nb) return;  // block-uniform, before any barrier
   const int64_t start = boff[(int64_t)b * G];
   const int64_t end = b + 1 < nb ? boff[(int64_t)(b + 1) * G] : P;
-  const int64_t base = (int64_t)b << kIncBits;
+  const int64_t base = (int64_t)b << bits;
   for (int i = tid; i < kIds; i += 1024) cnt[i] = 0;
   __syncthreads();
   // four loads in flight per thread before their LDS updates
@@ -170,9 +174,9 @@ __global__ __launch_bounds__(1024) void inc_finish_kernel(const Dims* __restrict
   const int32_t first = before + inc - sum;
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
-    const int64_t v = base + kPer * tid + i;
-    cnt[kPer * tid + i] = first + loc[i];
-    if (v < V) voff[v] = start + first + loc[i];
+    const int32_t j = kPer * tid + i;
+    cnt[j] = first + loc[i];
+    if (j < ids && base + j < V) voff[base + j] = start + first + loc[i];
   }
   __syncthreads();
   for (int64_t k0 = start + tid; k0 < end; k0 += 4 * 1024) {
@@ -220,7 +224,8 @@ __global__ __launch_bounds__(kIncScatterThreads) void flagged_bucket_kernel(
   __shared__ int32_t h[kIncBuckets];
   __shared__ int64_t s_e0;
   const int64_t E = d->E, P = d->P, NV = acc_vertices(nv64, nv32);
-  const int32_t nb = (int32_t)((NV + (1 << kIncBits) - 1) >> kIncBits);
+  const int bits = incidence_bits(NV);
+  const int32_t nb = (int32_t)((NV + (1ll << bits) - 1) >> bits);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   constexpr int NW = kIncScatterThreads / kWave;
   const int64_t G = gridDim.x;
@@ -243,7 +248,7 @@ __global__ __launch_bounds__(kIncScatterThreads) void flagged_bucket_kernel(
         const uint32_t p = pins[k];
         if (!(p & kDst)) continue;
         const uint32_t v = p & kIdMask;
-        const int32_t at = atomicAdd(&h[v >> kIncBits], 1);
+        const int32_t at = atomicAdd(&h[v >> bits], 1);
         if (SCATTER) pairs[at] = ((uint64_t)v << 32) | (uint32_t)m;
       }
     }
@@ -263,12 +268,14 @@ __global__ __launch_bounds__(1024) void flagged_sum_kernel(
   constexpr int kIds = 1 << kIncBits;
   __shared__ int32_t sum[kIds];
   const int64_t NV = acc_vertices(nv64, nv32);
-  const int32_t nb = (int32_t)((NV + kIds - 1) >> kIncBits);
+  const int bits = incidence_bits(NV);
+  const int32_t ids = 1 << bits;
+  const int32_t nb = (int32_t)((NV + ids - 1) >> bits);
   const int32_t b = blockIdx.x;
   if (b >= nb) return;  // block-uniform
   const int64_t start = boff[(int64_t)b * G];
   const int64_t end = b + 1 < nb ? boff[(int64_t)(b + 1) * G] : boff[*n_pairs_at];
-  const int64_t base = (int64_t)b << kIncBits;
+  const int64_t base = (int64_t)b << bits;
   for (int i = threadIdx.x; i < kIds; i += 1024) sum[i] = 0;
   __syncthreads();
   for (int64_t k = start + threadIdx.x; k < end; k += 1024) {
@@ -276,7 +283,7 @@ __global__ __launch_bounds__(1024) void flagged_sum_kernel(
     atomicAdd(&sum[(int32_t)((pr >> 32) - base)], (int32_t)(uint32_t)pr);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kIds; i += 1024)
+  for (int i = threadIdx.x; i < ids; i += 1024)
     if (base + i < NV && sum[i]) acc[base + i] += sum[i];
 }
 
