@@ -159,38 +159,42 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
       };
       for (int32_t wi = 0; wi < nw; ++wi) {  // block-uniform
         const uint32_t lo = (uint32_t)wi << kBits;
-        // chunks of this window: thread t owns incident hyperedges t, t + THREADS, ...
-        int32_t mine = 0;
-        for (int64_t j = tid; j < deg; j += THREADS) {
-          const uint32_t e = a.vinc[v.beg + j] & kIdMask;
-          uint32_t b0, b1;
-          bounds(a.splits14 + (int64_t)e * (W + 1), wi, b0, b1);
-          mine += (int32_t)((b1 - b0 + kWave - 1) / kWave);
-        }
-        int32_t x3[3] = {mine, 0, 0}, p3[3], t3[3];
-        block_scan3<THREADS>(x3, p3, t3, S.ws);
-        const int32_t T = t3[0];
-        if (T == 0) {  // block-uniform; the scan's words are read before the next scan
-          __syncthreads();
-          continue;
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) tab4[8 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
-        for (int32_t r0 = 0; r0 < T; r0 += kMaxChunks) {  // block-uniform
-          const int32_t Tr = T - r0 < kMaxChunks ? T - r0 : kMaxChunks;
-          __syncthreads();  // table clear, previous round's chunks done
-          int32_t c = p3[0];  // this thread's first chunk in the window's list
-          for (int64_t j = tid; j < deg; j += THREADS) {
+        bool cleared = false;  // block-uniform: the table is cleared before the first sweep
+        // segments of THREADS incident hyperedges; thread t holds hyperedge
+        // seg + t of the segment (its slice of the window) in registers
+        for (int64_t seg = 0; seg < deg; seg += THREADS) {  // block-uniform
+          const int64_t j = seg + tid;
+          uint32_t first = 0, len = 0, wt = 0, mu = 0;
+          if (j < deg) {
             const uint32_t ent = a.vinc[v.beg + j];
             const uint32_t e = ent & kIdMask;
             uint32_t b0, b1;
             bounds(a.splits14 + (int64_t)e * (W + 1), wi, b0, b1);
-            const uint32_t first = (uint32_t)a.L.eoff[e] + b0;
-            const uint32_t len = b1 - b0;
-            const int32_t nch = (int32_t)((len + kWave - 1) / kWave);
+            len = b1 - b0;
+            if (len) {
+              first = (uint32_t)a.L.eoff[e] + b0;
+              wt = (uint32_t)a.L.w[e];
+              mu = (OV && (ent & kDst)) ? (uint32_t)a.L.mult[e] : 0u;
+            }
+          }
+          const int32_t nch = (int32_t)((len + kWave - 1) / kWave);
+          int32_t x3[3] = {nch, 0, 0}, p3[3], t3[3];
+          block_scan3<THREADS>(x3, p3, t3, S.ws);
+          const int32_t T = t3[0];
+          if (T == 0) {  // block-uniform; the scan's words are read before the next scan
+            __syncthreads();
+            continue;
+          }
+          if (!cleared) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) tab4[8 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
+            cleared = true;
+          }
+          for (int32_t r0 = 0; r0 < T; r0 += kMaxChunks) {  // block-uniform
+            const int32_t Tr = T - r0 < kMaxChunks ? T - r0 : kMaxChunks;
+            __syncthreads();  // table clear, previous round's chunks done
+            const int32_t c = p3[0];  // this thread's first chunk in the segment's list
             if (c + nch > r0 && c < r0 + Tr) {
-              const uint32_t wt = (uint32_t)a.L.w[e];
-              const uint32_t mu = (OV && (ent & kDst)) ? (uint32_t)a.L.mult[e] : 0u;
               for (int32_t q = 0; q < nch; ++q) {
                 const int32_t at = c + q - r0;
                 if (at < 0 || at >= Tr) continue;
@@ -199,91 +203,90 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
                                         left < (uint32_t)kWave ? left : (uint32_t)kWave, wt, mu);
               }
             }
-            c += nch;
-          }
-          if (tid < B) S.desc[Tr + tid] = make_uint4(0u, 0u, 0u, 0u);
-          if (tid == 0) S.s_next = NW;
-          __syncthreads();
-          const int32_t tb = (Tr + B - 1) / B;
-          // ---- the sweep
-          struct Batch {
-            uint32_t x[B];
-            int32_t cnt[B];
-            uint32_t wt[B], mu[B];
-          };
-          int32_t bclaim = wid;
-          auto fetch = [&](Batch& t, uint32_t (&pin)[B], int32_t bno) {
+            if (tid < B) S.desc[Tr + tid] = make_uint4(0u, 0u, 0u, 0u);
+            if (tid == 0) S.s_next = NW;
+            __syncthreads();
+            const int32_t tb = (Tr + B - 1) / B;
+            // ---- the sweep
+            struct Batch {
+              uint32_t x[B];
+              int32_t cnt[B];
+              uint32_t wt[B], mu[B];
+            };
+            int32_t bclaim = wid;
+            auto fetch = [&](Batch& t, uint32_t (&pin)[B], int32_t bno) {
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-              uint4 d = make_uint4(0u, 0u, 0u, 0u);
-              if (bno < tb) d = S.desc[bno * B + u];
-              t.x[u] = rfl_u32(d.x);
-              t.cnt[u] = (int32_t)rfl_u32(d.y);
-              t.wt[u] = rfl_u32(d.z);
-              t.mu[u] = rfl_u32(d.w);
-            }
+              for (int u = 0; u < B; ++u) {
+                uint4 d = make_uint4(0u, 0u, 0u, 0u);
+                if (bno < tb) d = S.desc[bno * B + u];
+                t.x[u] = rfl_u32(d.x);
+                t.cnt[u] = (int32_t)rfl_u32(d.y);
+                t.wt[u] = rfl_u32(d.z);
+                t.mu[u] = rfl_u32(d.w);
+              }
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-              const uint32_t last4 = t.cnt[u] > 0 ? (uint32_t)(t.cnt[u] - 1) * 4u : 0u;
-              const char* p = reinterpret_cast<const char*>(a.L.pins + t.x[u]);
-              const uint32_t off = lofs < last4 ? lofs : last4;
-              pin[u] = *reinterpret_cast<const uint32_t*>(p + off);
-            }
-            if (bno < tb) {  // wave-uniform: claim the next batch
-              int32_t cc = 0;
-              if (lane == 0) cc = atomicAdd(&S.s_next, 1);
-              bclaim = cc;
-            }
-            __builtin_amdgcn_sched_barrier(0);
-          };
-          auto process = [&](const Batch& t, const uint32_t (&pin)[B]) {
+              for (int u = 0; u < B; ++u) {
+                const uint32_t last4 = t.cnt[u] > 0 ? (uint32_t)(t.cnt[u] - 1) * 4u : 0u;
+                const char* p = reinterpret_cast<const char*>(a.L.pins + t.x[u]);
+                const uint32_t off = lofs < last4 ? lofs : last4;
+                pin[u] = *reinterpret_cast<const uint32_t*>(p + off);
+              }
+              if (bno < tb) {  // wave-uniform: claim the next batch
+                int32_t cc = 0;
+                if (lane == 0) cc = atomicAdd(&S.s_next, 1);
+                bclaim = cc;
+              }
+              __builtin_amdgcn_sched_barrier(0);
+            };
+            auto process = [&](const Batch& t, const uint32_t (&pin)[B]) {
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-              const uint32_t id = pin[u] & kIdMask;
-              const bool act = lofs < (uint32_t)t.cnt[u] * 4u && id != n;
-              if (act) {  // no cross-lane operation inside
-                const uint32_t share = (OV && (pin[u] & kDst)) ? t.mu[u] : 0u;
-                uint64_t sc;
-                uint32_t ov;
-                if (C) {
-                  const uint32_t add = (t.wt[u] << ob) | share;
-                  const uint32_t now = atomicAdd(&tab32[id - lo], add) + add;
-                  sc = now >> ob;
-                  ov = now & omask;
-                } else {
-                  const uint64_t add = ((uint64_t)t.wt[u] << 32) | (uint64_t)share;
-                  const uint64_t now =
-                      atomicAdd((unsigned long long*)&S.tab[id - lo], (unsigned long long)add) +
-                      add;
-                  sc = now >> 32;
-                  ov = (uint32_t)now;
+              for (int u = 0; u < B; ++u) {
+                const uint32_t id = pin[u] & kIdMask;
+                const bool act = lofs < (uint32_t)t.cnt[u] * 4u && id != n;
+                if (act) {  // no cross-lane operation inside
+                  const uint32_t share = (OV && (pin[u] & kDst)) ? t.mu[u] : 0u;
+                  uint64_t sc;
+                  uint32_t ov;
+                  if (C) {
+                    const uint32_t add = (t.wt[u] << ob) | share;
+                    const uint32_t now = atomicAdd(&tab32[id - lo], add) + add;
+                    sc = now >> ob;
+                    ov = now & omask;
+                  } else {
+                    const uint64_t add = ((uint64_t)t.wt[u] << 32) | (uint64_t)share;
+                    const uint64_t now =
+                        atomicAdd((unsigned long long*)&S.tab[id - lo], (unsigned long long)add) +
+                        add;
+                    sc = now >> 32;
+                    ov = (uint32_t)now;
+                  }
+                  const uint64_t key = (sc << 32) | (uint64_t)(kSent - id);
+                  if (key > best && (v.all_valid || merge_valid(a, v, id, OV ? (int64_t)ov : 0)))
+                    best = key;
                 }
-                const uint64_t key = (sc << 32) | (uint64_t)(kSent - id);
-                if (key > best && (v.all_valid || merge_valid(a, v, id, OV ? (int64_t)ov : 0)))
-                  best = key;
+              }
+              asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
+            };
+            {
+              Batch ta, tb2;
+              uint32_t pa[B], pb[B];
+              int32_t cur_b = wid;
+              fetch(ta, pa, cur_b);
+              while (cur_b < tb) {
+                const int32_t nb = __builtin_amdgcn_readlane(bclaim, 0);
+                fetch(tb2, pb, nb);
+                process(ta, pa);
+                cur_b = nb;
+                if (cur_b >= tb) break;
+                const int32_t nb2 = __builtin_amdgcn_readlane(bclaim, 0);
+                fetch(ta, pa, nb2);
+                process(tb2, pb);
+                cur_b = nb2;
               }
             }
-            asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
-          };
-          {
-            Batch ta, tb2;
-            uint32_t pa[B], pb[B];
-            int32_t cur_b = wid;
-            fetch(ta, pa, cur_b);
-            while (cur_b < tb) {
-              const int32_t nb = __builtin_amdgcn_readlane(bclaim, 0);
-              fetch(tb2, pb, nb);
-              process(ta, pa);
-              cur_b = nb;
-              if (cur_b >= tb) break;
-              const int32_t nb2 = __builtin_amdgcn_readlane(bclaim, 0);
-              fetch(ta, pa, nb2);
-              process(tb2, pb);
-              cur_b = nb2;
-            }
           }
-        }
-        __syncthreads();  // the window's sweep done before the table is cleared again
+        }  // segments
+        if (cleared) __syncthreads();  // the window's sweeps done before the next clear
       }
     };
     if (compact) windows(std::integral_constant<bool, true>{});

@@ -619,3 +619,21 @@ def test_dense_entry_widths(ctx):
     with _tuned(ctx, dense_ratio=8):
         run_hierarchy_parity(ctx, g, lim, max_levels=3, census=census, verbose=True)
     assert census[9] >= 12000
+
+
+@pytest.mark.parametrize("delta", [1 << 30, 600], ids=["scores", "overlap"])
+def test_dense_vertex_segments(ctx, delta):
+    """Four hubs that 3,000 of 30,000 axons reach (about 3,000 incident
+    hyperedges each, more than the 1,024 a dense work-group holds at once),
+    scored in dense windows in three segments of incident hyperedges that
+    share one table (with Delta = 600 the overlap enters, list 9).  Three
+    levels against the oracle."""
+    g = synth.hub_graph(3, 30000, 20, 4, 0.1)
+    L0 = oracle.level0(g)
+    lim = synth.Limits(512, 65536, delta)
+    deg = np.bincount((L0.pins & 0x7FFFFFFF).astype(np.int64), minlength=L0.V)
+    b = hgcheck.score_buckets(L0, lim, dense_ratio=8)
+    hubs = deg > 2048
+    assert hubs.sum() == 4 and np.all(b[hubs] == (9 if delta < (1 << 30) else 8))
+    with _tuned(ctx, dense_ratio=8):
+        run_hierarchy_parity(ctx, g, lim, max_levels=3, verbose=True)
