@@ -432,9 +432,16 @@ void level_step(hg_batch* b, int from, int to) {
   LevelView L{F.dims, F.eoff, F.pins, F.w, F.mult, F.size, F.syn, F.ax, F.gid};
   build_incidence(L, V, E, P, S.vcount, S.voff, S.vinc, S.partials, s, S.inc);
   Buckets bk{S.bcount, S.blist, S.bvisits};
-  expansion_and_buckets(L, S.voff, S.vinc, V, S.xn, b->gc, b->max_graphs, bk, c->tuning, s);
+  expansion_and_buckets(L, S.voff, S.vinc, V, S.xn, b->gc, b->max_graphs, bk, c->tuning, s,
+                        S.n_win14);
   ScoreArgs sa{L,  S.voff, S.vinc, S.xn,      b->gc, S.cursor,         b->cand,
                b->cscore, S.work, bk, c->dev_err, c->tuning.fill16};
+  // aligned and dense windows over the union's ids, where the capacity
+  // allows their split tables
+  sa.splits = S.splits;
+  sa.n_win = S.n_win;
+  sa.splits14 = S.splits14;
+  sa.n_win14 = S.n_win14;
   score_candidates(sa, V, P, s);
   MatchArgs ma{F.dims, b->cand, b->cscore, S.bkey, S.jump, S.jump, S.flags, b->match, b->vmap,
                S.rep, S.rank, S.partials, b->n_coarse, b->any_cand};

@@ -121,6 +121,19 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
     const uint32_t n = (uint32_t)v.n;
     const int64_t deg = v.deg;
     uint64_t best = 0;
+    // the id range of n's neighbourhood (first and last pins of its incident
+    // hyperedges; pins ascend): windows outside it hold no visit (a graph of
+    // a batch occupies one id range of the union)
+    uint32_t idmin = 0xFFFFFFFFu, idmax = 0;
+    for (int64_t j = tid; j < deg; j += THREADS) {
+      const uint32_t e = a.vinc[v.beg + j] & kIdMask;
+      const int64_t e0 = a.L.eoff[e], e1 = a.L.eoff[e + 1];
+      const uint32_t f = a.L.pins[e0] & kIdMask, l = a.L.pins[e1 - 1] & kIdMask;
+      idmin = f < idmin ? f : idmin;
+      idmax = l > idmax ? l : idmax;
+    }
+    idmax = (uint32_t)block_max_u64<THREADS>(idmax, S.red);
+    idmin = ~(uint32_t)block_max_u64<THREADS>((uint64_t)(~idmin), S.red);
     // bounds of a score (S_n) and of an overlap (M_n), for the entry width
     int32_t ob = 0;  // overlap bits of a compact entry
     bool compact = true;
@@ -146,6 +159,8 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
       constexpr bool C = decltype(compact_tag)::value;
       constexpr int kBits = C ? kDenseBits + 1 : kDenseBits;
       const int32_t nw = C ? (Wl + 1) / 2 : Wl;
+      const int32_t w_lo = deg > 0 ? (int32_t)(idmin >> kBits) : 0;
+      const int32_t w_hi = deg > 0 ? (int32_t)(idmax >> kBits) + 1 : 0;  // exclusive
       const uint32_t omask = C ? ((1u << ob) - 1u) : 0xFFFFFFFFu;
       // split-table bounds of window wi (two 2^14 windows when compact)
       auto bounds = [&](const uint32_t* sr, int32_t wi, uint32_t& b0, uint32_t& b1) {
@@ -157,7 +172,7 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
           b1 = sr[wi + 1];
         }
       };
-      for (int32_t wi = 0; wi < nw; ++wi) {  // block-uniform
+      for (int32_t wi = w_lo; wi < nw && wi < w_hi; ++wi) {  // block-uniform
         const uint32_t lo = (uint32_t)wi << kBits;
         bool cleared = false;  // block-uniform: the table is cleared before the first sweep
         // segments of THREADS incident hyperedges; thread t holds hyperedge
