@@ -191,15 +191,18 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def _pack(sizes, cap_pins):
-    """Consecutive groups whose pin totals stay within cap_pins."""
-    groups, cur, tot = [], [], 0
+def _pack(sizes, cap_pins, vsizes=None, cap_vertices=None):
+    """Consecutive groups whose pin totals stay within cap_pins (and vertex
+    totals within cap_vertices)."""
+    groups, cur, tot, vtot = [], [], 0, 0
     for i, p in enumerate(sizes):
-        if cur and tot + p > cap_pins:
+        v = vsizes[i] if vsizes is not None else 0
+        if cur and (tot + p > cap_pins or (cap_vertices and vtot + v > cap_vertices)):
             groups.append(cur)
-            cur, tot = [], 0
+            cur, tot, vtot = [], 0, 0
         cur.append(i)
         tot += p
+        vtot += v
     if cur:
         groups.append(cur)
     return groups
@@ -210,8 +213,8 @@ def run_batch(args):
     neuron count log-uniform in [10k, 500k), fan-out U{16..256}, weights
     U{1..100}, limits 512/32768/2048 per graph.
 
-    (a) one level of every graph, batched (graphs packed into unions below
-    2^31 pins, one union step each) vs plain (hg_coarsen_level + hg_contract
+    (a) one level of every graph, batched (graphs packed into unions of at
+    most 2^21 vertices and below 2^31 pins, one union step each) vs plain (hg_coarsen_level + hg_contract
     per graph); the score-step tuning is autotuned first and used by both;
     (b) whole hierarchies of two size-scaled copies of the distribution
     (neurons in [1k, 20k) with the full fan-out range, and [500, 5000) with
@@ -261,7 +264,9 @@ def run_batch(args):
     t_plain = time.perf_counter() - t0
     _log(f"plain: one level of {len(levels)} graphs in {t_plain:.3f} s")
 
-    groups = _pack([L.P for L in levels], (1 << 31) - 1)
+    # unions of at most 2^21 vertices, the largest level the dense score
+    # windows cover (and below 2^31 pins)
+    groups = _pack([L.P for L in levels], (1 << 31) - 1, [L.V for L in levels], 1 << 21)
     capV = max(sum(levels[i].V for i in gr) for gr in groups)
     capE = max(sum(levels[i].E for i in gr) for gr in groups)
     capP = max(sum(levels[i].P for i in gr) for gr in groups)
@@ -631,7 +636,7 @@ def run_serve(args):
     which = np.where(big, n_small + rng.integers(0, n_big, n_req),
                      rng.integers(0, n_small, n_req))
     if full:
-        srv = serve.Server(ctx, max_graphs=256, cap_vertices=4_000_000, cap_edges=4_000_000,
+        srv = serve.Server(ctx, max_graphs=256, cap_vertices=1 << 21, cap_edges=4_000_000,
                            cap_pins=640_000_000, levels_per_step=4, use_graph=True)
     else:
         srv = serve.Server(ctx, max_graphs=1024, cap_vertices=2_000_000, cap_edges=2_000_000,

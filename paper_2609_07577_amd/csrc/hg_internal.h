@@ -130,7 +130,7 @@ void exclusive_scan_i64(const int64_t* in, int64_t* out, const int64_t* count,
 // counters.
 constexpr int kIncBits = 13;
 constexpr int kIncBuckets = 4096;
-constexpr int kIncMinBuckets = 256;
+constexpr int kIncMinBuckets = 1024;
 constexpr int kIncBlocks = 1024;
 struct IncScratch {
   uint64_t* pairs = nullptr;  // [P] (vertex << 32 | entry); may alias other scratch
