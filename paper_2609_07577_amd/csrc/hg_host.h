@@ -169,7 +169,7 @@ struct CoarsenScratch {
     bvisits = a.template take<int64_t>(kNumBuckets);
     work = a.template take<int32_t>(kNumBuckets);
     cursor = a.template take<int32_t>(2 * P);
-    inc = incidence_scratch_carve(a, V, reinterpret_cast<uint64_t*>(cursor));
+    inc = incidence_scratch_carve(a, V, P, reinterpret_cast<uint64_t*>(cursor));
     cand = a.template take<int32_t>(V);
     cscore = a.template take<int32_t>(V);
     bkey = a.template take<uint64_t>(V);
@@ -220,8 +220,8 @@ struct ContractLayout {
     cs.partials = a.template take<int64_t>(scan_partials_size());
     cs.bitmap_words = (V + 31) / 32 + 1;
     cs.bitmap = a.template take<uint32_t>((int64_t)kHugeWG * 2 * cs.bitmap_words);
-    uint64_t* pairs = a.template take<uint64_t>(P);
-    cs.inc = incidence_scratch_carve(a, V, pairs);
+    uint64_t* pairs = P >= kIncMinPins ? a.template take<uint64_t>(P) : nullptr;
+    cs.inc = incidence_scratch_carve(a, V, P, pairs);
   }
 };
 

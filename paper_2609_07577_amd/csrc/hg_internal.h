@@ -147,13 +147,17 @@ __host__ __device__ inline int incidence_bits(int64_t V) {
 // the most buckets a level of at most maxV vertices can use
 inline int64_t incidence_buckets(int64_t maxV) {
   const int64_t wide = (maxV + (1ll << kIncBits) - 1) >> kIncBits;
-  return wide > kIncMinBuckets ? wide : (maxV > 0 ? kIncMinBuckets : 0);
+  if (wide > kIncMinBuckets) return wide;
+  return maxV < kIncMinBuckets ? maxV : kIncMinBuckets;
 }
+// Levels of fewer than kIncMinPins pins keep the atomic path (and need no
+// bucket arrays).
+constexpr int64_t kIncMinPins = 1 << 20;
 template <typename A>
-IncScratch incidence_scratch_carve(A& a, int64_t maxV, uint64_t* pairs) {
+IncScratch incidence_scratch_carve(A& a, int64_t maxV, int64_t maxP, uint64_t* pairs) {
   IncScratch s;
   const int64_t nb = incidence_buckets(maxV);
-  if (nb < 1 || nb > kIncBuckets) return s;
+  if (nb < 1 || nb > kIncBuckets || maxP < kIncMinPins) return s;
   s.pairs = pairs;
   s.boff = a.template take<int64_t>(nb * kIncBlocks + 1);
   s.bcnt = a.template take<int32_t>(nb * kIncBlocks);
