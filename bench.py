@@ -60,7 +60,8 @@ WORKLOADS = {
 
 # The score kernel of each work list of the library's bucket rule (lists 4-7
 # and 9 also count shared inbound axons); lists 2 and 6 use the aligned-window
-# variant on levels of at most 16 windows of 2^19 ids.
+# variants on levels of at most 16 windows of 2^19 ids (with 16-byte body
+# loads unless the tuning's wide_loads is 0).
 SCORE_KERNELS = (
     "score_block_kernel<256,4096>", "score_block_kernel<512,16384>",
     "score_window_kernel<1024>", "score_block_kernel<512,16384,multipass>",
@@ -105,7 +106,8 @@ def read_traffic(workload):
         return None
     with open(path) as f:
         d = json.load(f)
-    cur = source_hash(os.path.join(ROOT, "paper_2609_07577_amd", "csrc", "hg_score.hip"))
+    src = d.get("source_file", "paper_2609_07577_amd/csrc/hg_score.hip")
+    cur = source_hash(os.path.join(ROOT, src))
     if d.get("source_hash") != cur:
         return None
     return d.get("bytes_per_launch")
@@ -890,8 +892,10 @@ def main():
     n_by_list, visits_by_list = ctx.score_census()
     top = int(np.argmax(visits_by_list))
     kernel = SCORE_KERNELS[top]
-    if top in (2, 6) and V <= (16 << 19):
-        kernel = "score_window2_kernel<1024%s>" % (",overlap" if top == 6 else "")
+    if top in (2, 6) and V <= (16 << 19):  # aligned windows (pins of torch tensors: 16-byte aligned)
+        wide = ctx.get_tuning()["wide_loads"]
+        kernel = "%s<1024%s>" % ("score_wide_kernel" if wide else "score_window2_kernel",
+                                 ",overlap" if top == 6 else "")
     value = P / (ms_step / 1000.0)
     b_s2 = s2_bytes(V, E, P, X)
     t_s2 = phases["score"] / 1000.0

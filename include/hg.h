@@ -297,14 +297,18 @@ int hg_connectivity_static(hg_ctx* ctx, const hg_level* lvl, const int32_t* part
  * windows of neighbour ids with an on-chip bitmap of seen ids (at most 768
  * incident hyperedges), else in passes over a table, each range aimed at
  * pass_fill16/16 of it where the distinct-axon overlap of Section 3 can
- * bind.  Results never depend on these values, only the speed does.
- * Defaults 8, 5 and 8; accepted ranges 1..12, 1..10 and 0..64
+ * bind.  On levels whose id windows are aligned (at most 16 windows of 2^19
+ * ids) and whose pins are 16-byte aligned, wide_loads = 1 reads the long
+ * slices of the windows 16 bytes per lane; 0 reads one pin per lane.
+ * Results never depend on these values, only the speed does.
+ * Defaults 8, 5, 8 and 1; accepted ranges 1..12, 1..10, 0..64 and 0..1
  * (HG_ERR_INVALID_ARG otherwise).
  */
 typedef struct {
   int32_t single_pass_load16;
   int32_t pass_fill16;
   int32_t dense_ratio;
+  int32_t wide_loads;
 } hg_tuning;
 int hg_set_tuning(hg_ctx* ctx, const hg_tuning* tuning);
 int hg_get_tuning(hg_ctx* ctx, hg_tuning* tuning);

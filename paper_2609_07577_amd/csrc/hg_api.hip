@@ -240,9 +240,12 @@ int hg_set_tuning(hg_ctx* c, const hg_tuning* t) {
     return fail(c, HG_ERR_INVALID_ARG, "pass_fill16 %d outside 1..10", t->pass_fill16);
   if (t->dense_ratio < 0 || t->dense_ratio > 64)
     return fail(c, HG_ERR_INVALID_ARG, "dense_ratio %d outside 0..64", t->dense_ratio);
+  if (t->wide_loads < 0 || t->wide_loads > 1)
+    return fail(c, HG_ERR_INVALID_ARG, "wide_loads %d outside 0..1", t->wide_loads);
   c->tuning.load16 = t->single_pass_load16;
   c->tuning.fill16 = t->pass_fill16;
   c->tuning.dense_ratio = t->dense_ratio;
+  c->tuning.wide = t->wide_loads;
   return HG_OK;
 }
 
@@ -251,6 +254,7 @@ int hg_get_tuning(hg_ctx* c, hg_tuning* t) {
   t->single_pass_load16 = c->tuning.load16;
   t->pass_fill16 = c->tuning.fill16;
   t->dense_ratio = c->tuning.dense_ratio;
+  t->wide_loads = c->tuning.wide;
   return HG_OK;
 }
 
@@ -343,6 +347,7 @@ int hg_coarsen_level(hg_ctx* c, const hg_level* in, const hg_limits* lim, int32_
   sa.n_win = S.n_win;
   sa.splits14 = S.splits14;
   sa.n_win14 = S.n_win14;
+  sa.wide = c->tuning.wide;
   mark(c, 1, 0);
   score_candidates(sa, V, P, s);
   mark(c, 1, 1);

@@ -436,6 +436,7 @@ void level_step(hg_batch* b, int from, int to) {
                         S.n_win14);
   ScoreArgs sa{L,  S.voff, S.vinc, S.xn,      b->gc, S.cursor,         b->cand,
                b->cscore, S.work, bk, c->dev_err, c->tuning.fill16};
+  sa.wide = c->tuning.wide;
   // aligned and dense windows over the union's ids, where the capacity
   // allows their split tables
   sa.splits = S.splits;
@@ -629,7 +630,9 @@ int hg_batch_step(hg_batch* b, int32_t n_levels, int32_t use_graph) {
   hipStream_t s = c->stream;
   if (use_graph) {
     if (b->exec[0] && (b->captured_tuning.load16 != c->tuning.load16 ||
-                       b->captured_tuning.fill16 != c->tuning.fill16))
+                       b->captured_tuning.fill16 != c->tuning.fill16 ||
+                       b->captured_tuning.dense_ratio != c->tuning.dense_ratio ||
+                       b->captured_tuning.wide != c->tuning.wide))
       drop_graphs(b);
     if (!b->exec[0]) {
       // capture on a private stream (the context's may be the null stream,

@@ -53,6 +53,7 @@ struct Tuning {
   int32_t load16 = 8;  // single-pass tables take X_n up to load16/16 of their slots
   int32_t fill16 = 5;  // multipass ranges aim at fill16/16 of the stream table
   int32_t dense_ratio = 8;  // dense windows for X_n * dense_ratio >= V (0: never)
+  int32_t wide = 1;         // aligned windows with 16-byte body loads (0: one pin per lane)
 };
 
 // Device views of a level.
@@ -229,6 +230,7 @@ struct ScoreArgs {
   // The same at the dense windows of kDenseBits bits (n_win14 = 0: none).
   uint32_t* splits14 = nullptr;
   int32_t n_win14 = 0;
+  int32_t wide = 1;  // Tuning::wide
 };
 constexpr int kWinAlignBits = 19;
 constexpr int kMaxAlignedWindows = 16;
@@ -236,6 +238,10 @@ void score_candidates(const ScoreArgs& a, int64_t maxV, int64_t maxP, hipStream_
 // Dense-window scoring of work lists 8 and 9 (hg_score_dense.hip); called by
 // score_candidates, a no-op on levels without dense windows.
 void score_dense(const ScoreArgs& a, int64_t maxV, hipStream_t s);
+// Aligned-window scoring of work list `bucket` (2, or 6 with the overlap)
+// with 16-byte body loads (hg_score_wide.hip); false when the level has no
+// aligned windows or its pins are not 16-byte aligned (nothing launched).
+bool score_wide(const ScoreArgs& a, int bucket, bool ov, int64_t maxV, hipStream_t s);
 
 // ---- S3-S5 (hg_match.hip) ---------------------------------------------------
 struct MatchArgs {

@@ -1733,15 +1733,16 @@ void score_candidates(const ScoreArgs& a, int64_t maxV, int64_t maxP, hipStream_
     }
     window_splits_kernel<<<4096, 256, 0, s>>>(a.L.dims, a.L.eoff, a.L.pins, a.n_win,
                                               a.splits);
-    k2w<<<g2[dev][0], 1024, 0, s>>>(a, 2, maxV);
+    if (!(a.wide && score_wide(a, 2, false, maxV, s))) k2w<<<g2[dev][0], 1024, 0, s>>>(a, 2, maxV);
   } else {
     k2<<<g[2], 1024, 0, s>>>(a, 2, maxV);
   }
   k3<<<g[3], 512, 0, s>>>(a, 3, maxV, maxP);
   k4<<<g[4], 256, 0, s>>>(a, 4, maxV, maxP);
   k5<<<g[5], 512, 0, s>>>(a, 5, maxV, maxP);
-  if (aligned)
-    k6w<<<g2[dev][1], 1024, 0, s>>>(a, 6, maxV);
+  if (aligned) {
+    if (!(a.wide && score_wide(a, 6, true, maxV, s))) k6w<<<g2[dev][1], 1024, 0, s>>>(a, 6, maxV);
+  }
   else
     k6<<<g[6], 1024, 0, s>>>(a, 6, maxV);
   score_dense(a, maxV, s);

@@ -56,7 +56,8 @@ class Limits(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     """Score-step tuning (hg_tuning): results never depend on it."""
-    _fields_ = [("single_pass_load16", _i32), ("pass_fill16", _i32), ("dense_ratio", _i32)]
+    _fields_ = [("single_pass_load16", _i32), ("pass_fill16", _i32), ("dense_ratio", _i32),
+                ("wide_loads", _i32)]
 
 
 class _Level(ctypes.Structure):
@@ -198,15 +199,15 @@ class Context:
         return int(self.lib.hg_scratch_bytes(self.h))
 
     def set_tuning(self, single_pass_load16: int = 8, pass_fill16: int = 5,
-                   dense_ratio: int = 8):
-        t = Tuning(single_pass_load16, pass_fill16, dense_ratio)
+                   dense_ratio: int = 8, wide_loads: int = 1):
+        t = Tuning(single_pass_load16, pass_fill16, dense_ratio, wide_loads)
         self._check(self.lib.hg_set_tuning(self.h, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
         t = Tuning()
         self._check(self.lib.hg_get_tuning(self.h, ctypes.byref(t)))
         return dict(single_pass_load16=t.single_pass_load16, pass_fill16=t.pass_fill16,
-                    dense_ratio=t.dense_ratio)
+                    dense_ratio=t.dense_ratio, wide_loads=t.wide_loads)
 
     def score_census(self) -> tuple[list[int], list[int]]:
         """(vertices, neighbour visits) per score work list of the last level."""

@@ -181,8 +181,9 @@ class _tuned:
         self.ctx.set_tuning(**self.old)
 
 
-@pytest.mark.parametrize("dense_ratio", [0, 8], ids=["windows", "dense"])
-def test_overlap_kernels_hub_levels(ctx, dense_ratio):
+@pytest.mark.parametrize("dense_ratio,wide", [(0, 1), (0, 0), (8, 1)],
+                         ids=["windows", "windows-narrow", "dense"])
+def test_overlap_kernels_hub_levels(ctx, dense_ratio, wide):
     """Levels where the distinct-axon bound of Section 3 binds with thousands
     of distinct neighbours: 12,000 neurons, each axon reaching 100 random
     neurons, plus 8 hubs that about 900 axons reach; Delta = 1000, so every
@@ -195,7 +196,7 @@ def test_overlap_kernels_hub_levels(ctx, dense_ratio):
     against the oracle, element by element."""
     g = synth.hub_graph(1, 12000, 100, 8, 0.075)
     census = np.zeros(10, np.int64)
-    with _tuned(ctx, dense_ratio=dense_ratio):
+    with _tuned(ctx, dense_ratio=dense_ratio, wide_loads=wide):
         run_hierarchy_parity(ctx, g, synth.Limits(512, 65536, 1000), max_levels=6,
                              census=census, verbose=True)
     print(f"  census {census.tolist()}", flush=True)
@@ -342,28 +343,30 @@ def test_tuning_never_changes_results(ctx):
     L = ctx.upload(g)
     seen = {}
     try:
-        for load, fill, dr in ((8, 5, 0), (1, 1, 0), (12, 10, 4), (4, 3, 16), (1, 10, 0),
-                               (8, 5, 8), (1, 1, 64)):
-            ctx.set_tuning(load, fill, dr)
+        for load, fill, dr, wide in ((8, 5, 0, 1), (1, 1, 0, 1), (12, 10, 4, 1), (4, 3, 16, 1),
+                                     (1, 10, 0, 1), (8, 5, 8, 1), (1, 1, 64, 1), (8, 5, 0, 0),
+                                     (1, 1, 0, 0)):
+            ctx.set_tuning(load, fill, dr, wide)
             out = ctx.coarsen_level(L, lim)
             ctx.sync()
             nv, _ = ctx.score_census()
             b = hgcheck.score_buckets(OL, lim, load16=load, dense_ratio=dr)
             assert nv == np.bincount(b[b >= 0], minlength=10).tolist(), (load, dr, nv)
-            seen[(load, fill, dr)] = tuple(nv)
+            seen[(load, fill, dr, wide)] = tuple(nv)
             for k, ref in (("cand", expect.cand), ("cscore", expect.cscore),
                            ("match", expect.match), ("vmap", expect.vmap)):
                 np.testing.assert_array_equal(_np(out[k]), ref,
-                                              err_msg=f"{k} tuning {load}/{fill}/{dr}")
-        for bad in ((0, 5, 8), (13, 5, 8), (8, 0, 8), (8, 11, 8), (8, 5, -1), (8, 5, 65)):
+                                              err_msg=f"{k} tuning {load}/{fill}/{dr}/{wide}")
+        for bad in ((0, 5, 8, 1), (13, 5, 8, 1), (8, 0, 8, 1), (8, 11, 8, 1), (8, 5, -1, 1),
+                    (8, 5, 65, 1), (8, 5, 8, 2), (8, 5, 8, -1)):
             with pytest.raises(hg.HgError):
                 ctx.set_tuning(*bad)
     finally:
         ctx.set_tuning(8, 5, 8)
     print(f"  census per setting {seen}", flush=True)
     assert len(set(seen.values())) >= 4, "the settings did not move vertices between lists"
-    assert seen[(1, 1, 0)][2] > 1000 and seen[(1, 1, 0)][6] > 1000  # windows, overlap passes
-    assert seen[(1, 1, 64)][8] > 1000 and seen[(1, 1, 64)][9] > 1000  # dense windows
+    assert seen[(1, 1, 0, 1)][2] > 1000 and seen[(1, 1, 0, 1)][6] > 1000  # windows, overlap passes
+    assert seen[(1, 1, 64, 1)][8] > 1000 and seen[(1, 1, 64, 1)][9] > 1000  # dense windows
 
 
 def test_out_of_range_maps_are_rejected(ctx):
@@ -422,14 +425,16 @@ def _window_bucket_vertices(g, lim=synth.LIMITS["powerlaw"], load16=8, dense_rat
     return np.flatnonzero(b == 2) if dense_ratio == 0 else np.flatnonzero(b >= 8)
 
 
-# The large-neighbourhood cases run twice: scored in windows of the id range
-# (the dense route off) and in dense windows (every vertex that visits at
-# least one id in 64 of the level).
-ROUTES = pytest.mark.parametrize("dense_ratio", [0, 64], ids=["windows", "dense"])
+# The large-neighbourhood cases run three times: scored in windows of the id
+# range (the dense route off) with the long slices read 16 bytes per lane,
+# the same with one pin per lane, and in dense windows (every vertex that
+# visits at least one id in 64 of the level).
+ROUTES = pytest.mark.parametrize("dense_ratio,wide", [(0, 1), (0, 0), (64, 1)],
+                                 ids=["windows", "windows-narrow", "dense"])
 
 
 @ROUTES
-def test_window_list_overflow_halves_the_window(ctx, dense_ratio):
+def test_window_list_overflow_halves_the_window(ctx, dense_ratio, wide):
     """Every neighbour of the 9000 targets is shared by four hyperedges, so a
     window of the multipass score step holds three repeat visits per id and
     overflows its list of repeat visits until the window is narrowed to a
@@ -438,12 +443,12 @@ def test_window_list_overflow_halves_the_window(ctx, dense_ratio):
     axons = [(nt + i, list(range(nt)), w) for i, w in enumerate((3, 5, 2, 7))]
     g = synth.from_axons(nt + 4, axons)
     assert len(_window_bucket_vertices(g, dense_ratio=dense_ratio)) >= nt
-    with _tuned(ctx, dense_ratio=dense_ratio):
+    with _tuned(ctx, dense_ratio=dense_ratio, wide_loads=wide):
         run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
 
 
 @ROUTES
-def test_window_slice_runs_past_its_estimate(ctx, dense_ratio):
+def test_window_slice_runs_past_its_estimate(ctx, dense_ratio, wide):
     """Three hyperedges whose pins are 4000 consecutive low ids plus one id
     near the top of a 600,000-vertex level: the id-density estimate of a
     window's slice falls far short, so the kernel must continue the slice
@@ -454,12 +459,12 @@ def test_window_slice_runs_past_its_estimate(ctx, dense_ratio):
     axons.append((n - 1, sorted(set(range(0, n - 20, 997)) - {n - 1}), 2))
     g = synth.from_axons(n, axons)
     assert len(_window_bucket_vertices(g, dense_ratio=dense_ratio)) >= 4000
-    with _tuned(ctx, dense_ratio=dense_ratio):
+    with _tuned(ctx, dense_ratio=dense_ratio, wide_loads=wide):
         run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
 
 
 @ROUTES
-def test_window_degree_limit(ctx, dense_ratio):
+def test_window_degree_limit(ctx, dense_ratio, wide):
     """Two large neighbourhoods on either side of the window kernel's limit
     on incident hyperedges: vertex 0 is a target of 768 axons (scored in
     windows), vertex 1 of 769 (scored by the global multipass kernel); each
@@ -479,13 +484,13 @@ def test_window_degree_limit(ctx, dense_ratio):
         assert 0 in wb and 1 in wb
     else:
         assert 0 in wb and 1 not in wb
-    with _tuned(ctx, dense_ratio=dense_ratio):
+    with _tuned(ctx, dense_ratio=dense_ratio, wide_loads=wide):
         run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
 
 
 @ROUTES
 @pytest.mark.parametrize("weights", [(1,), (1, 2)], ids=["equal", "two-valued"])
-def test_window_random_neighbourhoods_few_weights(ctx, weights, dense_ratio):
+def test_window_random_neighbourhoods_few_weights(ctx, weights, dense_ratio, wide):
     """Large random neighbourhoods whose hyperedges share few weight values:
     1250 axons of 400 random targets over 20,000 neurons (about 25 axons
     reach each neuron, 16,000 of which are scored in windows), weights all 1
@@ -500,7 +505,7 @@ def test_window_random_neighbourhoods_few_weights(ctx, weights, dense_ratio):
         axons.append((src, sorted(int(x) for x in t), int(rng.choice(weights))))
     g = synth.from_axons(n, axons)
     assert len(_window_bucket_vertices(g, dense_ratio=dense_ratio)) >= 15_000
-    with _tuned(ctx, dense_ratio=dense_ratio):
+    with _tuned(ctx, dense_ratio=dense_ratio, wide_loads=wide):
         run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=3, verbose=True)
 
 
@@ -538,7 +543,7 @@ def _disjoint_neighbourhoods(seed, n, hubs, k, fan, heavy):
 
 @ROUTES
 @pytest.mark.parametrize("heavy", [False, True], ids=["equal", "heavy-late"])
-def test_window_lowest_id_single(ctx, heavy, dense_ratio):
+def test_window_lowest_id_single(ctx, heavy, dense_ratio, wide):
     """Hubs scored in windows (600,000 ids, two windows) whose neighbours
     are all singles (disjoint target sets): the candidate is decided by the
     lowest id among the batches of the heaviest weight, spread over many
@@ -563,7 +568,7 @@ def test_window_lowest_id_single(ctx, heavy, dense_ratio):
         assert r0.cscore[h] == best_w
         if heavy:
             assert r0.cand[h] > min(v for v, _ in nb)
-    with _tuned(ctx, dense_ratio=dense_ratio):
+    with _tuned(ctx, dense_ratio=dense_ratio, wide_loads=wide):
         run_hierarchy_parity(ctx, g, synth.LIMITS["powerlaw"], max_levels=2, verbose=True)
 
 

@@ -26,12 +26,13 @@ def test_binding_has_no_cpu_fallback():
 
 
 def test_tuning_struct_layout_matches_header():
-    """hg_tuning is three int32 fields in the order the header declares."""
+    """hg_tuning is four int32 fields in the order the header declares."""
     from paper_2609_07577_amd import hg
     assert [f[0] for f in hg.Tuning._fields_] == ["single_pass_load16", "pass_fill16",
-                                                  "dense_ratio"]
+                                                  "dense_ratio", "wide_loads"]
     hdr = open(os.path.join(ROOT, "include", "hg.h")).read()
     body = hdr[hdr.index("typedef struct {\n  int32_t single_pass_load16;"):]
     body = body[:body.index("} hg_tuning;")]
+    assert body.count("int32_t") == 4
     assert body.index("single_pass_load16") < body.index("pass_fill16") < \
-        body.index("dense_ratio")
+        body.index("dense_ratio") < body.index("wide_loads")
