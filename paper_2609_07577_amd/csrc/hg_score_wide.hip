@@ -122,8 +122,10 @@ __global__ __launch_bounds__(THREADS) void score_wide_kernel(ScoreArgs a, int bu
     // thread j owns incident hyperedge j: its weight, the cursor of the
     // unprocessed part of its slice and the slice's end at the next aligned
     // window boundary (loaded one window ahead)
+    // (the split value is kept as loaded and added only where it is used, a
+    // window later: an add right after the load would wait for it there)
     const bool owner = tid < deg;
-    uint32_t e_j = 0, cur = 0, base_j = 0, wend_next = 0;
+    uint32_t e_j = 0, cur = 0, base_j = 0, split_next = 0;
     int32_t w_j = 0, mu_j = 0;
     const uint32_t* srow = nullptr;
     if (owner) {
@@ -138,15 +140,15 @@ __global__ __launch_bounds__(THREADS) void score_wide_kernel(ScoreArgs a, int bu
         S.m_mu[tid] = mu_j;
       }
       srow = a.splits + (int64_t)e_j * (W + 1);
-      wend_next = base_j + srow[1];
+      split_next = srow[1];
     }
     int passes = 0;
     bool stop = false;  // a bound was reached: the vertex keeps no candidate
     for (int32_t wi = 0; wi < W && !stop; ++wi) {  // block-uniform
       const uint32_t W0 = (uint32_t)wi << kWinAlignBits;
       const uint32_t W1 = W0 + kWinIds;
-      const uint32_t wend = wend_next;
-      if (owner && wi + 1 < W) wend_next = base_j + srow[wi + 2];
+      const uint32_t wend = base_j + split_next;
+      if (owner && wi + 1 < W) split_next = srow[wi + 2];
       // the slice's first pin, tested for a single after sweep 1
       uint32_t first_pin = 0;
       if (owner && cur < wend) first_pin = a.L.pins[cur];
