@@ -128,13 +128,15 @@ def _edge_subset(OL, frac, rng):
                          OL.mult[keep].copy(), OL.size, OL.syn, OL.soff, OL.sids)
 
 
-def cpu_baseline(g, lim, X, P, seconds, gpu_cand, gpu_cscore, gpu_vmap, n_coarse):
+def cpu_baseline(g, lim, X, P, seconds):
     """The oracle's time for the whole level, every step timed on a bounded
     sample and scaled to the level: candidates (Eq. 12) for a seeded vertex
     sample, scaled by neighbour visits; the incidence build in full;
-    matching (Eq. 13) and the vertex map in full (on the GPU's candidates,
-    equal to the oracle's); the contraction on two seeded hyperedge subsets
-    (4% and 8% of the hyperedges, every vertex), scaled linearly in pins."""
+    matching (Eq. 13) and the vertex map over all vertices, on the oracle's
+    candidates of the sample (no candidate elsewhere: the step's cost is
+    linear in the vertices); the contraction under that vertex map on two
+    seeded hyperedge subsets (4% and 8% of the hyperedges, every vertex),
+    scaled linearly in pins.  Every input is the oracle's own."""
     import oracle
     oracle.build(force=False)
     nthreads = len(os.sched_getaffinity(0))
@@ -155,20 +157,23 @@ def cpu_baseline(g, lim, X, P, seconds, gpu_cand, gpu_cscore, gpu_vmap, n_coarse
     q = np.sort(rng.choice(g.n_vertices, n, replace=False)).astype(np.int32)
     secs = np.zeros(2, np.float64)
     t0 = time.perf_counter()
-    oracle.candidates(OL, lim, query=q, nthreads=nthreads, seconds=secs)
+    qc, qs = oracle.candidates(OL, lim, query=q, nthreads=nthreads, seconds=secs)
     t_cand_wall = time.perf_counter() - t0
     t_setup, t_vert = float(secs[0]), max(float(secs[1]), 1e-6)
     xs = float(xn[q].sum())
     t_cand = t_vert * (X / xs)
+    cand = np.full(g.n_vertices, -1, np.int32)
+    cscore = np.zeros(g.n_vertices, np.int32)
+    cand[q], cscore[q] = qc, qs
     t0 = time.perf_counter()
-    m = oracle.match(gpu_cand, gpu_cscore)
+    m = oracle.match(cand, cscore)
     vmap, nc = oracle.vmap_from_match(m)
     t_match = time.perf_counter() - t0
     timed = []
     for frac in (0.04, 0.08):
         sub = _edge_subset(OL, frac, rng)
         t0 = time.perf_counter()
-        oracle.contract(sub, gpu_vmap, n_coarse)
+        oracle.contract(sub, vmap, nc)
         timed.append((sub.P, time.perf_counter() - t0))
     (p1, t1), (p2, t2) = timed
     slope = max(0.0, (t2 - t1) / max(1, p2 - p1))
@@ -182,7 +187,8 @@ def cpu_baseline(g, lim, X, P, seconds, gpu_cand, gpu_cscore, gpu_vmap, n_coarse
         "sample": (f"oracle level 0 scaled from samples: candidates of {n} seeded vertices "
                    f"({xs:.3g} of {X:.3g} neighbour visits, {t_cand_wall:.1f} s incl. "
                    f"{t_setup:.1f} s incidence build) scaled by visits to {t_cand:.0f} s; "
-                   f"matching and vertex map over all vertices {t_match:.1f} s; contraction of "
+                   f"matching and vertex map over all vertices (on the sample's candidates) "
+                   f"{t_match:.1f} s; contraction of "
                    f"{p1} and {p2} pins ({t1:.1f} s, {t2:.1f} s) scaled linearly to {P} pins: "
                    f"{t_contract:.0f} s; {t_level:.0f} s per level on {nthreads} threads "
                    f"(candidate step parallel, the rest sequential)"),
@@ -934,12 +940,7 @@ def main():
     if not args.no_cpu_baseline and args.start_level == 0:
         print("[bench] timing the CPU oracle on samples of every step", file=sys.stderr,
               flush=True)
-        full = ctx.coarsen_level(L, lim)
-        ctx.sync()
-        result["cpu_baseline"] = cpu_baseline(
-            g, lim, X, P, args.cpu_seconds, full["cand"].cpu().numpy(),
-            full["cscore"].cpu().numpy(), full["vmap"].cpu().numpy(),
-            int(full["n_coarse"].item()))
+        result["cpu_baseline"] = cpu_baseline(g, lim, X, P, args.cpu_seconds)
     print(json.dumps(result), flush=True)
 
 
