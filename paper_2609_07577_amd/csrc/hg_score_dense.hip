@@ -44,17 +44,16 @@ __global__ void dense_splits_kernel(const Dims* __restrict__ d, const int64_t* _
 }
 
 // Dense windows (neighbourhoods that visit at least one id in dense_ratio
-// of the level): per window of ids, one packed LDS entry per id holds the
-// id's (score, overlap) so far, and one sweep over the window's slices adds
-// the visit's (weight, overlap share) with one returning LDS atomic.  The
-// entry returned plus the visit's share is the id's (score, overlap) so
-// far; every id's last visit sees its totals, and scores and overlaps only
-// grow, so the best valid neighbour is the largest (score, -id) a lane sees
-// among valid ids, whatever the order of the visits: validity is tested
-// only for keys above the lane's best, with the overlap seen by that visit
-// (the test only gets easier as the overlap grows).  OV: the overlap share
-// of a visit is the hyperedge's multiplicity when n and the visited id both
-// carry its flag.
+// of the level): per window of ids, one packed LDS entry per id, and one
+// sweep over the window's slices adds each visit's (weight, overlap share)
+// to its id's entry with a non-returning LDS atomic (nothing in the sweep
+// waits for the LDS).  Then every thread reads the final (score, overlap)
+// of its own entries, takes the best valid (score, -id) among them (n left
+// out) and zeroes them for the next window: each id is tested for validity
+// at most once, with its exact totals, and only when its key beats the
+// thread's best and the vertex's threshold (a key some thread found valid).
+// OV: the overlap share of a visit is the hyperedge's multiplicity when n
+// and the visited id both carry its flag.
 //
 // Entry width per vertex: a score is at most S_n (the weight of n's
 // incident hyperedges) and an overlap at most M_n (their multiplicity where
@@ -79,6 +78,7 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
     uint4 desc[kMaxChunks + B];  // x first pin, y pin count, z weight, w overlap share
     int32_t ws[3 * NW];
     uint64_t red[2 * NW];
+    uint64_t thr;                // largest key found valid so far for the vertex
     int32_t s_item;
     int32_t s_next;
   };
@@ -100,6 +100,9 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
   uint4* const tab4 = reinterpret_cast<uint4*>(S.tab);
   uint32_t* const tab32 = reinterpret_cast<uint32_t*>(S.tab);
   const uint32_t lofs = (uint32_t)lane * 4u;
+  // the table starts zeroed; every window's scan zeroes the entries it read
+#pragma unroll
+  for (int i = 0; i < 8; ++i) tab4[8 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
 
   while (true) {
     __syncthreads();
@@ -121,6 +124,7 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
     const uint32_t n = (uint32_t)v.n;
     const int64_t deg = v.deg;
     uint64_t best = 0;
+    if (tid == 0) S.thr = 0;  // read after the barriers below
     // the id range of n's neighbourhood (first and last pins of its incident
     // hyperedges; pins ascend): windows outside it hold no visit (a graph of
     // a batch occupies one id range of the union)
@@ -200,11 +204,7 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
             __syncthreads();
             continue;
           }
-          if (!cleared) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) tab4[8 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
-            cleared = true;
-          }
+          cleared = true;
           for (int32_t r0 = 0; r0 < T; r0 += kMaxChunks) {  // block-uniform
             const int32_t Tr = T - r0 < kMaxChunks ? T - r0 : kMaxChunks;
             __syncthreads();  // table clear, previous round's chunks done
@@ -257,27 +257,15 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
 #pragma unroll
               for (int u = 0; u < B; ++u) {
                 const uint32_t id = pin[u] & kIdMask;
-                const bool act = lofs < (uint32_t)t.cnt[u] * 4u && id != n;
+                const bool act = lofs < (uint32_t)t.cnt[u] * 4u;
                 if (act) {  // no cross-lane operation inside
                   const uint32_t share = (OV && (pin[u] & kDst)) ? t.mu[u] : 0u;
-                  uint64_t sc;
-                  uint32_t ov;
                   if (C) {
-                    const uint32_t add = (t.wt[u] << ob) | share;
-                    const uint32_t now = atomicAdd(&tab32[id - lo], add) + add;
-                    sc = now >> ob;
-                    ov = now & omask;
+                    atomicAdd(&tab32[id - lo], (t.wt[u] << ob) | share);
                   } else {
-                    const uint64_t add = ((uint64_t)t.wt[u] << 32) | (uint64_t)share;
-                    const uint64_t now =
-                        atomicAdd((unsigned long long*)&S.tab[id - lo], (unsigned long long)add) +
-                        add;
-                    sc = now >> 32;
-                    ov = (uint32_t)now;
+                    atomicAdd((unsigned long long*)&S.tab[id - lo],
+                              (unsigned long long)(((uint64_t)t.wt[u] << 32) | (uint64_t)share));
                   }
-                  const uint64_t key = (sc << 32) | (uint64_t)(kSent - id);
-                  if (key > best && (v.all_valid || merge_valid(a, v, id, OV ? (int64_t)ov : 0)))
-                    best = key;
                 }
               }
               asm volatile("" ::"v"(pin[0]), "v"(pin[1]), "v"(pin[2]), "v"(pin[3]));
@@ -301,7 +289,45 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
             }
           }
         }  // segments
-        if (cleared) __syncthreads();  // the window's sweeps done before the next clear
+        if (cleared) {  // block-uniform
+          __syncthreads();  // the window's sweeps done
+          // this thread's entries: their best valid key, then zeroed
+          const uint64_t thr = S.thr;
+          uint64_t lim = best > thr ? best : thr;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const uint4 q = tab4[8 * tid + i];
+            tab4[8 * tid + i] = make_uint4(0u, 0u, 0u, 0u);
+            const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int k = 0; k < (C ? 4 : 2); ++k) {
+              uint64_t sc;
+              uint32_t ov, id;
+              if (C) {
+                sc = w4[k] >> ob;
+                ov = w4[k] & omask;
+                id = lo + (uint32_t)(32 * tid + 4 * i + k);
+              } else {
+                sc = w4[2 * k + 1];
+                ov = w4[2 * k];
+                id = lo + (uint32_t)(16 * tid + 2 * i + k);
+              }
+              const uint64_t key = (sc << 32) | (uint64_t)(kSent - id);
+              if (sc > 0 && id != n && key > lim &&
+                  (v.all_valid || merge_valid(a, v, id, OV ? (int64_t)ov : 0))) {
+                best = key;
+                lim = key;
+              }
+            }
+          }
+          uint64_t m = best;
+#pragma unroll
+          for (int d = kWave / 2; d > 0; d >>= 1) {
+            const uint64_t o = __shfl_xor(m, d, kWave);
+            m = o > m ? o : m;
+          }
+          if (lane == 0 && m > thr) atomicMax((unsigned long long*)&S.thr, (unsigned long long)m);
+        }
       }
     };
     if (compact) windows(std::integral_constant<bool, true>{});
