@@ -290,8 +290,9 @@ int hg_connectivity_static(hg_ctx* ctx, const hg_level* lvl, const int32_t* part
  * one pass over an on-chip table when its distinct-neighbour bound (its
  * expansion, the sum of the sizes of its incident hyperedges, capped by the
  * vertex count) is at most single_pass_load16/16 of the table's slots.
- * Larger neighbourhoods that visit at least one id in dense_ratio of the
- * level's ids (dense_ratio * expansion >= V; 0 disables it) are scored in
+ * Neighbourhoods that visit at least one id in dense_ratio of the level's
+ * ids (dense_ratio * expansion >= V; 0 disables it) and are larger than the
+ * single-pass tables or have an expansion of at least 2^16 are scored in
  * dense windows of 2^14 ids, one packed (score, overlap) word per id, on
  * levels of at most 2^21 vertices.  Other large neighbourhoods are scored in
  * windows of neighbour ids with an on-chip bitmap of seen ids (at most 768
@@ -370,10 +371,10 @@ int hg_batch_sizes(hg_batch* batch, int64_t* sizes);
  * rule described at hg_tuning: 0 single pass in the small table, 1 single
  * pass in the big table, 2 windows with a bitmap of seen ids, 3 passes over a
  * table; 4-7 the same where the distinct-axon overlap of Section 3 can bind;
- * 8 and 9 (without and with the overlap) dense windows, taken by the large
- * neighbourhoods of lists 2, 3, 6, 7 that visit at least one id in
- * dense_ratio (hg_tuning, default 8) of the level, on levels of at most 2^21
- * vertices.  `out` is host
+ * 8 and 9 (without and with the overlap) dense windows, taken by the
+ * neighbourhoods that visit at least one id in dense_ratio (hg_tuning,
+ * default 8) of the level and are either large (lists 2, 3, 6, 7) or have an
+ * expansion of at least 2^16, on levels of at most 2^21 vertices.  `out` is host
  * int64[2 * HG_SCORE_LISTS].
  */
 #define HG_SCORE_LISTS 10

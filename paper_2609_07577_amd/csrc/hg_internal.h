@@ -187,12 +187,15 @@ void level0_state(const Dims* d, const int64_t* eoff, const uint32_t* pins, int6
 // Buckets 0-3 without, 4-7 with the shared-inbound count: single pass in the
 // small table, single pass in the big table, multipass with the incident
 // hyperedges staged in LDS (degree <= kWinDeg), multipass with them read
-// from global memory; 8 without, 9 with it: dense windows (large
-// neighbourhoods that visit at least one id in Tuning::dense_ratio of the
-// level).
+// from global memory; 8 without, 9 with it: dense windows (neighbourhoods
+// that visit at least one id in Tuning::dense_ratio of the level and are
+// either large or visited at least kDenseMinVisits times: coarse levels
+// revisit few super-nodes very often, and one table entry per id takes the
+// visits with no hashing).
 constexpr int kNumBuckets = 10;
 constexpr int kDenseBits = 14;          // ids per dense window: 2^14
 constexpr int kMaxDenseWindows = 128;   // levels of at most 2^21 vertices
+constexpr int64_t kDenseMinVisits = 1 << 16;
 constexpr int kSmallSlots = 4096;
 constexpr int kBigSlots = 16384;
 constexpr int kBigSlotsOv = 8192;

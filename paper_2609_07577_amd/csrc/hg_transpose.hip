@@ -396,7 +396,9 @@ __global__ void expansion_kernel(LevelView L, const int64_t* __restrict__ voff,
 // the graph's vertex count): single pass in the small table (bound <=
 // load16/16 of it), single pass in the big table, or multipass; +4
 // when the distinct-axon bound can bind for n (ax_n + level max > Delta), so
-// the shared inbound count must be accumulated.  Vertices with X_n = 0 have
+// the shared inbound count must be accumulated; 8 or 9 (dense windows) for
+// neighbourhoods that visit at least one id in dense_ratio of the graph and
+// are large or visited at least kDenseMinVisits times.  Vertices with X_n = 0 have
 // no neighbour and are in no list.
 __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
                               const int64_t* __restrict__ voff,
@@ -425,8 +427,9 @@ __global__ void bucket_kernel(LevelView L, const int64_t* __restrict__ xn,
         else if (dist <= (int64_t)(ov ? kBigSlotsOv : kBigSlots) * load16 / 16) bk = 1;
         else bk = (voff[v + 1] - voff[v] <= kWinDeg) ? 2 : 3;
         if (ov) bk += 4;
-        // dense neighbourhoods (visits at least a kDenseRatio-th of the ids)
-        if ((bk & 3) >= 2 && dense_windows > 0 && dense_ratio > 0 &&
+        // dense neighbourhoods (visits at least a dense_ratio-th of the ids):
+        // the large ones, and the small ones visited very often
+        if (((bk & 3) >= 2 || x >= kDenseMinVisits) && dense_windows > 0 && dense_ratio > 0 &&
             x * dense_ratio >= (int64_t)G.nverts)
           bk = ov ? 9 : 8;
       }

@@ -140,7 +140,7 @@ def check_contraction(fine, coarse, vmap):
 
 
 def score_buckets(level, limits, load16=8, small=4096, big=16384, big_ov=8192, win_deg=768,
-                  dense_ratio=8):
+                  dense_ratio=8, dense_min_visits=1 << 16):
     """Work list of every vertex in the score step, by the rule the library
     applies before scoring (a host copy of that rule, used to show which
     scoring kernels an input reaches; results never depend on it).
@@ -151,8 +151,9 @@ def score_buckets(level, limits, load16=8, small=4096, big=16384, big_ov=8192, w
     incident hyperedges), passes over a table; +4 when the distinct-axon
     bound can bind for the vertex (its ax plus the level's largest ax above
     the limit), which makes the step also count shared inbound axons; 8 or 9
-    (without or with that count) for large neighbourhoods that visit at least
-    one id in ``dense_ratio`` of the level (0: never), on levels of at most
+    (without or with that count) for neighbourhoods that visit at least one id
+    in ``dense_ratio`` of the level (0: never) and are large (2, 3, 6, 7) or
+    have an expansion of at least ``dense_min_visits``, on levels of at most
     2^21 vertices."""
     eoff = np.asarray(level.eoff, dtype=np.int64)
     lens = np.diff(eoff)
@@ -169,8 +170,9 @@ def score_buckets(level, limits, load16=8, small=4096, big=16384, big_ov=8192, w
                  np.where(dist <= np.where(ov, big_ov, big) * load16 // 16, 1,
                           np.where(deg <= win_deg, 2, 3)))
     b = b + 4 * ov
-    # dense windows: large neighbourhoods visiting at least one id in 8, on
-    # levels of at most 2^21 vertices
+    # dense windows: large or often visited neighbourhoods visiting at least
+    # one id in dense_ratio, on levels of at most 2^21 vertices
     if dense_ratio > 0 and 0 < V <= (1 << 21):
-        b = np.where(((b & 3) >= 2) & (xn * dense_ratio >= V), 8 + ov, b)
+        big_or_hot = ((b & 3) >= 2) | (xn >= dense_min_visits)
+        b = np.where(big_or_hot & (xn * dense_ratio >= V), 8 + ov, b)
     return np.where(xn > 0, b, -1)

@@ -238,6 +238,22 @@ def test_batch_mix_graph_coarse_levels(ctx, dense_ratio):
         assert census[5] > 0 and census[6] > 0 and census[7] > 0
 
 
+def test_batch_mix_graph_to_the_stop_rule(ctx):
+    """The same graph to the stop rule (581 levels) with the default tuning:
+    on its coarse levels the super-nodes have few distinct neighbours (fewer
+    than the single-pass tables hold) but are visited more than 2^16 times,
+    and are scored in dense windows with and without the shared inbound
+    count; every level against the oracle, element by element, and the GPU
+    stops at the oracle's level."""
+    g = synth.batch_graph(1001, 0, 1000, 8000, 16, 256)
+    census = np.zeros(10, np.int64)
+    with _tuned(ctx, dense_ratio=8):
+        oh = run_hierarchy_parity(ctx, g, synth.LIMITS["batch"], census=census)
+    print(f"  {oh.n_levels} contractions, census {census.tolist()}", flush=True)
+    assert oh.n_levels > 500
+    assert census[8] >= 500 and census[9] >= 5000
+
+
 def test_uniform_tight_axon_limit(ctx):
     # Delta binds early, so the overlap test on candidate merges is exercised
     g = synth.uniform(5, 3000, 4, 40)
