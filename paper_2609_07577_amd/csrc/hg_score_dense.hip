@@ -176,7 +176,23 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
           b1 = sr[wi + 1];
         }
       };
-      for (int32_t wi = w_lo; wi < nw && wi < w_hi; ++wi) {  // block-uniform
+      // with at most THREADS incident hyperedges (one segment) thread t keeps
+      // hyperedge t's window-independent values in registers for all windows
+      // and loads the next window's slice bounds while this one is swept
+      const bool one_seg = deg <= THREADS;  // block-uniform
+      const int32_t w_end = nw < w_hi ? nw : w_hi;
+      uint32_t h_e0 = 0, h_wt = 0, h_mu = 0, nb0 = 0, nb1 = 0;
+      const uint32_t* h_row = a.splits14;
+      if (one_seg && tid < deg) {
+        const uint32_t ent = a.vinc[v.beg + tid];
+        const uint32_t e = ent & kIdMask;
+        h_row = a.splits14 + (int64_t)e * (W + 1);
+        if (w_lo < w_end) bounds(h_row, w_lo, nb0, nb1);
+        h_e0 = (uint32_t)a.L.eoff[e];
+        h_wt = (uint32_t)a.L.w[e];
+        h_mu = (OV && (ent & kDst)) ? (uint32_t)a.L.mult[e] : 0u;
+      }
+      for (int32_t wi = w_lo; wi < w_end; ++wi) {  // block-uniform
         const uint32_t lo = (uint32_t)wi << kBits;
         bool cleared = false;  // block-uniform: the table is cleared before the first sweep
         // segments of THREADS incident hyperedges; thread t holds hyperedge
@@ -184,7 +200,15 @@ __global__ __launch_bounds__(THREADS) void score_dense_kernel(ScoreArgs a, int b
         for (int64_t seg = 0; seg < deg; seg += THREADS) {  // block-uniform
           const int64_t j = seg + tid;
           uint32_t first = 0, len = 0, wt = 0, mu = 0;
-          if (j < deg) {
+          if (one_seg) {
+            if (j < deg) {
+              len = nb1 - nb0;
+              first = h_e0 + nb0;
+              wt = h_wt;
+              mu = h_mu;
+              if (wi + 1 < w_end) bounds(h_row, wi + 1, nb0, nb1);
+            }
+          } else if (j < deg) {
             const uint32_t ent = a.vinc[v.beg + j];
             const uint32_t e = ent & kIdMask;
             uint32_t b0, b1;
