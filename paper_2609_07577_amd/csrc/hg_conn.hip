@@ -1,8 +1,8 @@
 // S8: connectivity (paper, Section 3, Eq. 1):
 //   Conn = sum over hyperedges e of w(e) * (lambda(e) - 1),
 //   lambda(e) = number of distinct part[v] over the pins v of e.
-// Four size classes: a wave with one pin per lane sorts the block ids by
-// shuffles (<= 64 pins); a work-group counts distinct ids in an LDS hash set
+// Four size classes: a wave with one, two or four pins per lane sorts the
+// block ids by shuffles (<= 256 pins); a work-group counts distinct ids in an LDS hash set
 // of 4096 slots (<= 2048 pins, many work-groups per CU to hide the latency
 // of the part lookups) or of 32768 slots (<= 16384 pins); larger hyperedges
 // use a bitmap over the block-id range.
@@ -14,7 +14,7 @@ namespace hg {
 
 namespace {
 
-constexpr int kSmallMax = 64;
+constexpr int kSmallMax = 4 * kWave;
 constexpr int kMediumMax = 2048;
 constexpr int kBlockMax = 16384;
 constexpr int kThreads = 256;
@@ -57,6 +57,34 @@ struct ConnArgs {
   int64_t max_items;
 };
 
+// lambda(e) of one hyperedge of at most KPL * 64 pins by a wave: its block
+// ids sorted in registers, the heads of the runs counted.
+template <int KPL>
+__device__ inline int conn_wave(const ConnArgs& a, int64_t s0, int len) {
+  const int lane = threadIdx.x & (kWave - 1);
+  uint32_t key[KPL];
+#pragma unroll
+  for (int r = 0; r < KPL; ++r) {
+    key[r] = 0xFFFFFFFFu;
+    if (r * kWave + lane < len) key[r] = (uint32_t)a.part[a.L.pins[s0 + r * kWave + lane] & kIdMask];
+  }
+  wave_sort<KPL>(key);
+  int lambda = 0;
+#pragma unroll
+  for (int r = 0; r < KPL; ++r) {
+    uint32_t prev = __shfl_up(key[r], 1, kWave);
+    if (r > 0) {
+      const uint32_t last = __shfl(key[r > 0 ? r - 1 : 0], kWave - 1, kWave);
+      if (lane == 0) prev = last;
+    }
+    const int pos = r * kWave + lane;
+    const bool head = pos < len && (pos == 0 || prev != key[r]);
+    lambda += __popcll(__ballot(head));
+  }
+  return lambda;
+}
+
+// Up to 256 pins: a wave per hyperedge, one, two or four keys per lane.
 __global__ void conn_small_kernel(ConnArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -67,23 +95,10 @@ __global__ void conn_small_kernel(ConnArgs a) {
     const int64_t e = a.list[it];
     const int64_t s0 = a.L.eoff[e];
     const int len = (int)(a.L.eoff[e + 1] - s0);
-    uint32_t key = 0xFFFFFFFFu;
-    if (lane < len) key = (uint32_t)a.part[a.L.pins[s0 + lane] & kIdMask];
-#pragma unroll
-    for (int k = 2; k <= kWave; k <<= 1) {
-#pragma unroll
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        uint32_t other = __shfl_xor(key, j, kWave);
-        bool up = (lane & k) == 0;
-        bool lower = (lane & j) == 0;
-        uint32_t mn = key < other ? key : other;
-        uint32_t mx = key < other ? other : key;
-        key = (lower == up) ? mn : mx;
-      }
-    }
-    uint32_t prev = __shfl_up(key, 1, kWave);
-    bool head = lane < len && (lane == 0 || prev != key);
-    int lambda = __popcll(__ballot(head));
+    int lambda;
+    if (len <= kWave) lambda = conn_wave<1>(a, s0, len);  // wave-uniform
+    else if (len <= 2 * kWave) lambda = conn_wave<2>(a, s0, len);
+    else lambda = conn_wave<4>(a, s0, len);
     acc += (int64_t)a.L.w[e] * (lambda - 1);  // same value in every lane
   }
   if (lane == 0 && acc) atomicAdd((unsigned long long*)a.conn, (unsigned long long)acc);

@@ -6,8 +6,9 @@
 // S6  per fine hyperedge: relabel pins through vmap, sort by coarse id, merge
 //     equal ids (destination flag = OR), drop if fewer than two remain, and
 //     hash the resulting (id, flag) list.  Three size classes: one wave in
-//     registers (<= 64 pins), one work-group in LDS (<= 16384 pins), and a
-//     bitmap over the coarse id range for anything larger.
+//     registers (<= 256 pins, one, two or four keys per lane), one work-group in
+//     LDS (<= 16384 pins), and a bitmap over the coarse id range for
+//     anything larger.
 // S7  group identical lists: a global open-addressing table keyed by the
 //     64-bit hash elects the smallest fine hyperedge of each hash value; every
 //     member is then compared pin by pin with it, and the rare members whose
@@ -27,7 +28,7 @@ namespace hg {
 
 namespace {
 
-constexpr int kSmallMax = 64;
+constexpr int kSmallMax = 4 * kWave;
 constexpr int kMediumMax = 2048;
 constexpr int kBlockMax = 16384;
 constexpr int kBlockThreads = 256;
@@ -117,9 +118,48 @@ __device__ inline void emit_pin(const S6Args& a, int64_t e, int64_t pos, uint32_
   a.tpin[a.L.eoff[e] + pos] = pin;
 }
 
-// Up to 64 pins: one key per lane, bitonic sort by shuffles.
-__global__ void s6_small_kernel(S6Args a) {
+// S6 of one hyperedge of at most KPL * 64 pins by a wave: keys (coarse id,
+// flag) sorted in registers, the last key of each run of one id kept (its
+// flag is the OR of the run's), emitted at its rank.  Returns the number
+// emitted; h gets the sum of their hashes (this lane's part).
+template <int KPL>
+__device__ inline int s6_wave(const S6Args& a, int64_t e, int64_t s0, int len, int32_t m,
+                              uint64_t& h) {
   const int lane = threadIdx.x & (kWave - 1);
+  const uint64_t below = (1ull << lane) - 1;
+  uint32_t key[KPL];
+#pragma unroll
+  for (int r = 0; r < KPL; ++r) {
+    key[r] = kPad;
+    if (r * kWave + lane < len) {
+      const uint32_t p = a.L.pins[s0 + r * kWave + lane];
+      key[r] = ((uint32_t)a.vmap[p & kIdMask] << 1) | (p >> 31);
+    }
+  }
+  wave_sort<KPL>(key);
+  int n_out = 0;
+#pragma unroll
+  for (int r = 0; r < KPL; ++r) {
+    uint32_t next = __shfl_down(key[r], 1, kWave);
+    if (r + 1 < KPL) {
+      const uint32_t first = __shfl(key[r + 1 < KPL ? r + 1 : r], 0, kWave);
+      if (lane == kWave - 1) next = first;
+    }
+    const int pos = r * kWave + lane;
+    const bool tail = pos < len && (pos == len - 1 || (next >> 1) != (key[r] >> 1));
+    const uint64_t tb = __ballot(tail);
+    if (tail) {
+      const uint32_t pin = key_to_pin(key[r]);
+      emit_pin(a, e, n_out + __popcll(tb & below), pin, m);
+      h += mix64(pin);
+    }
+    n_out += __popcll(tb);
+  }
+  return n_out;
+}
+
+// Up to 256 pins: a wave per hyperedge, one, two or four keys per lane.
+__global__ void s6_small_kernel(S6Args a) {
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
   const int64_t cnt = a.count[0] < a.max_items ? a.count[0] : a.max_items;
@@ -127,36 +167,12 @@ __global__ void s6_small_kernel(S6Args a) {
     const int64_t e = a.list[it];
     const int64_t s0 = a.L.eoff[e];
     const int len = (int)(a.L.eoff[e + 1] - s0);
-    uint32_t key = kPad;
-    if (lane < len) {
-      uint32_t p = a.L.pins[s0 + lane];
-      key = ((uint32_t)a.vmap[p & kIdMask] << 1) | (p >> 31);
-    }
-#pragma unroll
-    for (int k = 2; k <= kWave; k <<= 1) {
-#pragma unroll
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        uint32_t other = __shfl_xor(key, j, kWave);
-        bool up = (lane & k) == 0;
-        bool lower = (lane & j) == 0;
-        uint32_t mn = key < other ? key : other;
-        uint32_t mx = key < other ? other : key;
-        key = (lower == up) ? mn : mx;
-      }
-    }
-    uint32_t next = __shfl_down(key, 1, kWave);
-    bool valid = lane < len;
-    bool tail = valid && (lane == len - 1 || (next >> 1) != (key >> 1));
-    uint64_t tails = __ballot(tail);
-    int rank = __popcll(tails & ((1ull << lane) - 1));
-    int n_out = __popcll(tails);
-    int32_t m = a.L.mult[e];
+    const int32_t m = a.L.mult[e];
     uint64_t h = 0;
-    if (tail) {
-      uint32_t pin = key_to_pin(key);
-      emit_pin(a, e, rank, pin, m);
-      h = mix64(pin);
-    }
+    int n_out;
+    if (len <= kWave) n_out = s6_wave<1>(a, e, s0, len, m, h);  // wave-uniform
+    else if (len <= 2 * kWave) n_out = s6_wave<2>(a, e, s0, len, m, h);
+    else n_out = s6_wave<4>(a, e, s0, len, m, h);
     h = wave_sum(h);
     // every lane stores the same values (no lane-only code in this loop)
     a.tlen[e] = n_out;

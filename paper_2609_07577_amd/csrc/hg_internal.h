@@ -102,6 +102,43 @@ __device__ inline int32_t wave_bucket_slot(int b, int32_t* count) {
   return pos;
 }
 
+// Ascending bitonic sort of the KPL * kWave keys of a wave: key r of lane l
+// is at position r * kWave + l (pad with the largest value).  Steps whose
+// partner distance is below kWave exchange by shuffles, the others between
+// a lane's own registers.  All 64 lanes must be active.
+template <int KPL>
+__device__ inline void wave_sort(uint32_t (&key)[KPL]) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int k = 2; k <= KPL * kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= kWave) {
+        const int rj = j / kWave;
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+          if (r & rj) continue;
+          const bool up = ((r * kWave + lane) & k) == 0;
+          const uint32_t x = key[r], y = key[r | rj];
+          const uint32_t mn = x < y ? x : y, mx = x < y ? y : x;
+          key[r] = up ? mn : mx;
+          key[r | rj] = up ? mx : mn;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+          const uint32_t other = __shfl_xor(key[r], j, kWave);
+          const bool up = ((r * kWave + lane) & k) == 0;
+          const bool lower = (lane & j) == 0;
+          const uint32_t mn = key[r] < other ? key[r] : other;
+          const uint32_t mx = key[r] < other ? other : key[r];
+          key[r] = (lower == up) ? mn : mx;
+        }
+      }
+    }
+  }
+}
+
 // ---- primitives (hg_prims.hip) --------------------------------------------
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t s);
