@@ -180,8 +180,9 @@ __global__ void s6_small_kernel(S6Args a) {
   }
 }
 
+template <int THREADS = kBlockThreads>
 __device__ inline int64_t block_exclusive_scan_i32(int32_t v, int32_t* total, int32_t* wsum) {
-  constexpr int NW = kBlockThreads / kWave;
+  constexpr int NW = THREADS / kWave;
   int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   int32_t inc = v;
 #pragma unroll
@@ -202,8 +203,9 @@ __device__ inline int64_t block_exclusive_scan_i32(int32_t v, int32_t* total, in
   return base + inc - v;
 }
 
+template <int THREADS = kBlockThreads>
 __device__ inline uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
-  constexpr int NW = kBlockThreads / kWave;
+  constexpr int NW = THREADS / kWave;
   v = wave_sum(v);
   int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   if (lane == 0) red[wid] = v;
@@ -217,12 +219,14 @@ __device__ inline uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
 
 // Hyperedges of class CLS (at most MAXN pins): one work-group, bitonic sort
 // in LDS (the medium class keeps its keys small enough for many work-groups
-// per CU, which hide the latency of the vertex-map lookups).
-template <int MAXN, int CLS>
-__global__ __launch_bounds__(kBlockThreads) void s6_block_kernel(S6Args a) {
+// per CU, which hide the latency of the vertex-map lookups; the large class
+// sorts with 1024 threads, eight compare-exchanges per thread and step at
+// 16384 keys).
+template <int MAXN, int CLS, int THREADS>
+__global__ __launch_bounds__(THREADS) void s6_block_kernel(S6Args a) {
   __shared__ uint32_t keys[MAXN];
-  __shared__ int32_t wsum[kBlockThreads / kWave];
-  __shared__ uint64_t red[kBlockThreads / kWave];
+  __shared__ int32_t wsum[THREADS / kWave];
+  __shared__ uint64_t red[THREADS / kWave];
   __shared__ int32_t s_item;
   const int tid = threadIdx.x;
   int32_t cnt = a.count[CLS];
@@ -241,7 +245,7 @@ __global__ __launch_bounds__(kBlockThreads) void s6_block_kernel(S6Args a) {
     const int len = (int)(a.L.eoff[e + 1] - s0);
     int N = 128;
     while (N < len && N < MAXN) N <<= 1;
-    for (int i = tid; i < N; i += kBlockThreads) {
+    for (int i = tid; i < N; i += THREADS) {
       uint32_t key = kPad;
       if (i < len) {
         uint32_t p = a.L.pins[s0 + i];
@@ -252,7 +256,7 @@ __global__ __launch_bounds__(kBlockThreads) void s6_block_kernel(S6Args a) {
     __syncthreads();
     for (int k = 2; k <= N; k <<= 1) {
       for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int t = tid; t < N / 2; t += kBlockThreads) {
+        for (int t = tid; t < N / 2; t += THREADS) {
           int i = 2 * t - (t & (j - 1));
           int l = i + j;
           uint32_t x = keys[i], y = keys[l];
@@ -266,14 +270,14 @@ __global__ __launch_bounds__(kBlockThreads) void s6_block_kernel(S6Args a) {
       }
     }
     // compaction of run tails, contiguous chunk per thread
-    const int per = (len + kBlockThreads - 1) / kBlockThreads;
+    const int per = (len + THREADS - 1) / THREADS;
     const int lo = tid * per;
     const int hi = lo + per < len ? lo + per : len;
     int32_t c = 0;
     for (int i = lo; i < hi; ++i)
       if (i == len - 1 || (keys[i + 1] >> 1) != (keys[i] >> 1)) ++c;
     int32_t total;
-    int64_t pos = block_exclusive_scan_i32(c, &total, wsum);
+    int64_t pos = block_exclusive_scan_i32<THREADS>(c, &total, wsum);
     const int32_t m = a.L.mult[e];
     uint64_t h = 0;
     for (int i = lo; i < hi; ++i) {
@@ -283,7 +287,7 @@ __global__ __launch_bounds__(kBlockThreads) void s6_block_kernel(S6Args a) {
         h += mix64(pin);
       }
     }
-    h = block_sum_u64(h, red);
+    h = block_sum_u64<THREADS>(h, red);
     if (tid == 0) {
       a.tlen[e] = total;
       a.fp[e] = ((h + mix64(0x5151ull + (uint64_t)total)) & a.fp_mask) | 1ull;
@@ -559,9 +563,9 @@ int contract_level(const LevelView& L, int64_t maxV, int64_t maxE, int64_t maxP,
   a6.count = cs.ecount;
   s6_small_kernel<<<gridEw, 256, 0, s>>>(a6);
   a6.list = cs.ebucket + maxE;
-  s6_block_kernel<kMediumMax, 1><<<device_cu_count() * 8, kBlockThreads, 0, s>>>(a6);
+  s6_block_kernel<kMediumMax, 1, kBlockThreads><<<device_cu_count() * 8, kBlockThreads, 0, s>>>(a6);
   a6.list = cs.ebucket + 2 * maxE;
-  s6_block_kernel<kBlockMax, 2><<<device_cu_count() * 2, kBlockThreads, 0, s>>>(a6);
+  s6_block_kernel<kBlockMax, 2, 1024><<<device_cu_count() * 2, 1024, 0, s>>>(a6);
   a6.list = cs.ebucket + 3 * maxE;
   s6_huge_kernel<<<kHugeWG, kBlockThreads, 0, s>>>(a6);
   // the axons of the coarse vertices: + mult of every coarse hyperedge copy
