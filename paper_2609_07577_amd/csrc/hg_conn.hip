@@ -2,10 +2,10 @@
 //   Conn = sum over hyperedges e of w(e) * (lambda(e) - 1),
 //   lambda(e) = number of distinct part[v] over the pins v of e.
 // Four size classes: a wave with one, two or four pins per lane sorts the
-// block ids by shuffles (<= 256 pins); a work-group counts distinct ids in an LDS hash set
-// of 4096 slots (<= 2048 pins, many work-groups per CU to hide the latency
-// of the part lookups) or of 32768 slots (<= 16384 pins); larger hyperedges
-// use a bitmap over the block-id range.
+// block ids by shuffles (<= 256 pins); a work-group counts distinct ids in
+// an LDS hash set of 4096 slots (<= 2048 pins, many work-groups per CU to
+// hide the latency of the part lookups) or of 32768 slots (<= 16384 pins,
+// 1024 threads); larger hyperedges use a bitmap over the block-id range.
 // Sums are int64 and combined with integer atomics, so the result does not
 // depend on scheduling.
 #include "hg_internal.h"
@@ -105,8 +105,8 @@ __global__ void conn_small_kernel(ConnArgs a) {
 }
 
 // Hyperedges of class CLS (at most SLOTS / 2 pins): one work-group each.
-template <int SLOTS, int CLS>
-__global__ __launch_bounds__(kThreads) void conn_block_kernel(ConnArgs a) {
+template <int SLOTS, int CLS, int THREADS>
+__global__ __launch_bounds__(THREADS) void conn_block_kernel(ConnArgs a) {
   __shared__ uint32_t set[SLOTS];
   __shared__ int32_t s_item;
   __shared__ int32_t s_new;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void conn_block_kernel(ConnArgs a) {
     if (tid == 0) atomicOr(a.err, kErrWorkCount);
     cnt = (int32_t)a.max_items;
   }
-  for (int i = tid; i < SLOTS; i += kThreads) set[i] = kEmptySlot;
+  for (int i = tid; i < SLOTS; i += THREADS) set[i] = kEmptySlot;
   int64_t acc = 0;
   while (true) {
     __syncthreads();
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kThreads) void conn_block_kernel(ConnArgs a) {
     while (cap < 2 * (uint64_t)(s1 - s0) && cap < (uint32_t)SLOTS) cap <<= 1;
     const uint32_t mask = cap - 1;
     int mine = 0;
-    for (int64_t k = s0 + tid; k < s1; k += kThreads) {
+    for (int64_t k = s0 + tid; k < s1; k += THREADS) {
       uint32_t b = (uint32_t)a.part[a.L.pins[k] & kIdMask];
       uint32_t h = (b * 0x9E3779B1u) & mask;
       uint32_t probe = 0;
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kThreads) void conn_block_kernel(ConnArgs a) {
     if (mine) atomicAdd(&s_new, mine);
     __syncthreads();
     if (tid == 0) acc += (int64_t)a.L.w[e] * (s_new - 1);
-    for (uint32_t i = tid; i < cap; i += kThreads) set[i] = kEmptySlot;
+    for (uint32_t i = tid; i < cap; i += THREADS) set[i] = kEmptySlot;
   }
   if (tid == 0 && acc) atomicAdd((unsigned long long*)a.conn, (unsigned long long)acc);
 }
@@ -209,9 +209,9 @@ void connectivity(const LevelView& L, int64_t maxE, int64_t part_range, const in
              (part_range + 31) / 32, cs.err, maxE};
   conn_small_kernel<<<grid_for(maxE, 4, 16384), 256, 0, s>>>(a);
   a.list = cs.ebucket + maxE;
-  conn_block_kernel<2 * kMediumMax, 1><<<device_cu_count() * 8, kThreads, 0, s>>>(a);
+  conn_block_kernel<2 * kMediumMax, 1, kThreads><<<device_cu_count() * 8, kThreads, 0, s>>>(a);
   a.list = cs.ebucket + 2 * maxE;
-  conn_block_kernel<2 * kBlockMax, 2><<<device_cu_count(), kThreads, 0, s>>>(a);
+  conn_block_kernel<2 * kBlockMax, 2, 1024><<<device_cu_count(), 1024, 0, s>>>(a);
   a.list = cs.ebucket + 3 * maxE;
   conn_huge_kernel<<<kHugeWG, kThreads, 0, s>>>(a);
 }
