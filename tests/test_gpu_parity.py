@@ -297,6 +297,37 @@ def test_huge_hyperedges_contract_and_connectivity(ctx):
         assert_level_equal(C, oracle.contract(OL, vmap, len(uniq)), f"huge k={k}")
 
 
+def test_contract_and_connectivity_at_class_sizes(ctx):
+    """Hyperedges of 63-66, 127-130, 255-258, 2047-2050 and 16383-16386
+    pins (either side of the wave sorts with one, two and four keys per lane
+    and of the work-group classes of S6 and S8) under general partitions
+    (many pins of one hyperedge in one part, flags merged): the contracted
+    level and Eq. 1 against the oracle."""
+    import torch as T
+    rng = np.random.default_rng(21)
+    n = 40000
+    sizes = [63, 64, 65, 66, 127, 128, 129, 130, 255, 256, 257, 258,
+             2047, 2048, 2049, 2050, 16383, 16384, 16385, 16386]
+    axons = []
+    for s_, k in enumerate(sizes * 3):
+        tg = sorted(set(rng.choice(np.arange(n), k, replace=False).tolist()) - {s_})
+        axons.append((s_, tg, int(rng.integers(1, 9))))
+    g = synth.from_axons(n, axons)
+    L = ctx.upload(g)
+    OL = oracle.level0(g)
+    lens = np.diff(np.asarray(OL.eoff))
+    for k in sizes:
+        assert np.any(np.abs(lens - (k + 1)) <= 1), k
+    for k in (2, 97, 3000, 39999):
+        part = rng.integers(0, k, n).astype(np.int32)
+        uniq = np.unique(part)
+        vmap = np.searchsorted(uniq, part).astype(np.int32)
+        tv = T.from_numpy(vmap).cuda()
+        assert int(ctx.connectivity(L, tv).item()) == oracle.connectivity(OL.eoff, OL.pins, OL.w, vmap)
+        C = ctx.contract(L, tv, T.tensor([len(uniq)], dtype=T.int32, device="cuda"))
+        assert_level_equal(C, oracle.contract(OL, vmap, len(uniq)), f"class sizes k={k}")
+
+
 def test_contract_general_partitions(ctx):
     import torch as T
     rng = np.random.default_rng(11)
