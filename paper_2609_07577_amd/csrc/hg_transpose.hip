@@ -344,12 +344,16 @@ __global__ void reset_maxima_kernel(GraphConst* gc, int32_t n_graphs, int32_t* b
   }
 }
 
+// MULTI (a union of graphs): the per-graph maxima and vertex counts are kept
+// per wave and written when the graph changes; a single graph's come from
+// graph_maxima_kernel instead (per-wave atomics from every wave of the
+// expansion would all hit the same four words).
+template <bool MULTI>
 __global__ void expansion_kernel(LevelView L, const int64_t* __restrict__ voff,
                                  const uint32_t* __restrict__ vinc, int64_t* __restrict__ xn,
                                  GraphConst* __restrict__ gc, Buckets b, int64_t maxV) {
   // A wave per vertex: lanes stride over its incidence list (coarse
-  // super-nodes have tens of thousands of incident hyperedges).  The
-  // per-graph maxima are kept per wave and written when the graph changes.
+  // super-nodes have tens of thousands of incident hyperedges).
   const int64_t V = L.dims->V;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
@@ -367,7 +371,8 @@ __global__ void expansion_kernel(LevelView L, const int64_t* __restrict__ voff,
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
     if (lane == 0) xn[v] = x;
-    const int g = L.gid ? L.gid[v] : 0;
+    if (!MULTI) continue;
+    const int g = L.gid[v];
     if (g != gcur) {  // wave-uniform
       if (gcur >= 0 && lane == 0) {
         atomicMax(&gc[gcur].max_size, msz);
@@ -384,11 +389,47 @@ __global__ void expansion_kernel(LevelView L, const int64_t* __restrict__ voff,
     msy = sy > msy ? sy : msy;
     max_ = ax > max_ ? ax : max_;
   }
-  if (gcur >= 0 && lane == 0) {
+  if (MULTI && gcur >= 0 && lane == 0) {
     atomicMax(&gc[gcur].max_size, msz);
     atomicMax(&gc[gcur].max_syn, msy);
     atomicMax(&gc[gcur].max_ax, max_);
     atomicAdd(&gc[gcur].nverts, cnt);
+  }
+}
+
+// A single graph's level maxima of size, syn and ax and its vertex count: a
+// grid-stride reduction with one atomic per work-group and field.
+__global__ __launch_bounds__(256) void graph_maxima_kernel(LevelView L,
+                                                           GraphConst* __restrict__ gc) {
+  __shared__ int32_t red[3][256 / kWave];
+  const int64_t V = L.dims->V;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  int32_t m[3] = {0, 0, 0};
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t sz = L.size[v], sy = L.syn[v], ax = L.ax[v];
+    m[0] = sz > m[0] ? sz : m[0];
+    m[1] = sy > m[1] ? sy : m[1];
+    m[2] = ax > m[2] ? ax : m[2];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+      const int32_t o = __shfl_xor(m[c], d, kWave);
+      m[c] = o > m[c] ? o : m[c];
+    }
+    if (lane == 0) red[c][wid] = m[c];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      int32_t r = 0;
+      for (int w = 0; w < 256 / kWave; ++w) r = red[c][w] > r ? red[c][w] : r;
+      if (r > 0) atomicMax(c == 0 ? &gc[0].max_size : (c == 1 ? &gc[0].max_syn : &gc[0].max_ax), r);
+    }
+    if (blockIdx.x == 0) gc[0].nverts = (int32_t)V;
   }
 }
 
@@ -504,7 +545,12 @@ void expansion_and_buckets(const LevelView& L, const int64_t* voff, const uint32
                            int64_t maxV, int64_t* xn, GraphConst* gc, int32_t n_graphs,
                            Buckets b, Tuning t, hipStream_t s, int32_t dense_windows) {
   reset_maxima_kernel<<<1, 256, 0, s>>>(gc, n_graphs, b.count, b.visits);
-  expansion_kernel<<<grid_for(maxV, 4, 16384), 256, 0, s>>>(L, voff, vinc, xn, gc, b, maxV);
+  if (L.gid) {
+    expansion_kernel<true><<<grid_for(maxV, 4, 16384), 256, 0, s>>>(L, voff, vinc, xn, gc, b, maxV);
+  } else {
+    expansion_kernel<false><<<grid_for(maxV, 4, 16384), 256, 0, s>>>(L, voff, vinc, xn, gc, b, maxV);
+    graph_maxima_kernel<<<grid_for(maxV, 256 * 8, 1024), 256, 0, s>>>(L, gc);
+  }
   bucket_kernel<<<grid_for(maxV, 256, 16384), 256, 0, s>>>(L, xn, voff, gc, b, maxV,
                                                           t.load16, dense_windows,
                                                           t.dense_ratio);
